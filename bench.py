@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path: one FMM matrix-vector product (single + double
+layer Laplace potential) on the clustered 4M-point workload.
+
+A step is one full fmm_apply (P2M, M2M, P2L, M2L, L2L, check-to-equivalent
+maps, leaf evaluation) with the tree, lists and operators already built and
+all inputs resident in HBM. The headline value is the split-BF16 M2L form;
+the plain float32 form is measured beside it on the same tree. Errors are
+relative L2 against the float64 direct sum at sampled targets, which is also
+what the CPU baseline times.
+
+Prints one JSON line (rank 0, one GPU).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FMM matvec Mpoints/s at 1e-6 rel err: split-BF16 MFMA M2L vs plain FP32"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32_mfma": 157.3, "fp32_valu": 157.3, "fp64": 78.6}
+FLOPS_PER_PAIR = {"sl": 11, "dl": 13, "sl+dl": 16, "sl+field": 20}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_form(F, torch, x, nrm, q, mu, precision, order, leaf, steps, warmup):
+    opts = F.fmm_default_options(order=order, leaf_size=leaf, precision=precision,
+                                 src_kernels=F.FMM_SRC_SINGLE | F.FMM_SRC_DOUBLE, outputs=F.FMM_OUT_POT,
+                                 root=(0.0, 0.0, 0.0, 1.0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = F.fmm_setup(x, nrm, options=opts)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = F.fmm_plan_info(plan)
+    pot = torch.empty(x.shape[0], device=x.device)
+    for _ in range(warmup):
+        F.fmm_apply(plan, q=q, mu=mu, pot=pot)
+    torch.cuda.synchronize()
+    F.fmm_set_timing(plan, True)
+    stage_sum = {}
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        F.fmm_apply(plan, q=q, mu=mu, pot=pot)
+        for k, v in F.fmm_stage_times(plan).items():
+            stage_sum[k] = stage_sum.get(k, 0.0) + v
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    F.fmm_destroy(plan)
+    stages = {k: v / steps for k, v in stage_sum.items()}
+    return {"ms": ms, "setup_s": setup_s, "info": info, "stages": stages, "pot": pot}
+
+
+def roofline(res, precision):
+    info, st = res["info"], res["stages"]
+    ns = info["n_surface"]
+    m2l_flops = 2.0 * ns * ns * info["m2l_pairs"]
+    eval_flops = FLOPS_PER_PAIR["sl+dl"] * info["p2p_pairs"] + FLOPS_PER_PAIR["sl"] * info["surf_evals"]
+    p2m_flops = FLOPS_PER_PAIR["sl+dl"] * info["p2m_evals"]
+    cands = {
+        "M2L": (m2l_flops, st["M2L"], "mfma", PEAK_TFLOPS["bf16" if precision == 1 else "fp32_mfma"]),
+        "EVAL": (eval_flops, st["EVAL"], "alu", PEAK_TFLOPS["fp32_valu"]),
+        "P2M": (p2m_flops, st["P2M"], "alu", PEAK_TFLOPS["fp32_valu"]),
+    }
+    name = max(cands, key=lambda k: cands[k][1])
+    flops, ms, bound, peak = cands[name]
+    achieved = flops / (ms * 1e-3) / 1e12
+    out = {"kernel": name, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+           "frac": round(achieved / peak, 5), "traffic": None, "algorithmic_flops": flops, "avg_ms": round(ms, 4)}
+    others = {}
+    for k, (f, t, b, p) in cands.items():
+        a = f / (t * 1e-3) / 1e12 if t > 0 else 0.0
+        others[k] = {"bound": b, "achieved_tflops": round(a, 3), "peak": p, "frac": round(a / p, 5),
+                     "avg_ms": round(t, 4)}
+    return out, others
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=4_000_000)
+    ap.add_argument("--order", type=int, default=8)
+    ap.add_argument("--leaf", type=int, default=128)
+    ap.add_argument("--sample", type=int, default=4000, help="targets checked against the float64 direct sum")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the plain float32 form")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle (error and baseline)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note only).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1605_01715_amd as F
+    import workloads as W
+
+    if not os.path.exists(F.library_path()):
+        raise SystemExit("the HIP library is not built; run: python __graft_entry__.py")
+    dev = torch.device("cuda:0")
+    log(f"bench: generating clustered workload n={args.n}")
+    d = W.clustered(args.n)
+    x = torch.from_numpy(d["xyz"]).to(dev)
+    nrm = torch.from_numpy(d["normals"]).to(dev)
+    q = torch.from_numpy(d["q"]).to(dev)
+    mu = torch.from_numpy(d["mu"]).to(dev)
+
+    rng = np.random.default_rng(1)
+    sample = np.sort(rng.choice(args.n, size=min(args.sample, args.n), replace=False))
+    ref = None
+    cpu = None
+    if not args.no_cpu:
+        from oracle import direct
+
+        log(f"bench: CPU oracle direct sum at {len(sample)} targets x {args.n} sources")
+        direct._load()
+        dip = d["mu"].astype(np.float64)[:, None] * d["normals"].astype(np.float64)
+        t0 = time.perf_counter()
+        ref, _ = direct.direct_sum(d["xyz"][sample], d["xyz"], d["q"], dip)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": round(len(sample) / t_cpu / 1e6, 6), "unit": "Mpoints/s", "cores": direct.num_threads(),
+               "kind": "oracle",
+               "sample": f"float64 direct O(N^2) sum at {len(sample)} sampled targets against all {args.n} "
+                         f"sources ({t_cpu:.1f} s), extrapolated to a full matvec"}
+
+    results = {}
+    forms = [("split_bf16", F.FMM_PREC_SPLIT_BF16)] + ([] if args.no_fp32 else [("fp32", F.FMM_PREC_FP32)])
+    for name, prec in forms:
+        log(f"bench: form {name}: setup + {args.warmup} warmup + {args.steps} timed steps")
+        r = run_form(F, torch, x, nrm, q, mu, prec, args.order, args.leaf, args.steps, args.warmup)
+        if ref is not None:
+            got = r["pot"].cpu().numpy()[sample].astype(np.float64)
+            r["err"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        r["roofline"], r["kernels"] = roofline(r, prec)
+        results[name] = r
+        log(f"bench: form {name}: {r['ms']:.3f} ms/step, setup {r['setup_s']:.2f} s, err {r.get('err')}, "
+            f"stages {json.dumps({k: round(v, 3) for k, v in r['stages'].items()})}")
+
+    main_r = results["split_bf16"]
+    info = main_r["info"]
+    value = info["n_points"] / (main_r["ms"] * 1e-3) / 1e6
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_r["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16x6",
+        "data": "synthetic",
+        "config": {"workload": f"clustered cloud, {args.n} points (70% in 64 Gaussian blobs sigma 0.02, 30% "
+                               f"uniform in the unit cube), single + double layer potential, order {args.order}, "
+                               f"leaf size {args.leaf}, adaptive octree, split-BF16 M2L",
+                   "n_points": info["n_points"], "order": args.order, "leaf_size": args.leaf,
+                   "boxes": info["n_boxes"], "levels": info["n_levels"]},
+        "rel_l2_error": main_r.get("err"),
+        "setup_s": round(main_r["setup_s"], 3),
+        "stages_ms": {k: round(v, 4) for k, v in main_r["stages"].items()},
+        "roofline": main_r["roofline"],
+        "kernels": main_r["kernels"],
+        "cpu_baseline": cpu,
+    }
+    if "fp32" in results:
+        f = results["fp32"]
+        line["fp32_form"] = {"value": round(info["n_points"] / (f["ms"] * 1e-3) / 1e6, 3),
+                             "ms_per_step": round(f["ms"], 4), "rel_l2_error": f.get("err"),
+                             "stages_ms": {k: round(v, 4) for k, v in f["stages"].items()},
+                             "roofline": f["roofline"]}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

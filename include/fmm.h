@@ -1,0 +1,224 @@
+/*
+ * fmm.h — C ABI of the MI355X kernel-independent FMM boundary-integral library.
+ *
+ * The library evaluates the quadrature sum of the general boundary-integral
+ * problem (arXiv:1605.01715, Sec. II.A, Eq. sum_fmm)
+ *
+ *     f(r_i) = sum_j K(r_i, r_j) sigma_j
+ *
+ * in O(N) with a kernel-independent fast multipole method, for the Laplace
+ * kernels of the paper's two model problems:
+ *
+ *   single layer  q_j / (4 pi |x_i - y_j|)
+ *   double layer  mu_j (x_i - y_j) . n_j / (4 pi |x_i - y_j|^3)
+ *                 (Sec. II.B Eq. fk_integral; the normal derivative is applied
+ *                  at the particle-to-multipole step, Sec. III.A.1 Eq. p2m)
+ *   field         -grad of the single layer, q_j (x_i - y_j) / (4 pi |x_i - y_j|^3)
+ *                 (Sec. III.A.2 Eq. kernel_pol)
+ *
+ * Targets and sources may be distinct point sets (the target-source model of
+ * Sec. III.A.1). A pair closer than the tolerance radius `cutoff` contributes
+ * nothing (Sec. III.A.1, singularity exclusion). Quadrature weights are folded
+ * into the densities by the caller (sigma_j = phi_1(r_j) w(r_j), Sec. III.A.1).
+ *
+ * GMRES solves the matrix-free systems of Sec. III (A x = b with only the
+ * action of A defined), using one FMM evaluation per iteration.
+ *
+ * Conventions for every entry point:
+ *   - Every pointer argument marked "device" is HIP device memory on the
+ *     current device; every pointer marked "host" is ordinary host memory.
+ *   - Device arrays are read or written in stream order on `hip_stream`
+ *     (a hipStream_t; NULL is the default stream). The caller owns them and
+ *     may free or reuse them once the stream has passed the call.
+ *   - All functions return an fmm_status and never throw or abort across the
+ *     ABI. On failure, fmm_last_error() returns a message describing it
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Point arrays are float32, array-of-structures [n][3] (x, y, z).
+ */
+#ifndef FMM_MI355X_H
+#define FMM_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_plan_s *fmm_plan; /* opaque; owned by the library */
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_ERR_ARG = 1,           /* invalid argument, detected before any device work */
+    FMM_ERR_NOMEM = 2,         /* a device or host allocation failed */
+    FMM_ERR_DEVICE = 3,        /* a HIP runtime call failed */
+    FMM_ERR_NOT_CONVERGED = 4, /* gmres_solve reached max_iter; outputs hold the best iterate */
+    FMM_ERR_STATE = 5          /* the plan was destroyed or is not usable */
+} fmm_status;
+
+/* Source kernels (bitmask). */
+enum { FMM_SRC_SINGLE = 1, FMM_SRC_DOUBLE = 2 };
+/* Outputs (bitmask). FIELD is defined for the single layer only. */
+enum { FMM_OUT_POT = 1, FMM_OUT_FIELD = 2 };
+/* Arithmetic of the box-to-box (M2L) translations. Every other step is float32
+ * (float64 for the check-to-equivalent maps). SPLIT_BF16 splits both operands
+ * into three bfloat16 parts and sums six partial products with float32
+ * accumulation on the matrix cores. */
+enum { FMM_PREC_FP32 = 0, FMM_PREC_SPLIT_BF16 = 1 };
+
+typedef struct {
+    int order;          /* p: points per edge of the equivalent/check surfaces, 2..10 */
+    int leaf_size;      /* s: adaptive tree splits boxes holding more than s points (targets + sources) */
+    int uniform_depth;  /* > 0: uniform tree, every box above this level is split (0 = adaptive) */
+    int max_depth;      /* deepest level, <= 21 */
+    int precision;      /* FMM_PREC_* */
+    int src_kernels;    /* FMM_SRC_* bitmask: which densities fmm_apply takes */
+    int outputs;        /* FMM_OUT_* bitmask */
+    int nrhs;           /* number of density vectors per apply, 1..4 */
+    float cutoff;       /* tolerance radius (Sec. III.A.1), e.g. 1e-5; r < cutoff excluded, r == 0 always */
+    double root[4];     /* root cube x0, y0, z0, width; width <= 0: derived from the points */
+    double pinv_eps;    /* relative SVD truncation of the check-to-equivalent maps; <= 0: default */
+} fmm_options;
+
+/* Fill `opt` with defaults: order 6, leaf_size 64, adaptive, max_depth 21, FP32,
+ * single layer, potential, nrhs 1, cutoff 1e-5, root derived, default pinv_eps. */
+void fmm_default_options(fmm_options *opt);
+
+/*
+ * Build a plan: octree over targets and sources (Morton order, Sec. III.B),
+ * interaction lists, translation operators and work lists.
+ *   src_xyz  device [n_src][3]   source points (required when n_src > 0)
+ *   src_nrm  device [n_src][3]   source normals; required iff FMM_SRC_DOUBLE
+ *   trg_xyz  device [n_trg][3]   target points, or NULL: targets are the sources
+ *   trg_nrm  device [n_trg][3]   target normals (used by FMM_OP_DIELECTRIC), or NULL
+ *   opt      host               options (copied)
+ *   out      host               receives the plan
+ * Errors: FMM_ERR_ARG for NULL required pointers, n < 0, order outside 2..10,
+ * leaf_size < 1, max_depth outside 1..21, nrhs outside 1..4, a field output
+ * with the double layer, and non-finite coordinates or normals (detected by a
+ * device reduction before the tree is built; no plan is created).
+ * n_src == 0 is allowed: every apply then returns zeros.
+ */
+int fmm_setup(const float *src_xyz, const float *src_nrm, int64_t n_src,
+              const float *trg_xyz, const float *trg_nrm, int64_t n_trg,
+              const fmm_options *opt, void *hip_stream, fmm_plan *out);
+
+/*
+ * One FMM evaluation (Sec. II.A Eq. sum_fmm with the kernels above).
+ *   q      device [nrhs][n_src]      single-layer densities (weights folded in), or NULL
+ *   mu     device [nrhs][n_src]      double-layer strengths, or NULL
+ *   pot    device [nrhs][n_trg]      potentials, or NULL (overwritten)
+ *   field  device [nrhs][n_trg][3]   fields, or NULL (overwritten)
+ * At least one of q/mu that the plan's src_kernels names must be given, and
+ * every output requested here must be in the plan's outputs.
+ * A plan holds scratch: two applies of one plan must not overlap in time.
+ */
+int fmm_apply(fmm_plan plan, const float *q, const float *mu, float *pot, float *field,
+              void *hip_stream);
+
+/* Matrix-free operators for gmres_solve (targets = sources; n = n_src):
+ *   FMM_OP_FK          y = a .* x + D[w .* x]            (Eq. fk_integral_discrete,
+ *                                                          a = Omega/(4 pi) - 1, w = weights)
+ *   FMM_OP_DIELECTRIC  y = a .* x + c .* (n_t . E[w .* x]) (Eqs. Ax, Eb, pol_discret,
+ *                                                          a = ebar + self term, c = deps, w = areas)
+ * D is the double-layer potential and E the single-layer field of the plan;
+ * a, c, w are device float32 [n]. */
+enum { FMM_OP_FK = 1, FMM_OP_DIELECTRIC = 2 };
+typedef struct {
+    int kind;
+    const float *a;
+    const float *c;
+    const float *w;
+} fmm_operator;
+
+/*
+ * Restarted GMRES(restart) on the operator above (Sec. III, matrix-free; the
+ * paper's tolerance is 1e-5, Sec. IV.B). Orthogonalisation and residual norms
+ * are float64 on the device; one fmm_apply per iteration.
+ *   b        device double [n]    right-hand side
+ *   x        device double [n]    in: initial guess, out: solution (best iterate)
+ *   iters    host int             iterations done
+ *   rel_res  host double          final true relative residual ||b - A x|| / ||b||
+ * Returns FMM_ERR_NOT_CONVERGED (with iters, rel_res and x filled) when
+ * max_iter is reached first.
+ */
+int gmres_solve(fmm_plan plan, const fmm_operator *op, const double *b, double *x,
+                double rtol, int restart, int max_iter, int *iters, double *rel_res,
+                void *hip_stream);
+
+/* Release the plan and its device memory. NULL is a no-op. */
+int fmm_destroy(fmm_plan plan);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *fmm_last_error(void);
+
+/*
+ * Plain O(n_trg * n_src) evaluation of the same sum on the GPU (no tree):
+ * the all-pairs reference and small-problem path. Arguments as fmm_apply
+ * with nrhs = 1; nrm is required iff mu != NULL.
+ */
+int fmm_direct(const float *src_xyz, const float *src_nrm, int64_t n_src,
+               const float *trg_xyz, int64_t n_trg, const float *q, const float *mu,
+               float cutoff, float *pot, float *field, void *hip_stream);
+
+/* Plan statistics (host struct filled from host-side copies). */
+typedef struct {
+    int64_t n_src, n_trg, n_points;      /* points inserted in the tree = n_points */
+    int64_t n_boxes, n_leaves, n_levels;
+    int64_t n_u, n_v, n_w, n_x;          /* list entries (U counts leaf pairs, self included) */
+    int64_t n_surface;                   /* n_s = 6 (p-1)^2 + 2 */
+    int64_t p2p_pairs;                   /* near-field point pairs evaluated per apply */
+    int64_t m2l_pairs;                   /* M2L box pairs (V-list entries with sources) per rhs */
+    int64_t surf_evals;                  /* target x surface-point evaluations (L2P + M2P) per rhs */
+    int64_t p2m_evals;                   /* surface-point x source evaluations (P2M + P2L) per rhs */
+    double root[4];                      /* root cube actually used */
+    double setup_ms;                     /* wall time of fmm_setup */
+} fmm_info;
+int fmm_plan_info(fmm_plan plan, fmm_info *info);
+
+/*
+ * Copy the tree and lists to host memory for inspection. Any pointer may be
+ * NULL to skip it. Sizes: box arrays [n_boxes]; list offsets [n_boxes+1];
+ * list entries [n_u|n_v|n_w|n_x]; perms [n_src] / [n_trg]; keys [n_points].
+ * Lists are sorted ascending within each box. Boxes are numbered level by
+ * level, in Morton order within a level.
+ */
+typedef struct {
+    int32_t *level, *anchor /* [n_boxes][3] */, *parent;
+    int64_t *begin, *end;               /* range in the sorted combined point order */
+    int64_t *tbeg, *tend, *sbeg, *send; /* target / source ranges */
+    int32_t *u_off, *u_idx, *v_off, *v_idx, *w_off, *w_idx, *x_off, *x_idx;
+    int64_t *src_perm, *trg_perm;       /* user index of the k-th sorted source / target */
+    uint64_t *keys;                     /* sorted Morton keys of the combined points */
+} fmm_tree_export;
+int fmm_export_tree(fmm_plan plan, const fmm_tree_export *out);
+
+/* Host utility (no device work): truncated-SVD pseudo-inverse of the n x n
+ * row-major float64 matrix K (host), singular values below eps * sigma_max
+ * dropped, written to out (host, n x n row-major). This is the
+ * check-to-equivalent map construction used by fmm_setup. */
+int fmm_pinv(const double *K, int n, double eps, double *out);
+
+/* Host utility: the unit surface Y(p) used for order p, [n_s][3] float64
+ * written to out (host); returns n_s through *ns. out may be NULL to query. */
+int fmm_unit_surface(int p, double *out, int *ns);
+
+/* Turn per-stage device timing on or off for later applies of this plan
+ * (hipEvents recorded on the apply's stream; the apply then waits for them). */
+int fmm_set_timing(fmm_plan plan, int enable);
+
+/*
+ * Copy per-box check potentials of the last apply to host memory, rhs 0:
+ * which = 0: upward check potentials [n_boxes][n_s];
+ * which = 1: downward check potentials after the parent's contribution
+ *            [n_boxes][n_s]. Boxes that were not computed hold zeros.
+ */
+int fmm_export_stage(fmm_plan plan, int which, float *host_out);
+
+/* Device time (ms) of each stage of the last apply made with timing on
+ * (fmm_set_timing); -1 when none was. Order: P2M, M2M, P2L, M2L, L2L, C2E, EVAL. */
+int fmm_stage_times(fmm_plan plan, double *ms /* [7] */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_MI355X_H */

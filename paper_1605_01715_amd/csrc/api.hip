@@ -1,0 +1,339 @@
+// C ABI of the library (declared in include/fmm.h).
+#include <chrono>
+#include <cmath>
+
+#include "plan.hpp"
+
+struct fmm_plan_s {
+    fmm::Plan p;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        f();
+        return FMM_OK;
+    } catch (const fmm::Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(FMM_ERR_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(FMM_ERR_DEVICE, e.what());
+    }
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+fmm::Plan &live(fmm_plan plan) {
+    if (!plan) throw fmm::Error(FMM_ERR_ARG, "plan is NULL");
+    if (!plan->p.alive) throw fmm::Error(FMM_ERR_STATE, "plan was destroyed");
+    return plan->p;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fmm_default_options(fmm_options *opt) {
+    if (!opt) return;
+    *opt = fmm_options{};
+    opt->order = 6;
+    opt->leaf_size = 64;
+    opt->uniform_depth = 0;
+    opt->max_depth = 21;
+    opt->precision = FMM_PREC_FP32;
+    opt->src_kernels = FMM_SRC_SINGLE;
+    opt->outputs = FMM_OUT_POT;
+    opt->nrhs = 1;
+    opt->cutoff = 1e-5f;
+    opt->root[0] = opt->root[1] = opt->root[2] = opt->root[3] = 0.0;
+    opt->pinv_eps = 0.0;
+}
+
+const char *fmm_last_error(void) { return g_last_error.c_str(); }
+
+int fmm_setup(const float *src_xyz, const float *src_nrm, int64_t n_src, const float *trg_xyz, const float *trg_nrm,
+              int64_t n_trg, const fmm_options *opt, void *hip_stream, fmm_plan *out) {
+    return guarded([&] {
+        using namespace fmm;
+        FMM_REQUIRE(out != nullptr, "fmm_setup: out is NULL");
+        *out = nullptr;
+        FMM_REQUIRE(opt != nullptr, "fmm_setup: options are NULL");
+        FMM_REQUIRE(n_src >= 0 && n_trg >= 0, "fmm_setup: negative point count");
+        FMM_REQUIRE(n_src == 0 || src_xyz != nullptr, "fmm_setup: src_xyz is NULL");
+        FMM_REQUIRE(trg_xyz == nullptr || n_trg >= 0, "fmm_setup: bad target count");
+        FMM_REQUIRE(opt->order >= 2 && opt->order <= 10, "fmm_setup: order must be in 2..10");
+        FMM_REQUIRE(opt->leaf_size >= 1, "fmm_setup: leaf_size must be >= 1");
+        FMM_REQUIRE(opt->max_depth >= 1 && opt->max_depth <= kMaxLevel, "fmm_setup: max_depth must be in 1..21");
+        FMM_REQUIRE(opt->uniform_depth >= 0 && opt->uniform_depth <= kMaxLevel, "fmm_setup: uniform_depth must be in 0..21");
+        FMM_REQUIRE(opt->nrhs >= 1 && opt->nrhs <= 4, "fmm_setup: nrhs must be in 1..4");
+        FMM_REQUIRE(opt->precision == FMM_PREC_FP32 || opt->precision == FMM_PREC_SPLIT_BF16,
+                    "fmm_setup: unknown precision");
+        FMM_REQUIRE((opt->src_kernels & ~3) == 0 && opt->src_kernels != 0, "fmm_setup: src_kernels must be a nonzero FMM_SRC_* mask");
+        FMM_REQUIRE((opt->outputs & ~3) == 0 && opt->outputs != 0, "fmm_setup: outputs must be a nonzero FMM_OUT_* mask");
+        FMM_REQUIRE(!((opt->outputs & FMM_OUT_FIELD) && (opt->src_kernels & FMM_SRC_DOUBLE)),
+                    "fmm_setup: the field output is defined for the single layer only");
+        FMM_REQUIRE(!(opt->src_kernels & FMM_SRC_DOUBLE) || n_src == 0 || src_nrm != nullptr,
+                    "fmm_setup: the double layer needs source normals");
+        FMM_REQUIRE(std::isfinite(opt->cutoff) && opt->cutoff >= 0.f, "fmm_setup: cutoff must be finite and >= 0");
+        FMM_REQUIRE(opt->root[3] <= 0.0 || (std::isfinite(opt->root[0]) && std::isfinite(opt->root[1]) &&
+                                            std::isfinite(opt->root[2]) && std::isfinite(opt->root[3])),
+                    "fmm_setup: root cube is not finite");
+        FMM_REQUIRE(n_src + n_trg < (int64_t(1) << 31), "fmm_setup: more than 2^31 - 1 points");
+
+        auto t0 = std::chrono::steady_clock::now();
+        hipStream_t s = as_stream(hip_stream);
+        auto *h = new fmm_plan_s();
+        try {
+            Plan &P = h->p;
+            P.opt = *opt;
+            P.nrhs = opt->nrhs;
+            P.sl = opt->src_kernels & FMM_SRC_SINGLE;
+            P.dl = opt->src_kernels & FMM_SRC_DOUBLE;
+            P.want_pot = opt->outputs & FMM_OUT_POT;
+            P.want_field = opt->outputs & FMM_OUT_FIELD;
+            P.m2l_prec = opt->precision == FMM_PREC_SPLIT_BF16 ? GemmPrec::BF16X6 : GemmPrec::F32;
+            TreeOptions to;
+            to.leaf_size = opt->leaf_size;
+            to.uniform_depth = opt->uniform_depth;
+            to.max_depth = opt->max_depth;
+            for (int c = 0; c < 4; ++c) to.root[c] = opt->root[c];
+            build_tree(P.t, src_xyz, src_nrm, n_src, trg_xyz, trg_nrm, n_trg, to, s);
+            double eps = opt->pinv_eps > 0 ? opt->pinv_eps : default_pinv_eps(opt->order);
+            P.ops = get_operators(opt->order, eps, s);
+            P.ns = P.ops->ns;
+            P.n_pad = P.ops->n_pad;
+            const size_t nvec = (size_t)P.t.nb * P.nrhs;
+            P.uchk.alloc(nvec * P.n_pad);
+            P.dchk.alloc(nvec * P.n_pad);
+            P.phi_u.alloc(nvec * P.n_pad);
+            P.phi_d.alloc(nvec * P.n_pad);
+            if (P.uchk.n) FMM_HIP(hipMemsetAsync(P.uchk.p, 0, P.uchk.bytes(), s));
+            if (P.phi_u.n) FMM_HIP(hipMemsetAsync(P.phi_u.p, 0, P.phi_u.bytes(), s));
+            if (P.phi_d.n) FMM_HIP(hipMemsetAsync(P.phi_d.p, 0, P.phi_d.bytes(), s));
+            const size_t nsv = (size_t)P.nrhs * P.t.n_src;
+            if (P.sl) P.q_sorted.alloc(nsv);
+            if (P.dl) {
+                P.mx.alloc(nsv);
+                P.my.alloc(nsv);
+                P.mz.alloc(nsv);
+            }
+            if (trg_nrm && !P.t.tsm && n_src) {
+                P.trg_nrm_user.alloc(3 * (size_t)n_src);
+                FMM_HIP(hipMemcpyAsync(P.trg_nrm_user.p, trg_nrm, 3 * n_src * sizeof(float),
+                                       hipMemcpyDeviceToDevice, s));
+            }
+            if (P.t.nb) plan_build_worklists(P, s);
+            FMM_HIP(hipStreamSynchronize(s));
+            P.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+int fmm_apply(fmm_plan plan, const float *q, const float *mu, float *pot, float *field, void *hip_stream) {
+    return guarded([&] {
+        using namespace fmm;
+        Plan &P = live(plan);
+        FMM_REQUIRE(q == nullptr || P.sl, "fmm_apply: q given but the plan has no single layer");
+        FMM_REQUIRE(mu == nullptr || P.dl, "fmm_apply: mu given but the plan has no double layer");
+        FMM_REQUIRE(pot == nullptr || P.want_pot, "fmm_apply: potential not among the plan's outputs");
+        FMM_REQUIRE(field == nullptr || P.want_field, "fmm_apply: field not among the plan's outputs");
+        FMM_REQUIRE(field == nullptr || mu == nullptr, "fmm_apply: the field output needs the single layer only");
+        hipStream_t s = as_stream(hip_stream);
+        const int64_t nt = P.t.n_trg;
+        if (P.t.nb == 0 || P.t.n_src == 0 || (q == nullptr && mu == nullptr)) {
+            if (pot && nt) FMM_HIP(hipMemsetAsync(pot, 0, sizeof(float) * P.nrhs * nt, s));
+            if (field && nt) FMM_HIP(hipMemsetAsync(field, 0, sizeof(float) * 3 * P.nrhs * nt, s));
+            return;
+        }
+        if (P.timing && !P.ev[0]) {
+            for (auto &e : P.ev) FMM_HIP(hipEventCreate(&e));
+        }
+        plan_apply(P, q, mu, pot, field, s);
+    });
+}
+
+int gmres_solve(fmm_plan plan, const fmm_operator *op, const double *b, double *x, double rtol, int restart,
+                int max_iter, int *iters, double *rel_res, void *hip_stream) {
+    int status = FMM_OK;
+    int rc = guarded([&] {
+        using namespace fmm;
+        Plan &P = live(plan);
+        FMM_REQUIRE(op && b && x && iters && rel_res, "gmres_solve: NULL argument");
+        FMM_REQUIRE(!P.t.tsm, "gmres_solve: the operator needs targets equal to sources");
+        FMM_REQUIRE(P.nrhs == 1, "gmres_solve: the plan must have nrhs = 1");
+        FMM_REQUIRE(P.t.n_src > 0, "gmres_solve: empty plan");
+        FMM_REQUIRE(op->a && op->w, "gmres_solve: operator coefficients a and w are required");
+        if (op->kind == FMM_OP_FK) {
+            FMM_REQUIRE(P.dl && P.want_pot, "gmres_solve: FK needs a double-layer plan with potential output");
+        } else if (op->kind == FMM_OP_DIELECTRIC) {
+            FMM_REQUIRE(op->c, "gmres_solve: dielectric operator needs c");
+            FMM_REQUIRE(P.sl && P.want_field, "gmres_solve: dielectric needs a single-layer plan with field output");
+            FMM_REQUIRE(P.trg_nrm_user.n, "gmres_solve: dielectric needs target normals at setup");
+        } else {
+            throw Error(FMM_ERR_ARG, "gmres_solve: unknown operator kind");
+        }
+        FMM_REQUIRE(rtol > 0.0 && std::isfinite(rtol), "gmres_solve: rtol must be > 0");
+        FMM_REQUIRE(restart >= 1 && restart <= 500, "gmres_solve: restart must be in 1..500");
+        FMM_REQUIRE(max_iter >= 0, "gmres_solve: max_iter must be >= 0");
+        plan_gmres(P, *op, b, x, rtol, restart, max_iter, iters, rel_res, &status, as_stream(hip_stream));
+    });
+    if (rc != FMM_OK) return rc;
+    if (status == FMM_ERR_NOT_CONVERGED)
+        g_last_error = "gmres_solve: not converged (relative residual " + std::to_string(*rel_res) + " after " +
+                       std::to_string(*iters) + " iterations)";
+    return status;
+}
+
+int fmm_destroy(fmm_plan plan) {
+    if (!plan) return FMM_OK;
+    return guarded([&] {
+        for (auto &e : plan->p.ev)
+            if (e) (void)hipEventDestroy(e);
+        plan->p.alive = false;
+        delete plan;
+    });
+}
+
+int fmm_direct(const float *src_xyz, const float *src_nrm, int64_t n_src, const float *trg_xyz, int64_t n_trg,
+               const float *q, const float *mu, float cutoff, float *pot, float *field, void *hip_stream) {
+    return guarded([&] {
+        using namespace fmm;
+        FMM_REQUIRE(n_src >= 0 && n_trg >= 0, "fmm_direct: negative count");
+        FMM_REQUIRE(n_src == 0 || src_xyz != nullptr, "fmm_direct: src_xyz is NULL");
+        FMM_REQUIRE(n_trg == 0 || trg_xyz != nullptr, "fmm_direct: trg_xyz is NULL");
+        FMM_REQUIRE(mu == nullptr || src_nrm != nullptr, "fmm_direct: mu needs normals");
+        FMM_REQUIRE(field == nullptr || mu == nullptr, "fmm_direct: field is defined for the single layer only");
+        FMM_REQUIRE(std::isfinite(cutoff) && cutoff >= 0.f, "fmm_direct: bad cutoff");
+        direct_all_pairs(trg_xyz, n_trg, src_xyz, src_nrm, n_src, q, mu, cutoff, pot, field, as_stream(hip_stream));
+    });
+}
+
+int fmm_plan_info(fmm_plan plan, fmm_info *info) {
+    return guarded([&] {
+        using namespace fmm;
+        Plan &P = live(plan);
+        FMM_REQUIRE(info != nullptr, "fmm_plan_info: info is NULL");
+        fmm_info r{};
+        r.n_src = P.t.n_src;
+        r.n_trg = P.t.n_trg;
+        r.n_points = P.t.n;
+        r.n_boxes = P.t.nb;
+        int64_t nl = 0;
+        for (auto v : P.t.h_leaf) nl += v;
+        r.n_leaves = nl;
+        r.n_levels = P.t.nlev;
+        r.n_u = P.t.U.total;
+        r.n_v = P.t.V.total;
+        r.n_w = P.t.W.total;
+        r.n_x = P.t.X.total;
+        r.n_surface = P.ns;
+        r.p2p_pairs = P.p2p_pairs;
+        r.m2l_pairs = P.m2l_pairs;
+        r.surf_evals = P.surf_evals;
+        r.p2m_evals = P.p2m_evals;
+        for (int c = 0; c < 3; ++c) r.root[c] = P.t.x0[c];
+        r.root[3] = P.t.w;
+        r.setup_ms = P.setup_ms;
+        *info = r;
+    });
+}
+
+int fmm_export_tree(fmm_plan plan, const fmm_tree_export *o) {
+    return guarded([&] {
+        using namespace fmm;
+        Plan &P = live(plan);
+        FMM_REQUIRE(o != nullptr, "fmm_export_tree: out is NULL");
+        Tree &t = P.t;
+        auto cp = [](auto *dst, const auto &src) {
+            if (dst) std::copy(src.begin(), src.end(), dst);
+        };
+        cp(o->level, t.h_level);
+        cp(o->anchor, t.h_anchor);
+        cp(o->parent, t.h_parent);
+        cp(o->begin, t.h_begin);
+        cp(o->end, t.h_end);
+        cp(o->tbeg, t.h_tbeg);
+        cp(o->tend, t.h_tend);
+        cp(o->sbeg, t.h_sbeg);
+        cp(o->send, t.h_send);
+        cp(o->u_off, t.U.h_off);
+        cp(o->u_idx, t.U.h_idx);
+        cp(o->v_off, t.V.h_off);
+        cp(o->v_idx, t.V.h_idx);
+        cp(o->w_off, t.W.h_off);
+        cp(o->w_idx, t.W.h_idx);
+        cp(o->x_off, t.X.h_off);
+        cp(o->x_idx, t.X.h_idx);
+        hipStream_t s = nullptr;
+        if (o->src_perm && t.n_src) d2h(o->src_perm, t.src_perm.p, t.n_src, s);
+        if (o->trg_perm && t.n_trg) d2h(o->trg_perm, t.tsm ? t.trg_perm.p : t.src_perm.p, t.n_trg, s);
+        if (o->keys && t.n) d2h(o->keys, t.keys.p, t.n, s);
+    });
+}
+
+int fmm_export_stage(fmm_plan plan, int which, float *host_out) {
+    return guarded([&] {
+        using namespace fmm;
+        Plan &P = live(plan);
+        FMM_REQUIRE(host_out != nullptr, "fmm_export_stage: out is NULL");
+        FMM_REQUIRE(which == 0 || which == 1, "fmm_export_stage: which must be 0 or 1");
+        const DBuf<float> &b = which == 0 ? P.uchk : P.dchk;
+        std::vector<float> all(b.n);
+        FMM_HIP(hipDeviceSynchronize());
+        d2h(all.data(), b.p, b.n, nullptr);
+        for (int64_t box = 0; box < P.t.nb; ++box)
+            for (int m = 0; m < P.ns; ++m)
+                host_out[box * P.ns + m] = all[((size_t)box * P.nrhs) * P.n_pad + m];
+    });
+}
+
+int fmm_pinv(const double *K, int n, double eps, double *out) {
+    return guarded([&] {
+        using namespace fmm;
+        FMM_REQUIRE(K && out && n > 0 && n <= 4096, "fmm_pinv: bad arguments");
+        FMM_REQUIRE(eps >= 0.0 && std::isfinite(eps), "fmm_pinv: bad eps");
+        std::vector<double> k(K, K + (size_t)n * n);
+        std::vector<double> p = pinv_jacobi(k, n, eps);
+        std::copy(p.begin(), p.end(), out);
+    });
+}
+
+int fmm_unit_surface(int p, double *out, int *ns) {
+    return guarded([&] {
+        using namespace fmm;
+        FMM_REQUIRE(p >= 2 && p <= 10 && ns, "fmm_unit_surface: bad arguments");
+        std::vector<double> y = unit_surface(p);
+        *ns = (int)(y.size() / 3);
+        if (out) std::copy(y.begin(), y.end(), out);
+    });
+}
+
+int fmm_set_timing(fmm_plan plan, int enable) {
+    return guarded([&] { live(plan).timing = enable != 0; });
+}
+
+int fmm_stage_times(fmm_plan plan, double *ms) {
+    return guarded([&] {
+        using namespace fmm;
+        Plan &P = live(plan);
+        FMM_REQUIRE(ms != nullptr, "fmm_stage_times: out is NULL");
+        for (int k = 0; k < ST_COUNT; ++k) ms[k] = P.have_times ? P.stage_ms[k] : -1.0;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,445 @@
+// Work lists and the apply pipeline of one FMM evaluation.
+//
+// Upward pass: P2M at the leaves, M2M level by level towards the root (on
+// check potentials). Far-field translation: M2L over the V lists, P2L over the
+// X lists. Downward pass: L2L level by level towards the leaves, then the
+// check-to-equivalent maps in float64. Evaluation: one fused kernel per leaf
+// adds L2P, M2P (W lists) and the near field (U lists and the direct W/X
+// pairs) and writes the results in the caller's order.
+//
+// Paper-silent reading: a W or X partner holding at most n_s points is
+// evaluated directly rather than through a surface (this never changes what
+// is computed, only how).
+#include <algorithm>
+
+#include "plan.hpp"
+
+namespace fmm {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void k_m2l_src(const int32_t *cols, int64_t ncolumns, const int32_t *vdense, const int64_t *sbeg,
+                          const int64_t *send, int nrhs, int32_t *src) {
+    // src[tile][d][c] for tile = idx / (316 * 64)
+    int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t ntile = ncolumns / 64;
+    if (idx >= ntile * kNumDirs * 64) return;
+    int c = (int)(idx % 64);
+    int64_t r = idx / 64;
+    int d = (int)(r % kNumDirs);
+    int64_t tile = r / kNumDirs;
+    int32_t v = cols[tile * 64 + c];
+    int32_t out = -1;
+    if (v >= 0) {
+        int32_t box = v / nrhs, rr = v % nrhs;
+        int32_t a = vdense[(int64_t)box * kNumDirs + d];
+        if (a >= 0 && send[a] > sbeg[a]) out = a * nrhs + rr;
+    }
+    src[idx] = out;
+}
+
+__global__ void k_sort_densities(const int64_t *perm, int64_t n, int nrhs, const float *q, const float *mu,
+                                 const float *nx, const float *ny, const float *nz, float *qs, float *mx, float *my,
+                                 float *mz) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int64_t o = perm[i];
+    for (int r = 0; r < nrhs; ++r) {
+        if (q) qs[r * n + i] = q[r * n + o];
+        if (mu) {
+            float m = mu[r * n + o];
+            mx[r * n + i] = m * nx[i];
+            my[r * n + i] = m * ny[i];
+            mz[r * n + i] = m * nz[i];
+        }
+    }
+}
+
+// Pack output-vector lists into tiles of `ncol` columns; vector index = box * nrhs + r.
+std::vector<int32_t> tile_columns(const std::vector<int32_t> &boxes, int nrhs, int ncol, int &ntile) {
+    std::vector<int32_t> cols;
+    for (int32_t b : boxes)
+        for (int r = 0; r < nrhs; ++r) cols.push_back(b * nrhs + r);
+    ntile = (int)((cols.size() + ncol - 1) / ncol);
+    cols.resize((size_t)ntile * ncol, -1);
+    return cols;
+}
+
+void add_range(std::vector<int32_t> &rng, int64_t s0, int64_t s1) {
+    if (s1 <= s0) return;
+    rng.push_back((int32_t)s0);
+    rng.push_back((int32_t)s1);
+}
+
+// sort ranges by start and merge touching ones
+void merge_ranges(std::vector<int32_t> &r, size_t from) {
+    size_t n = (r.size() - from) / 2;
+    if (n < 2) return;
+    std::vector<std::pair<int32_t, int32_t>> v(n);
+    for (size_t i = 0; i < n; ++i) v[i] = {r[from + 2 * i], r[from + 2 * i + 1]};
+    std::sort(v.begin(), v.end());
+    r.resize(from);
+    int32_t a = v[0].first, b = v[0].second;
+    for (size_t i = 1; i < n; ++i) {
+        if (v[i].first == b) {
+            b = v[i].second;
+        } else {
+            r.push_back(a);
+            r.push_back(b);
+            a = v[i].first;
+            b = v[i].second;
+        }
+    }
+    r.push_back(a);
+    r.push_back(b);
+}
+
+}  // namespace
+
+void plan_build_worklists(Plan &P, hipStream_t s) {
+    Tree &t = P.t;
+    const int64_t nb = t.nb;
+    const int nrhs = P.nrhs, ns = P.ns;
+    auto nsrc = [&](int64_t b) { return t.h_send[b] - t.h_sbeg[b]; };
+    auto ntrg = [&](int64_t b) { return t.h_tend[b] - t.h_tbeg[b]; };
+    auto leaf = [&](int64_t b) { return t.h_leaf[b] != 0; };
+    auto lvl = [&](int64_t b) { return t.h_level[b]; };
+    const auto &U = t.U, &W = t.W, &X = t.X;
+
+    // per-vector scale = box half-width (check-to-equivalent maps)
+    {
+        std::vector<double> sc((size_t)nb * nrhs);
+        for (int64_t b = 0; b < nb; ++b)
+            for (int r = 0; r < nrhs; ++r) sc[b * nrhs + r] = t.h_half[b];
+        P.col_scale = upload(sc, s);
+    }
+
+    // P2M
+    {
+        std::vector<int32_t> items, roff{0}, rng;
+        for (int64_t b = 0; b < nb; ++b)
+            if (leaf(b) && lvl(b) >= 2 && nsrc(b) > 0) {
+                items.push_back((int32_t)b);
+                add_range(rng, t.h_sbeg[b], t.h_send[b]);
+                roff.push_back((int32_t)(rng.size() / 2));
+                P.p2m_evals += nsrc(b) * ns;
+            }
+        P.n_p2m = (int)items.size();
+        P.p2m_items = upload(items, s);
+        P.p2m_roff = upload(roff, s);
+        P.p2m_rng = upload(rng, s);
+    }
+
+    const int ncol = gemm_ncol(GemmPrec::F32);
+    const int ncol64 = gemm_ncol(GemmPrec::F64);
+    // M2M, bottom-up (float64 tiles)
+    for (int l = t.nlev - 2; l >= 2; --l) {
+        std::vector<int32_t> boxes;
+        for (int64_t b = t.lvl_off[l]; b < t.lvl_off[l + 1]; ++b)
+            if (!leaf(b) && nsrc(b) > 0) boxes.push_back((int32_t)b);
+        if (boxes.empty()) continue;
+        GemmJob j;
+        std::vector<int32_t> cols = tile_columns(boxes, nrhs, ncol64, j.ntile);
+        j.nterm = 8;
+        std::vector<int32_t> src((size_t)j.ntile * 8 * ncol64, -1);
+        for (int tl = 0; tl < j.ntile; ++tl)
+            for (int c = 0; c < ncol64; ++c) {
+                int32_t v = cols[(size_t)tl * ncol64 + c];
+                if (v < 0) continue;
+                int32_t box = v / nrhs, r = v % nrhs;
+                for (int o = 0; o < 8; ++o) {
+                    int32_t ch = t.h_child[8 * (size_t)box + o];
+                    if (ch >= 0 && nsrc(ch) > 0) src[((size_t)tl * 8 + o) * ncol64 + c] = ch * nrhs + r;
+                }
+            }
+        j.cols = upload(cols, s);
+        j.src = upload(src, s);
+        P.m2m_jobs.push_back(std::move(j));
+    }
+
+    // M2L: every target box at level >= 2 with at least one V partner holding sources
+    {
+        std::vector<int32_t> boxes;
+        for (int64_t b = 0; b < nb; ++b) {
+            if (lvl(b) < 2 || ntrg(b) == 0) continue;
+            bool any = false;
+            for (int32_t k = t.V.h_off[b]; k < t.V.h_off[b + 1] && !any; ++k) any = nsrc(t.V.h_idx[k]) > 0;
+            if (any) {
+                boxes.push_back((int32_t)b);
+                for (int32_t k = t.V.h_off[b]; k < t.V.h_off[b + 1]; ++k)
+                    if (nsrc(t.V.h_idx[k]) > 0) ++P.m2l_pairs;
+            }
+        }
+        GemmJob &j = P.m2l;
+        std::vector<int32_t> cols = tile_columns(boxes, nrhs, ncol, j.ntile);
+        j.nterm = kNumDirs;
+        j.cols = upload(cols, s);
+        if (j.ntile > 0) {
+            j.src.alloc((size_t)j.ntile * kNumDirs * ncol);
+            int64_t total = (int64_t)j.ntile * kNumDirs * ncol;
+            hipLaunchKernelGGL(k_m2l_src, dim3(grid_for(total, kBlock)), dim3(kBlock), 0, s, j.cols.p,
+                               (int64_t)j.ntile * ncol, t.vdense.p, t.sbeg.p, t.send.p, nrhs, j.src.p);
+            FMM_HIP(hipGetLastError());
+        }
+    }
+
+    // P2L (X lists of boxes holding more than n_s targets)
+    {
+        std::vector<int32_t> items, roff{0}, rng;
+        for (int64_t b = 0; b < nb; ++b) {
+            if (ntrg(b) <= ns) continue;
+            size_t from = rng.size();
+            for (int32_t k = X.h_off[b]; k < X.h_off[b + 1]; ++k) {
+                int32_t a = X.h_idx[k];
+                add_range(rng, t.h_sbeg[a], t.h_send[a]);
+            }
+            if (rng.size() == from) continue;
+            merge_ranges(rng, from);
+            for (size_t e = from; e < rng.size(); e += 2) P.p2m_evals += (int64_t)(rng[e + 1] - rng[e]) * ns;
+            items.push_back((int32_t)b);
+            roff.push_back((int32_t)(rng.size() / 2));
+        }
+        P.n_p2l = (int)items.size();
+        P.p2l_items = upload(items, s);
+        P.p2l_roff = upload(roff, s);
+        P.p2l_rng = upload(rng, s);
+    }
+
+    // L2L, top-down, float64 tiles grouped by octant (one matrix per tile)
+    for (int l = 3; l < t.nlev; ++l) {
+        std::vector<int32_t> by_oct[8];
+        for (int64_t b = t.lvl_off[l]; b < t.lvl_off[l + 1]; ++b) {
+            if (ntrg(b) == 0) continue;
+            const int32_t *a = &t.h_anchor[3 * b];
+            int o = ((a[0] & 1) << 2) | ((a[1] & 1) << 1) | (a[2] & 1);
+            by_oct[o].push_back((int32_t)b);
+        }
+        GemmJob j;
+        j.nterm = 1;
+        j.use_mat = true;
+        std::vector<int32_t> cols, src, mat;
+        for (int o = 0; o < 8; ++o) {
+            if (by_oct[o].empty()) continue;
+            int nt = 0;
+            std::vector<int32_t> c = tile_columns(by_oct[o], nrhs, ncol64, nt);
+            for (int tl = 0; tl < nt; ++tl) {
+                mat.push_back(o);
+                for (int k = 0; k < ncol64; ++k) {
+                    int32_t v = c[(size_t)tl * ncol64 + k];
+                    cols.push_back(v);
+                    src.push_back(v < 0 ? -1 : t.h_parent[v / nrhs] * nrhs + v % nrhs);
+                }
+            }
+            j.ntile += nt;
+        }
+        if (j.ntile == 0) continue;
+        j.cols = upload(cols, s);
+        j.src = upload(src, s);
+        j.mat = upload(mat, s);
+        P.l2l_jobs.push_back(std::move(j));
+    }
+
+    // check-to-equivalent maps and the leaf evaluation lists
+    std::vector<int32_t> down_boxes;
+    std::vector<uint8_t> up_needed(nb, 0);
+    std::vector<int32_t> wleaf, wt0, soff{0}, sbox, poff{0}, prng;
+    std::vector<int8_t> skind;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (!leaf(b) || ntrg(b) == 0) continue;
+        if (lvl(b) >= 2) {
+            down_boxes.push_back((int32_t)b);
+            sbox.push_back((int32_t)b);
+            skind.push_back(0);
+            P.surf_evals += ntrg(b) * ns;
+        }
+        size_t from = prng.size();
+        for (int32_t k = U.h_off[b]; k < U.h_off[b + 1]; ++k) {
+            int32_t a = U.h_idx[k];
+            add_range(prng, t.h_sbeg[a], t.h_send[a]);
+        }
+        for (int32_t k = W.h_off[b]; k < W.h_off[b + 1]; ++k) {
+            int32_t a = W.h_idx[k];
+            if (nsrc(a) == 0) continue;
+            if (nsrc(a) <= ns) {
+                add_range(prng, t.h_sbeg[a], t.h_send[a]);
+            } else {
+                sbox.push_back(a);
+                skind.push_back(1);
+                up_needed[a] = 1;
+                P.surf_evals += ntrg(b) * ns;
+            }
+        }
+        for (int64_t anc = b; anc >= 0; anc = t.h_parent[anc]) {
+            if (ntrg(anc) > ns) continue;
+            for (int32_t k = X.h_off[anc]; k < X.h_off[anc + 1]; ++k) {
+                int32_t a = X.h_idx[k];
+                add_range(prng, t.h_sbeg[a], t.h_send[a]);
+            }
+        }
+        merge_ranges(prng, from);
+        int64_t npts = 0;
+        for (size_t e = from; e < prng.size(); e += 2) npts += prng[e + 1] - prng[e];
+        P.p2p_pairs += npts * ntrg(b);
+        soff.push_back((int32_t)sbox.size());
+        poff.push_back((int32_t)(prng.size() / 2));
+        for (int64_t t0 = 0; t0 < ntrg(b); t0 += 64) {
+            wleaf.push_back((int32_t)b);
+            wt0.push_back((int32_t)t0);
+        }
+    }
+    // soff/poff are indexed by leaf id: expand to all boxes
+    {
+        std::vector<int32_t> so(nb + 1, 0), po(nb + 1, 0);
+        size_t li = 0;
+        int32_t cs = 0, cp = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            so[b] = cs;
+            po[b] = cp;
+            if (leaf(b) && ntrg(b) > 0) {
+                cs = soff[li + 1];
+                cp = poff[li + 1];
+                ++li;
+            }
+        }
+        so[nb] = cs;
+        po[nb] = cp;
+        P.soff = upload(so, s);
+        P.poff = upload(po, s);
+    }
+    P.nwork = (int)wleaf.size();
+    P.wleaf = upload(wleaf, s);
+    P.wt0 = upload(wt0, s);
+    P.sbox = upload(sbox, s);
+    P.skind = upload(skind, s);
+    P.prng = upload(prng, s);
+    {
+        GemmJob &j = P.c2e_down;
+        std::vector<int32_t> cols = tile_columns(down_boxes, nrhs, ncol64, j.ntile);
+        j.nterm = 1;
+        j.cols = upload(cols, s);
+        j.src = upload(cols, s);
+    }
+    {
+        std::vector<int32_t> ub;
+        for (int64_t b = 0; b < nb; ++b)
+            if (up_needed[b]) ub.push_back((int32_t)b);
+        GemmJob &j = P.c2e_up;
+        std::vector<int32_t> cols = tile_columns(ub, nrhs, ncol64, j.ntile);
+        j.nterm = 1;
+        j.cols = upload(cols, s);
+        j.src = upload(cols, s);
+    }
+    FMM_HIP(hipStreamSynchronize(s));
+}
+
+static void run_gemm(Plan &P, GemmJob &j, GemmPrec prec, const void *mats, const float *in, float *out,
+                     const double *scale, bool accumulate, hipStream_t s) {
+    if (j.ntile == 0) return;
+    GemmLaunch a;
+    a.n_pad = P.n_pad;
+    a.ntile = j.ntile;
+    a.nterm = j.nterm;
+    a.tile_cols = j.cols.p;
+    a.term_src = j.src.p;
+    a.term_mat = j.use_mat ? j.mat.p : nullptr;
+    a.mats = mats;
+    a.mat_elems = P.ops->mat_elems;
+    a.in = in;
+    a.out = out;
+    a.col_scale = scale;
+    a.accumulate = accumulate ? 1 : 0;
+    box_gemm(prec, a, s);
+}
+
+void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s) {
+    Tree &t = P.t;
+    const int nrhs = P.nrhs;
+    const Operators &op = *P.ops;
+    auto mark = [&](int k) {
+        if (P.timing) FMM_HIP(hipEventRecord(P.ev[k], s));
+    };
+    const bool sl = q != nullptr, dl = mu != nullptr;
+    hipLaunchKernelGGL(k_sort_densities, dim3(grid_for(t.n_src, kBlock)), dim3(kBlock), 0, s, t.src_perm.p, t.n_src,
+                       nrhs, q, mu, t.snx.p, t.sny.p, t.snz.p, P.q_sorted.p, P.mx.p, P.my.p, P.mz.p);
+    FMM_HIP(hipGetLastError());
+    if (P.dchk.n) FMM_HIP(hipMemsetAsync(P.dchk.p, 0, P.dchk.bytes(), s));
+
+    PointSrc src;
+    src.x = t.sx.p;
+    src.y = t.sy.p;
+    src.z = t.sz.p;
+    src.q = P.q_sorted.p;
+    src.mx = P.mx.p;
+    src.my = P.my.p;
+    src.mz = P.mz.p;
+    src.n = t.n_src;
+    SurfaceGeom g;
+    g.Y = op.dY.p;
+    g.ns = op.ns;
+    g.n_pad = op.n_pad;
+    g.centre = t.centre.p;
+    g.half = t.half.p;
+
+    mark(ST_P2M);
+    points_to_surface(nrhs, sl, dl, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, kRadOut, g, src, P.uchk.p,
+                      false, s);
+    mark(ST_M2M);
+    for (auto &j : P.m2m_jobs) run_gemm(P, j, GemmPrec::F64, op.m2m_f64.p, P.uchk.p, P.uchk.p, nullptr, false, s);
+    mark(ST_P2L);
+    points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, kRadIn, g, src, P.dchk.p,
+                      true, s);
+    mark(ST_M2L);
+    if (P.m2l_prec == GemmPrec::BF16X6)
+        run_gemm(P, P.m2l, GemmPrec::BF16X6, op.m2l_bf.p, P.uchk.p, P.dchk.p, nullptr, true, s);
+    else
+        run_gemm(P, P.m2l, GemmPrec::F32, op.m2l_f32.p, P.uchk.p, P.dchk.p, nullptr, true, s);
+    mark(ST_L2L);
+    for (auto &j : P.l2l_jobs) run_gemm(P, j, GemmPrec::F64, op.l2l_f64.p, P.dchk.p, P.dchk.p, nullptr, true, s);
+    mark(ST_C2E);
+    run_gemm(P, P.c2e_down, GemmPrec::F64, op.dc2e_f64.p, P.dchk.p, P.phi_d.p, P.col_scale.p, false, s);
+    run_gemm(P, P.c2e_up, GemmPrec::F64, op.uc2e_f64.p, P.uchk.p, P.phi_u.p, P.col_scale.p, false, s);
+    mark(ST_EVAL);
+    EvalArgs e;
+    e.wleaf = P.wleaf.p;
+    e.wt0 = P.wt0.p;
+    e.nwork = P.nwork;
+    e.soff = P.soff.p;
+    e.sbox = P.sbox.p;
+    e.skind = P.skind.p;
+    e.poff = P.poff.p;
+    e.prng = P.prng.p;
+    e.tbeg = t.tbeg.p;
+    e.tend = t.tend.p;
+    if (t.tsm) {
+        e.tx = t.tx.p;
+        e.ty = t.ty.p;
+        e.tz = t.tz.p;
+        e.trg_perm = t.trg_perm.p;
+    } else {
+        e.tx = t.sx.p;
+        e.ty = t.sy.p;
+        e.tz = t.sz.p;
+        e.trg_perm = t.src_perm.p;
+    }
+    e.n_trg = t.n_trg;
+    e.phi_d = P.phi_d.p;
+    e.phi_u = P.phi_u.p;
+    e.delta2 = P.opt.cutoff * P.opt.cutoff;
+    e.pot = pot;
+    e.field = field;
+    eval_leaves(nrhs, sl, dl, e, g, src, s);
+    mark(ST_COUNT);
+    if (P.timing) {
+        FMM_HIP(hipEventSynchronize(P.ev[ST_COUNT]));
+        for (int k = 0; k < ST_COUNT; ++k) {
+            float ms = 0.f;
+            FMM_HIP(hipEventElapsedTime(&ms, P.ev[k], P.ev[k + 1]));
+            P.stage_ms[k] = ms;
+        }
+        P.have_times = true;
+    }
+}
+
+}  // namespace fmm

@@ -1,0 +1,65 @@
+// Plan object shared by the API translation units.
+#pragma once
+
+#include <memory>
+
+#include "gemm.hpp"
+#include "nbody.hpp"
+#include "operators.hpp"
+#include "tree.hpp"
+
+namespace fmm {
+
+struct GemmJob {
+    DBuf<int32_t> cols, src, mat;
+    int ntile = 0, nterm = 0;
+    bool use_mat = false;
+};
+
+enum Stage { ST_P2M = 0, ST_M2M, ST_P2L, ST_M2L, ST_L2L, ST_C2E, ST_EVAL, ST_COUNT };
+
+struct Plan {
+    fmm_options opt{};
+    int nrhs = 1;
+    bool sl = true, dl = false, want_pot = true, want_field = false;
+    bool alive = true;
+    Tree t;
+    std::shared_ptr<const Operators> ops;
+    int ns = 0, n_pad = 0;
+    GemmPrec m2l_prec = GemmPrec::F32;
+
+    DBuf<float> uchk, dchk, phi_u, phi_d;   // [nb * nrhs][n_pad]
+    DBuf<float> q_sorted, mx, my, mz;       // [nrhs][n_src]
+    DBuf<double> col_scale;                 // half-width per vector index
+    DBuf<float> trg_nrm_user;               // [n_trg][3] target normals, caller's order
+
+    DBuf<int32_t> p2m_items, p2m_roff, p2m_rng;
+    int n_p2m = 0;
+    DBuf<int32_t> p2l_items, p2l_roff, p2l_rng;
+    int n_p2l = 0;
+    std::vector<GemmJob> m2m_jobs;  // bottom-up
+    std::vector<GemmJob> l2l_jobs;  // top-down
+    GemmJob m2l, c2e_down, c2e_up;
+
+    DBuf<int32_t> wleaf, wt0, soff, sbox, poff, prng;
+    DBuf<int8_t> skind;
+    int nwork = 0;
+
+    int64_t p2p_pairs = 0;
+    int64_t m2l_pairs = 0;
+    int64_t surf_evals = 0;
+    int64_t p2m_evals = 0;
+    double setup_ms = 0;
+
+    bool timing = false;
+    hipEvent_t ev[ST_COUNT + 1] = {};
+    double stage_ms[ST_COUNT] = {-1, -1, -1, -1, -1, -1, -1};
+    bool have_times = false;
+};
+
+void plan_build_worklists(Plan &P, hipStream_t s);
+void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s);
+void plan_gmres(Plan &P, const fmm_operator &op, const double *b, double *x, double rtol, int restart, int max_iter,
+                int *iters, double *rel_res, int *status, hipStream_t s);
+
+}  // namespace fmm

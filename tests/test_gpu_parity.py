@@ -1,0 +1,280 @@
+"""Parity of the HIP path with the CPU float64 oracle, through the C ABI.
+
+Tolerances: the float32 path targets 1e-5 relative L2 against the float64
+direct sum (BASELINE target for the plain path). Where the oracle's own
+float64 KIFMM error at the same order is larger (double layer at p = 6) the
+bound is that error plus the float32 floor; against the oracle's KIFMM with
+the same pseudo-inverse threshold the bound is the float32 floor itself.
+Tree and lists are integer data and must match bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct as D
+from oracle import kifmm as K
+from oracle import tree as T
+
+from gpu_common import fmm_run, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _cloud(n, seed, frac_blob=0.6, sigma=0.03):
+    rng = np.random.default_rng(seed)
+    nb = int(n * frac_blob)
+    x = np.concatenate([rng.random((n - nb, 3)), np.clip(0.55 + sigma * rng.standard_normal((nb, 3)), 0, 0.999)])
+    x = x[rng.permutation(n)]
+    nrm = rng.standard_normal((n, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return x.astype(np.float32), nrm.astype(np.float32), rng.standard_normal(n).astype(np.float32), \
+        rng.standard_normal(n).astype(np.float32)
+
+
+# ------------------------------------------------------------------ direct kernel
+def test_direct_all_pairs_matches_oracle():
+    import torch
+
+    import paper_1605_01715_amd as F
+    from gpu_common import dev
+
+    say("test_direct_all_pairs: N=4096 config cube_uniform")
+    d = W.cube_uniform()
+    x = d["xyz"]
+    rng = np.random.default_rng(3)
+    nrm = rng.standard_normal((len(x), 3)).astype(np.float32)
+    mu = rng.standard_normal(len(x)).astype(np.float32)
+    xd = dev(x)
+    pot = torch.empty(len(x), device="cuda:0")
+    fld = torch.empty(3 * len(x), device="cuda:0")
+    F.fmm_direct(xd, xd, q=dev(d["q"]), pot=pot, field=fld)
+    torch.cuda.synchronize()
+    ref_p, ref_f = D.direct_sum(x, x, d["q"], None, field=True)
+    assert D.rel_l2(pot.cpu().numpy(), ref_p) < 1e-6
+    assert D.rel_l2(fld.cpu().numpy().reshape(-1, 3), ref_f) < 1e-6
+    F.fmm_direct(xd, xd, mu=dev(mu), src_nrm=dev(nrm), pot=pot)
+    torch.cuda.synchronize()
+    ref_d, _ = D.direct_sum(x, x, None, mu[:, None].astype(np.float64) * nrm)
+    assert D.rel_l2(pot.cpu().numpy(), ref_d) < 1e-6
+
+
+# ------------------------------------------------------------------ tree and lists
+def _compare_tree(plan, t, L):
+    import paper_1605_01715_amd as F
+
+    g = F.fmm_export_tree(plan)
+    nb = len(t.level)
+    assert len(g["level"]) == nb
+    np.testing.assert_array_equal(g["level"], t.level)
+    np.testing.assert_array_equal(g["anchor"], t.anchor)
+    np.testing.assert_array_equal(g["parent"], t.parent)
+    for k in ("begin", "end", "tbeg", "tend", "sbeg", "send"):
+        np.testing.assert_array_equal(g[k], getattr(t, k), err_msg=k)
+    np.testing.assert_array_equal(g["keys"], t.keys)
+    np.testing.assert_array_equal(g["src_perm"], t.src_perm)
+    np.testing.assert_array_equal(g["trg_perm"], t.trg_perm)
+    for name in "UVWX":
+        k = name.lower()
+        off, idx = g[k + "_off"], g[k + "_idx"]
+        for b in range(nb):
+            np.testing.assert_array_equal(idx[off[b]:off[b + 1]], L[name][b], err_msg=f"{name} list of box {b}")
+
+
+def test_tree_bit_exact_uniform():
+    say("test_tree_bit_exact_uniform: N=4096 depth 3")
+    d = W.cube_uniform()
+    r = fmm_run(d["xyz"], q=d["q"], depth=3, root=d["root"], keep_plan=True)
+    t = T.build_tree(d["xyz"], uniform_depth=3, root=d["root"])
+    _compare_tree(r["plan"], t, T.all_lists(t))
+
+
+@pytest.mark.parametrize("n,s,seed", [(6000, 20, 1), (20000, 64, 2), (1237, 7, 3)])
+def test_tree_bit_exact_adaptive(n, s, seed):
+    say(f"test_tree_bit_exact_adaptive: n={n} s={s} seed={seed}")
+    x, nrm, q, mu = _cloud(n, seed)
+    r = fmm_run(x, q=q, leaf=s, keep_plan=True)
+    t = T.build_tree(x, leaf_size=s)
+    _compare_tree(r["plan"], t, T.all_lists(t))
+
+
+def test_tree_bit_exact_separate_targets():
+    say("test_tree_bit_exact_separate_targets: 3000 targets, 5000 sources")
+    rng = np.random.default_rng(4)
+    trg = rng.random((3000, 3)).astype(np.float32)
+    src = np.clip(0.4 + 0.1 * rng.standard_normal((5000, 3)), -1, 2).astype(np.float32)
+    q = rng.standard_normal(5000).astype(np.float32)
+    r = fmm_run(src, q=q, trg=trg, leaf=30, keep_plan=True)
+    t = T.build_tree(src, trg=trg, leaf_size=30)
+    _compare_tree(r["plan"], t, T.all_lists(t))
+
+
+# ------------------------------------------------------------------ FMM vs direct sum
+def test_fmm_uniform_cube_p6():
+    """The small uniform-cube workload: p = 6, depth-3 uniform tree, single layer."""
+    say("test_fmm_uniform_cube_p6: N=4096")
+    d = W.cube_uniform()
+    r = fmm_run(d["xyz"], q=d["q"], order=6, depth=3, root=d["root"])
+    ref, _ = D.direct_sum(d["xyz"], d["xyz"], d["q"])
+    err = D.rel_l2(r["pot"][0], ref)
+    say(f"  rel L2 = {err:.3e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fmm_adaptive_single_double_layer(precision):
+    say(f"test_fmm_adaptive_single_double_layer: n=20000 s=40 p=6/8 precision={precision}")
+    x, nrm, q, mu = _cloud(20000, 5)
+    ref, _ = D.direct_sum(x, x, q, mu[:, None].astype(np.float64) * nrm)
+    r6 = fmm_run(x, q=q, mu=mu, nrm=nrm, order=6, leaf=40, precision=precision)
+    r8 = fmm_run(x, q=q, mu=mu, nrm=nrm, order=8, leaf=40, precision=precision)
+    e6, e8 = D.rel_l2(r6["pot"][0], ref), D.rel_l2(r8["pot"][0], ref)
+    say(f"  rel L2 p6 = {e6:.3e}  p8 = {e8:.3e}")
+    assert e6 < 3e-5
+    assert e8 < 3e-6
+
+
+def test_fmm_matches_oracle_kifmm_and_its_stages():
+    """Same tree, lists and pseudo-inverse threshold: the GPU float32 result
+    and its check potentials against the oracle's float64 KIFMM."""
+    import paper_1605_01715_amd as F
+
+    say("test_fmm_matches_oracle_kifmm_and_its_stages: n=6000 s=30 p=6")
+    x, nrm, q, mu = _cloud(6000, 6)
+    eps = 1e-8
+    r = fmm_run(x, q=q, mu=mu, nrm=nrm, order=6, leaf=30, pinv_eps=eps, keep_plan=True)
+    t = T.build_tree(x, leaf_size=30)
+    L = T.all_lists(t)
+    pot, _, st = K.kifmm_apply(t, L, K.Operators(6, eps), x, q=q, mu=mu, normals=nrm, return_stages=True)
+    err = D.rel_l2(r["pot"][0], pot)
+    say(f"  GPU vs oracle KIFMM rel L2 = {err:.3e}")
+    assert err < 2e-6
+    up = F.fmm_export_stage(r["plan"], 0)
+    dn = F.fmm_export_stage(r["plan"], 1)
+    has_src = (t.send - t.sbeg) > 0
+    sel = (t.level >= 2) & has_src
+    e_up = D.rel_l2(up[sel], st["u_chk"][sel])
+    sel_d = (t.level >= 2) & ((t.tend - t.tbeg) > 0)
+    e_dn = D.rel_l2(dn[sel_d], st["e_chk"][sel_d])
+    say(f"  upward check potentials rel L2 = {e_up:.3e}, downward = {e_dn:.3e}")
+    assert e_up < 1e-6
+    assert e_dn < 1e-5
+
+
+def test_fmm_separate_targets_stages():
+    """Separate targets and sources: GPU against the oracle's KIFMM, stage by stage."""
+    import paper_1605_01715_amd as F
+
+    say("test_fmm_separate_targets_stages: 4000 targets, 7000 sources, p=8")
+    rng = np.random.default_rng(7)
+    trg = rng.random((4000, 3)).astype(np.float32)
+    src = np.clip(0.5 + 0.2 * rng.standard_normal((7000, 3)), 0, 1).astype(np.float32)
+    q = rng.standard_normal(7000).astype(np.float32)
+    eps = 1e-8
+    r = fmm_run(src, q=q, trg=trg, order=8, leaf=50, pinv_eps=eps, keep_plan=True)
+    t = T.build_tree(src, trg=trg, leaf_size=50)
+    L = T.all_lists(t)
+    pot, _, st = K.kifmm_apply(t, L, K.Operators(8, eps), src, q=q, trg_xyz=trg, return_stages=True)
+    up = F.fmm_export_stage(r["plan"], 0)
+    dn = F.fmm_export_stage(r["plan"], 1)
+    sel = (t.level >= 2) & ((t.send - t.sbeg) > 0)
+    sel_d = (t.level >= 2) & ((t.tend - t.tbeg) > 0)
+    e_up = D.rel_l2(up[sel], st["u_chk"][sel])
+    e_dn = D.rel_l2(dn[sel_d], st["e_chk"][sel_d])
+    e = D.rel_l2(r["pot"][0], pot)
+    # per-box detail of the worst downward boxes
+    nrm = np.linalg.norm(st["e_chk"][sel_d], axis=1) + 1e-300
+    bad = np.argsort(-np.linalg.norm(dn[sel_d] - st["e_chk"][sel_d], axis=1) / nrm)[:5]
+    ids = np.flatnonzero(sel_d)[bad]
+    say(f"  pot {e:.3e}  up {e_up:.3e}  down {e_dn:.3e}")
+    for b in ids:
+        say(f"  box {b} level {t.level[b]} ntrg {t.tend[b]-t.tbeg[b]} nsrc {t.send[b]-t.sbeg[b]} "
+            f"leaf {t.leaf[b]} |V| {len(L['V'][b])} |X| {len(L['X'][b])} rel "
+            f"{np.linalg.norm(dn[b]-st['e_chk'][b])/np.linalg.norm(st['e_chk'][b]):.3e}")
+    assert e_up < 1e-6
+    assert e_dn < 1e-5
+    assert e < 2e-6
+
+
+def test_fmm_separate_targets_and_field():
+    say("test_fmm_separate_targets_and_field: 4000 targets, 7000 sources, field")
+    rng = np.random.default_rng(7)
+    trg = rng.random((4000, 3)).astype(np.float32)
+    src = np.clip(0.5 + 0.2 * rng.standard_normal((7000, 3)), 0, 1).astype(np.float32)
+    q = rng.standard_normal(7000).astype(np.float32)
+    rp = fmm_run(src, q=q, trg=trg, order=8, leaf=50)
+    rf = fmm_run(src, q=q, trg=trg, order=8, leaf=50, field=True)
+    ref_p, ref_f = D.direct_sum(trg, src, q, None, field=True)
+    ep, ef = D.rel_l2(rp["pot"][0], ref_p), D.rel_l2(rf["field"][0], ref_f)
+    say(f"  pot {ep:.3e}  field {ef:.3e}")
+    assert ep < 2e-6
+    assert ef < 2e-5
+
+
+def test_fmm_three_right_hand_sides():
+    say("test_fmm_three_right_hand_sides: n=8000, nrhs=3 double layer")
+    x, nrm, _, _ = _cloud(8000, 8)
+    rng = np.random.default_rng(9)
+    mu = rng.standard_normal((3, 8000)).astype(np.float32)
+    r = fmm_run(x, mu=mu, nrm=nrm, order=6, leaf=40, nrhs=3)
+    for k in range(3):
+        single = fmm_run(x, mu=mu[k], nrm=nrm, order=6, leaf=40)
+        np.testing.assert_allclose(r["pot"][k], single["pot"][0], rtol=0, atol=1e-6 * np.abs(single["pot"]).max())
+
+
+# ------------------------------------------------------------------ edge cases
+def test_edge_cases():
+    say("test_edge_cases")
+    # one point: no interactions
+    r = fmm_run(np.array([[0.3, 0.4, 0.5]], np.float32), q=np.array([2.0], np.float32))
+    assert r["pot"][0, 0] == 0.0
+    # coincident points are excluded from each other; all land in one deepest
+    # leaf. Each cluster sits on a box corner, the worst place for an
+    # expansion, so compare with the oracle's KIFMM of the same order.
+    x = np.full((300, 3), 0.25, np.float32)
+    x[150:] = 0.75
+    q = np.ones(300, np.float32)
+    r = fmm_run(x, q=q, leaf=8, order=4, pinv_eps=1e-8)
+    t = T.build_tree(x, leaf_size=8)
+    ref, _ = K.kifmm_apply(t, T.all_lists(t), K.Operators(4, 1e-8), x, q=q)
+    assert D.rel_l2(r["pot"][0], ref) < 1e-5
+    # ragged: sizes that are not multiples of any tile
+    for n in (2, 63, 65, 1001):
+        xx, nrm, qq, mu = _cloud(n, n)
+        r = fmm_run(xx, q=qq, mu=mu, nrm=nrm, leaf=9, order=6)
+        ref, _ = D.direct_sum(xx, xx, qq, mu[:, None].astype(np.float64) * nrm)
+        assert D.rel_l2(r["pot"][0], ref) < 3e-5, n
+    # points closer than the tolerance radius are excluded
+    x = np.array([[0.5, 0.5, 0.5], [0.5 + 4e-6, 0.5, 0.5], [0.9, 0.1, 0.2]], np.float32)
+    r = fmm_run(x, q=np.array([1.0, 1.0, 1.0], np.float32), leaf=1, order=4)
+    ref, _ = D.direct_sum(x, x, np.ones(3))
+    np.testing.assert_allclose(r["pot"][0], ref, rtol=1e-6)
+
+
+def test_empty_sources_give_zero():
+    import torch
+
+    import paper_1605_01715_amd as F
+    from gpu_common import dev
+
+    say("test_empty_sources_give_zero")
+    trg = dev(np.random.default_rng(0).random((100, 3)).astype(np.float32))
+    src = dev(np.zeros((0, 3), np.float32))
+    plan = F.fmm_setup(src, None, trg, None, options=F.fmm_default_options())
+    pot = torch.full((100,), 7.0, device="cuda:0")
+    F.fmm_apply(plan, q=dev(np.zeros(0, np.float32)), pot=pot)
+    torch.cuda.synchronize()
+    assert torch.all(pot == 0)
+    F.fmm_destroy(plan)
+
+
+def test_nonfinite_coordinates_rejected():
+    import paper_1605_01715_amd as F
+    from gpu_common import dev
+
+    say("test_nonfinite_coordinates_rejected")
+    x = np.random.default_rng(0).random((100, 3)).astype(np.float32)
+    x[17, 1] = np.nan
+    with pytest.raises(F.FmmError) as e:
+        F.fmm_setup(dev(x), options=F.fmm_default_options())
+    assert e.value.code == F.FMM_ERR_ARG
