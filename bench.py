@@ -77,6 +77,8 @@ def roofline(res, precision):
     achieved = flops / (ms * 1e-3) / 1e12
     out = {"kernel": name, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
            "frac": round(achieved / peak, 5), "traffic": None, "algorithmic_flops": flops, "avg_ms": round(ms, 4)}
+    if name == "M2L" and info.get("m2l_columns"):
+        out["m2l_fill"] = round(info["m2l_pairs"] / info["m2l_columns"], 4)
     others = {}
     for k, (f, t, b, p) in cands.items():
         a = f / (t * 1e-3) / 1e12 if t > 0 else 0.0

@@ -170,6 +170,10 @@ typedef struct {
     int64_t m2l_pairs;                   /* M2L box pairs (V-list entries with sources) per rhs */
     int64_t surf_evals;                  /* target x surface-point evaluations (L2P + M2P) per rhs */
     int64_t p2m_evals;                   /* surface-point x source evaluations (P2M + P2L) per rhs */
+    int64_t m2l_columns;                 /* matrix-vector products the M2L kernel computes, padding
+                                            included (m2l_pairs / m2l_columns is its fill) */
+    int64_t rank;                        /* r: singular values of the check-from-equivalent map kept;
+                                            the far-field state of a box is r values per rhs */
     double root[4];                      /* root cube actually used */
     double setup_ms;                     /* wall time of fmm_setup */
 } fmm_info;
@@ -207,10 +211,16 @@ int fmm_unit_surface(int p, double *out, int *ns);
 int fmm_set_timing(fmm_plan plan, int enable);
 
 /*
- * Copy per-box check potentials of the last apply to host memory, rhs 0:
- * which = 0: upward check potentials [n_boxes][n_s];
- * which = 1: downward check potentials after the parent's contribution
- *            [n_boxes][n_s]. Boxes that were not computed hold zeros.
+ * Copy per-box check potentials of the last apply to host memory, rhs 0.
+ * The far field is carried in compressed form (r values per box, see
+ * fmm_info.rank): the upward state is U_r^T u and the downward state V_r^T d,
+ * with K = U S V^T the check-from-equivalent map of the unit box. What is
+ * written is the reconstruction
+ * which = 0: U_r U_r^T u, the upward check potential projected onto the kept
+ *            left singular vectors, [n_boxes][n_s];
+ * which = 1: V_r V_r^T d, the same for the downward check potential after the
+ *            parent's contribution, [n_boxes][n_s].
+ * Boxes that were not computed hold zeros.
  */
 int fmm_export_stage(fmm_plan plan, int which, float *host_out);
 

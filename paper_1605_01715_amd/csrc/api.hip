@@ -102,7 +102,7 @@ int fmm_setup(const float *src_xyz, const float *src_nrm, int64_t n_src, const f
             P.dl = opt->src_kernels & FMM_SRC_DOUBLE;
             P.want_pot = opt->outputs & FMM_OUT_POT;
             P.want_field = opt->outputs & FMM_OUT_FIELD;
-            P.m2l_prec = opt->precision == FMM_PREC_SPLIT_BF16 ? GemmPrec::BF16X6 : GemmPrec::F32;
+            P.m2l_bf16 = opt->precision == FMM_PREC_SPLIT_BF16;
             TreeOptions to;
             to.leaf_size = opt->leaf_size;
             to.uniform_depth = opt->uniform_depth;
@@ -113,14 +113,18 @@ int fmm_setup(const float *src_xyz, const float *src_nrm, int64_t n_src, const f
             P.ops = get_operators(opt->order, eps, s);
             P.ns = P.ops->ns;
             P.n_pad = P.ops->n_pad;
+            P.r = P.ops->r;
+            P.r_pad = P.ops->r_pad;
             const size_t nvec = (size_t)P.t.nb * P.nrhs;
-            P.uchk.alloc(nvec * P.n_pad);
-            P.dchk.alloc(nvec * P.n_pad);
+            P.ut.alloc(nvec * P.r_pad);
+            P.dt.alloc(nvec * P.r_pad);
+            P.chk.alloc(nvec * P.n_pad);
             P.phi_u.alloc(nvec * P.n_pad);
             P.phi_d.alloc(nvec * P.n_pad);
-            if (P.uchk.n) FMM_HIP(hipMemsetAsync(P.uchk.p, 0, P.uchk.bytes(), s));
-            if (P.phi_u.n) FMM_HIP(hipMemsetAsync(P.phi_u.p, 0, P.phi_u.bytes(), s));
-            if (P.phi_d.n) FMM_HIP(hipMemsetAsync(P.phi_d.p, 0, P.phi_d.bytes(), s));
+            // zero once: padding entries are never written, vectors of boxes
+            // a stage skips stay zero
+            for (DBuf<float> *b : {&P.ut, &P.chk, &P.phi_u, &P.phi_d})
+                if (b->n) FMM_HIP(hipMemsetAsync(b->p, 0, b->bytes(), s));
             const size_t nsv = (size_t)P.nrhs * P.t.n_src;
             if (P.sl) P.q_sorted.alloc(nsv);
             if (P.dl) {
@@ -246,6 +250,8 @@ int fmm_plan_info(fmm_plan plan, fmm_info *info) {
         r.m2l_pairs = P.m2l_pairs;
         r.surf_evals = P.surf_evals;
         r.p2m_evals = P.p2m_evals;
+        r.m2l_columns = P.m2l_steps * P.m2l_ncol;
+        r.rank = P.r;
         for (int c = 0; c < 3; ++c) r.root[c] = P.t.x0[c];
         r.root[3] = P.t.w;
         r.setup_ms = P.setup_ms;
@@ -292,13 +298,20 @@ int fmm_export_stage(fmm_plan plan, int which, float *host_out) {
         Plan &P = live(plan);
         FMM_REQUIRE(host_out != nullptr, "fmm_export_stage: out is NULL");
         FMM_REQUIRE(which == 0 || which == 1, "fmm_export_stage: which must be 0 or 1");
-        const DBuf<float> &b = which == 0 ? P.uchk : P.dchk;
+        // reconstruct U_r ut (upward) or V_r dt (downward), [ns][r] host factors
+        const DBuf<float> &b = which == 0 ? P.ut : P.dt;
+        const std::vector<double> &B = which == 0 ? P.ops->U : P.ops->V;
         std::vector<float> all(b.n);
         FMM_HIP(hipDeviceSynchronize());
         d2h(all.data(), b.p, b.n, nullptr);
-        for (int64_t box = 0; box < P.t.nb; ++box)
-            for (int m = 0; m < P.ns; ++m)
-                host_out[box * P.ns + m] = all[((size_t)box * P.nrhs) * P.n_pad + m];
+        for (int64_t box = 0; box < P.t.nb; ++box) {
+            const float *x = &all[((size_t)box * P.nrhs) * P.r_pad];
+            for (int m = 0; m < P.ns; ++m) {
+                double v = 0.0;
+                for (int k = 0; k < P.r; ++k) v += B[(size_t)m * P.r + k] * (double)x[k];
+                host_out[box * P.ns + m] = (float)v;
+            }
+        }
     });
 }
 

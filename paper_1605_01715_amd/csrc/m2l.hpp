@@ -1,0 +1,28 @@
+// M2L translation kernel (V lists) on MFMA.
+#pragma once
+
+#include "common.hpp"
+
+namespace fmm {
+
+// ntile workgroups; tile t owns output vectors tile_cols[t][0..ncol) (-1 = unused)
+// and the active directions term_dir[e] for e in [tile_term_off[t], tile_term_off[t+1]),
+// with source vectors term_src[e][0..ncol) (-1 = none). Vectors are rows of
+// r_pad floats (compressed far-field state); matrices are float32, row-major
+// r_pad x r_pad, one per direction. out += sum over the tile's terms.
+struct M2LLaunch {
+    int r_pad = 0, ntile = 0, ncol = 0;
+    const int64_t *tile_term_off = nullptr;
+    const int32_t *term_dir = nullptr;
+    const int32_t *term_src = nullptr;
+    const int32_t *tile_cols = nullptr;
+    const float *mats = nullptr;
+    const float *in = nullptr;
+    float *out = nullptr;
+};
+
+int m2l_ncol(int r_pad);
+bool m2l_supported(int r_pad);  // any multiple of 32 up to 512
+void m2l_run(bool bf16, const M2LLaunch &a, hipStream_t s);
+
+}  // namespace fmm

@@ -80,8 +80,9 @@ __global__ __launch_bounds__(64) void k_points_to_surface(const int32_t *items, 
             for (int jj = 0; jj < cnt; ++jj) {
                 const float *p = sh + jj * W;
                 const float sx = p[0], sy = p[1], sz = p[2];
+#pragma unroll
                 for (int i = 0; i < TPL; ++i) {
-                    if (i >= ntpl) break;
+                    if (i >= ntpl) continue;  // static index keeps acc in registers
                     float dx = xm[i] - sx, dy = ym[i] - sy, dz = zm[i] - sz;
                     float r2 = dx * dx + dy * dy + dz * dz;
                     float inv = r2 > 0.f ? rsq(r2) : 0.f;
@@ -101,9 +102,10 @@ __global__ __launch_bounds__(64) void k_points_to_surface(const int32_t *items, 
             __syncthreads();
         }
     }
+#pragma unroll
     for (int i = 0; i < TPL; ++i) {
         int m = lane + 64 * i;
-        if (m >= g.ns) break;
+        if (m >= g.ns) continue;
         for (int r = 0; r < NRHS; ++r) {
             float *op = out + ((int64_t)b * NRHS + r) * g.n_pad + m;
             double v = acc[i][r] * (1.0 / kFourPi);

@@ -16,11 +16,13 @@
 // evaluation at the targets).
 #include "operators.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
 
 #include "gemm.hpp"
+#include "m2l.hpp"
 
 namespace fmm {
 
@@ -49,7 +51,8 @@ double default_pinv_eps(int p) {
 // orthogonal; then sigma_k = |w_k|, u_k = w_k / sigma_k, and V accumulates the
 // rotations. Pairs are visited in round-robin order so that each round's
 // rotations touch disjoint columns and run in parallel.
-std::vector<double> pinv_jacobi(const std::vector<double> &K, int n, double eps) {
+void svd_jacobi(const std::vector<double> &K, int n, std::vector<double> &U, std::vector<double> &s,
+                std::vector<double> &Vout) {
     std::vector<double> W((size_t)n * n), V((size_t)n * n, 0.0);  // column-major
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) W[(size_t)j * n + i] = K[(size_t)i * n + j];
@@ -83,42 +86,56 @@ std::vector<double> pinv_jacobi(const std::vector<double> &K, int n, double eps)
                 off = std::max(off, rel);
                 double zeta = (be - al) / (2.0 * ga);
                 double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
-                double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+                double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
                 for (int q = 0; q < n; ++q) {
                     double a = wi[q], b = wj[q];
-                    wi[q] = c * a - s * b;
-                    wj[q] = s * a + c * b;
+                    wi[q] = c * a - sn * b;
+                    wj[q] = sn * a + c * b;
                 }
                 double *vi = &V[(size_t)i * n], *vj = &V[(size_t)j * n];
                 for (int q = 0; q < n; ++q) {
                     double a = vi[q], b = vj[q];
-                    vi[q] = c * a - s * b;
-                    vj[q] = s * a + c * b;
+                    vi[q] = c * a - sn * b;
+                    vj[q] = sn * a + c * b;
                 }
             }
         }
         if (off < 1e-14) break;
     }
     std::vector<double> sig(n);
-    double smax = 0.0;
     for (int k = 0; k < n; ++k) {
         double s2 = 0.0;
         for (int q = 0; q < n; ++q) s2 += W[(size_t)k * n + q] * W[(size_t)k * n + q];
         sig[k] = std::sqrt(s2);
-        smax = std::max(smax, sig[k]);
     }
-    // pinv = sum_k v_k u_k^T / sigma_k = sum_k v_k w_k^T / sigma_k^2
-    std::vector<double> P((size_t)n * n, 0.0);  // row-major
-#pragma omp parallel for schedule(static)
-    for (int i = 0; i < n; ++i) {
-        for (int k = 0; k < n; ++k) {
-            if (!(sig[k] > eps * smax)) continue;
-            double f = V[(size_t)k * n + i] / (sig[k] * sig[k]);
-            const double *wk = &W[(size_t)k * n];
-            double *row = &P[(size_t)i * n];
-            for (int j = 0; j < n; ++j) row[j] += f * wk[j];
+    std::vector<int> ord(n);
+    for (int k = 0; k < n; ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return sig[a] > sig[b]; });
+    U.assign((size_t)n * n, 0.0);
+    Vout.assign((size_t)n * n, 0.0);
+    s.assign(n, 0.0);
+    for (int c = 0; c < n; ++c) {
+        const int k = ord[c];
+        s[c] = sig[k];
+        for (int q = 0; q < n; ++q) {
+            U[(size_t)q * n + c] = sig[k] > 0.0 ? W[(size_t)k * n + q] / sig[k] : 0.0;
+            Vout[(size_t)q * n + c] = V[(size_t)k * n + q];
         }
     }
+}
+
+std::vector<double> pinv_jacobi(const std::vector<double> &K, int n, double eps) {
+    std::vector<double> U, s, V;
+    svd_jacobi(K, n, U, s, V);
+    std::vector<double> P((size_t)n * n, 0.0);
+    const double smax = n ? s[0] : 0.0;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) {
+            if (!(s[k] > eps * smax)) continue;
+            const double f = V[(size_t)i * n + k] / s[k];
+            for (int j = 0; j < n; ++j) P[(size_t)i * n + j] += f * U[(size_t)j * n + k];
+        }
     return P;
 }
 
@@ -131,10 +148,9 @@ std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
     op->Y = unit_surface(p);
     const int n = op->ns = (int)op->Y.size() / 3;
     const int np = op->n_pad = ((n + 31) / 32) * 32;
-    op->mat_elems = (size_t)np * np;
     op->dY = upload(op->Y, s);
 
-    // UC2E = pinv(G(2.95 Y, 1.05 Y)); DC2E = pinv(G(1.05 Y, 2.95 Y)) = UC2E^T
+    // K = G(2.95 Y, 1.05 Y) = U S V^T, truncated at eps * sigma_max
     std::vector<double> K((size_t)n * n);
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
@@ -145,38 +161,57 @@ std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
             }
             K[(size_t)i * n + j] = 1.0 / (kFourPi * std::sqrt(d2));
         }
-    std::vector<double> uc2e = pinv_jacobi(K, n, eps);
-    std::vector<double> dc2e((size_t)n * n);
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) dc2e[(size_t)i * n + j] = uc2e[(size_t)j * n + i];
-    op->uc2e_host = uc2e;
-    DBuf<double> d_uc2e = upload(uc2e, s), d_dc2e = upload(dc2e, s);
+    std::vector<double> Uf, sv, Vf;
+    svd_jacobi(K, n, Uf, sv, Vf);
+    int r = 0;
+    while (r < n && sv[r] > eps * sv[0]) ++r;
+    const int rp = ((r + 31) / 32) * 32;
+    op->r = r;
+    op->r_pad = rp;
+    // host factors: Ur, Vr [n][r]; expansions U S^-1, V S^-1; projections U^T, V^T [r][n]
+    std::vector<double> Ur((size_t)n * r), Vr((size_t)n * r), UrSi((size_t)n * r), VrSi((size_t)n * r);
+    std::vector<double> PU((size_t)r * n), PV((size_t)r * n);
+    for (int q = 0; q < n; ++q)
+        for (int k = 0; k < r; ++k) {
+            Ur[(size_t)q * r + k] = Uf[(size_t)q * n + k];
+            Vr[(size_t)q * r + k] = Vf[(size_t)q * n + k];
+            UrSi[(size_t)q * r + k] = Uf[(size_t)q * n + k] / sv[k];
+            VrSi[(size_t)q * r + k] = Vf[(size_t)q * n + k] / sv[k];
+            PU[(size_t)k * n + q] = Uf[(size_t)q * n + k];
+            PV[(size_t)k * n + q] = Vf[(size_t)q * n + k];
+        }
+    op->U = Ur;
+    op->V = Vr;
+    DBuf<double> dUrSi = upload(UrSi, s), dVrSi = upload(VrSi, s), dPU = upload(PU, s), dPV = upload(PV, s);
+    const size_t rr = (size_t)rp * rp;
+    op->pu_f64.alloc((size_t)rp * np);
+    op->pv_f64.alloc((size_t)rp * np);
+    op->cu_f64.alloc((size_t)np * rp);
+    op->cd_f64.alloc((size_t)np * rp);
+    to_frag_f64(dPU.p, r, n, rp, np, op->pu_f64.p, s);
+    to_frag_f64(dPV.p, r, n, rp, np, op->pv_f64.p, s);
+    to_frag_f64(dVrSi.p, n, r, np, rp, op->cu_f64.p, s);
+    to_frag_f64(dUrSi.p, n, r, np, rp, op->cd_f64.p, s);
 
-    op->uc2e_f64.alloc(op->mat_elems);
-    op->dc2e_f64.alloc(op->mat_elems);
-    to_frag_f64(d_uc2e.p, n, np, op->uc2e_f64.p, s);
-    to_frag_f64(d_dc2e.p, n, np, op->dc2e_f64.p, s);
-
-    // translation matrices: G built on the device, multiplied by the C2E map in float64
-    auto build = [&](const std::vector<double> &prm, const DBuf<double> &c2e, DBuf<float> *f32,
-                     DBuf<uint16_t> *bf, DBuf<double> *f64) {
+    // translations: G (n x n) built on the device, then left(r x n) * G * right(n x r)
+    auto build = [&](const std::vector<double> &prm, const DBuf<double> &left, const DBuf<double> &right,
+                     DBuf<double> *f64, DBuf<float> *rm) {
         const int nb = (int)prm.size() / 9;
-        if (f32) f32->alloc((size_t)nb * op->mat_elems);
-        if (bf) bf->alloc((size_t)nb * 3 * op->mat_elems);
-        if (f64) f64->alloc((size_t)nb * op->mat_elems);
+        if (f64) f64->alloc((size_t)nb * rr);
+        if (rm) rm->alloc((size_t)nb * rr);
         const int chunk = 32;
-        DBuf<double> G((size_t)chunk * n * n), C((size_t)chunk * n * n);
+        DBuf<double> G((size_t)chunk * n * n), X((size_t)chunk * n * r), C((size_t)chunk * r * r);
         for (int b0 = 0; b0 < nb; b0 += chunk) {
             int cnt = std::min(chunk, nb - b0);
             std::vector<double> sub(prm.begin() + 9 * b0, prm.begin() + 9 * (b0 + cnt));
             DBuf<double> dprm = upload(sub, s);
             build_laplace_mats(op->dY.p, n, cnt, dprm.p, G.p, s);
-            dgemm_batched(G.p, c2e.p, C.p, n, cnt, s);
+            dgemm_batched(G.p, (size_t)n * n, right.p, 0, X.p, (size_t)n * r, n, r, n, cnt, s);
+            dgemm_batched(left.p, 0, X.p, (size_t)n * r, C.p, (size_t)r * r, r, r, n, cnt, s);
             for (int b = 0; b < cnt; ++b) {
-                const double *Cb = C.p + (size_t)b * n * n;
-                if (f32) to_frag_f32(Cb, n, np, f32->p + (size_t)(b0 + b) * op->mat_elems, s);
-                if (bf) to_frag_bf16x3(Cb, n, np, bf->p + (size_t)(b0 + b) * 3 * op->mat_elems, s);
-                if (f64) to_frag_f64(Cb, n, np, f64->p + (size_t)(b0 + b) * op->mat_elems, s);
+                const double *Cb = C.p + (size_t)b * r * r;
+                if (f64) to_frag_f64(Cb, r, r, rp, rp, f64->p + (size_t)(b0 + b) * rr, s);
+                if (rm) to_padded_f32(Cb, r, r, rp, rp, rm->p + (size_t)(b0 + b) * rr, s);
             }
             FMM_HIP(hipStreamSynchronize(s));
         }
@@ -196,9 +231,9 @@ std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
             for (int k = -3; k <= 3; ++k)
                 if (std::max(std::abs(i), std::max(std::abs(j), std::abs(k))) >= 2)
                     pm2l.insert(pm2l.end(), {0.0, 0.0, 0.0, kRadIn, 2.0 * i, 2.0 * j, 2.0 * k, kRadIn, 1.0});
-    build(pm2m, d_uc2e, nullptr, nullptr, &op->m2m_f64);
-    build(pl2l, d_dc2e, nullptr, nullptr, &op->l2l_f64);
-    build(pm2l, d_uc2e, &op->m2l_f32, &op->m2l_bf, nullptr);
+    build(pm2m, dPU, dVrSi, &op->m2m_f64, nullptr);
+    build(pl2l, dPV, dUrSi, &op->l2l_f64, nullptr);
+    build(pm2l, dPV, dVrSi, nullptr, &op->m2l_rm);
     FMM_HIP(hipStreamSynchronize(s));
     return op;
 }

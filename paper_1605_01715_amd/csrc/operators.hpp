@@ -7,32 +7,44 @@
 
 namespace fmm {
 
-// All matrices act on check potentials (the well-conditioned quantities) and
-// are built in float64 from the unit-box geometry, then stored in the
-// fragment layouts of gemm.hip:
-//   m2m[o]  = 1/2 G(2.95 Y, s_o/2 + 0.525 Y) UC2E          child check -> parent check
-//   m2l[d]  = G(1.05 Y, 2 d + 1.05 Y) UC2E                  source up-check -> target down-check
-//   l2l[o]  = G(s_o/2 + 0.525 Y, 2.95 Y) DC2E               parent down-check -> child down-check
-//   uc2e, dc2e                                               check -> equivalent density (float64)
-// with UC2E = pinv(G(2.95 Y, 1.05 Y)) and DC2E = pinv(G(1.05 Y, 2.95 Y)) = UC2E^T.
+// Far-field state in compressed coordinates.
+//
+// With K = G(2.95 Y, 1.05 Y) = U S V^T (truncated to the r singular values
+// above eps * sigma_max) the check-to-equivalent maps are
+// UC2E = V S^-1 U^T and DC2E = pinv(K^T) = U S^-1 V^T. Everything the
+// upward pass produces reaches the rest of the method only through U^T, and
+// everything the downward check potential feeds passes through V^T, so the
+// state is kept as r-vectors: ut = U^T u (upward) and dt = V^T d (downward).
+// The translations then are r x r matrices, built in float64 on unit boxes:
+//   m2m[o] = U^T (1/2 G(2.95 Y, s_o/2 + 0.525 Y)) V S^-1       child ut -> parent ut
+//   m2l[d] = V^T G(1.05 Y, 2 d + 1.05 Y) V S^-1                 source ut -> target dt
+//   l2l[o] = V^T G(s_o/2 + 0.525 Y, 2.95 Y) U S^-1              parent dt -> child dt
+// with the projections pu = U^T, pv = V^T (r x n_s) for check potentials
+// computed from points (P2M, P2L) and the expansions cu = V S^-1 and
+// cd = U S^-1 (n_s x r) giving equivalent densities (times the box half-width).
 struct Operators {
-    int p = 0, ns = 0, n_pad = 0;
+    int p = 0, ns = 0, n_pad = 0;  // surface points, padded to 32
+    int r = 0, r_pad = 0;          // kept singular values, padded to 32
     double eps = 0;
-    std::vector<double> Y;  // [ns][3]
+    std::vector<double> Y;         // [ns][3]
     DBuf<double> dY;
-    DBuf<float> m2l_f32;
-    DBuf<double> m2m_f64, l2l_f64;  // M2M and L2L run in float64 (cheap, and they feed every M2L)
-    DBuf<uint16_t> m2l_bf;  // 316 matrices x 3 parts
-    DBuf<double> uc2e_f64, dc2e_f64;
-    size_t mat_elems = 0;   // n_pad * n_pad
-    std::vector<double> uc2e_host;  // [ns][ns] row-major (float64)
+    DBuf<float> m2l_rm;            // [316][r_pad][r_pad] float32 row-major (M2L kernel)
+    DBuf<double> m2m_f64, l2l_f64; // [8] r_pad x r_pad, float64 fragment layout
+    DBuf<double> pu_f64, pv_f64;   // r_pad x n_pad fragment layout
+    DBuf<double> cu_f64, cd_f64;   // n_pad x r_pad fragment layout
+    std::vector<double> U, V;      // host [ns][r] row-major (reconstruction for inspection)
 };
 
 // Unit surface Y(p): boundary nodes of the p^3 grid on [-1,1]^3, lexicographic.
 std::vector<double> unit_surface(int p);
 
-// Truncated-SVD pseudo-inverse (one-sided Jacobi SVD, float64) of an n x n
-// row-major matrix; singular values below eps * sigma_max are dropped.
+// One-sided Jacobi SVD of an n x n row-major matrix: K = U diag(s) V^T with
+// s in descending order. U and V are n x n row-major.
+void svd_jacobi(const std::vector<double> &K, int n, std::vector<double> &U, std::vector<double> &s,
+                std::vector<double> &V);
+
+// Truncated-SVD pseudo-inverse of an n x n row-major matrix; singular values
+// below eps * sigma_max are dropped.
 std::vector<double> pinv_jacobi(const std::vector<double> &K, int n, double eps);
 
 // Cached per (device, p, eps); built on first use.

@@ -1,11 +1,12 @@
 // Work lists and the apply pipeline of one FMM evaluation.
 //
-// Upward pass: P2M at the leaves, M2M level by level towards the root (on
-// check potentials). Far-field translation: M2L over the V lists, P2L over the
-// X lists. Downward pass: L2L level by level towards the leaves, then the
-// check-to-equivalent maps in float64. Evaluation: one fused kernel per leaf
-// adds L2P, M2P (W lists) and the near field (U lists and the direct W/X
-// pairs) and writes the results in the caller's order.
+// Upward pass: P2M at the leaves (check potentials from points, projected
+// onto the compressed basis), M2M level by level towards the root.
+// Far-field translation: M2L over the V lists, P2L over the X lists (again
+// projected). Downward pass: L2L level by level towards the leaves, then the
+// expansions to equivalent densities in float64. Evaluation: one fused kernel
+// per leaf adds L2P, M2P (W lists) and the near field (U lists and the direct
+// W/X pairs) and writes the results in the caller's order.
 //
 // Paper-silent reading: a W or X partner holding at most n_s points is
 // evaluated directly rather than through a surface (this never changes what
@@ -19,26 +20,6 @@ namespace fmm {
 namespace {
 
 constexpr int kBlock = 256;
-
-__global__ void k_m2l_src(const int32_t *cols, int64_t ncolumns, const int32_t *vdense, const int64_t *sbeg,
-                          const int64_t *send, int nrhs, int32_t *src) {
-    // src[tile][d][c] for tile = idx / (316 * 64)
-    int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int64_t ntile = ncolumns / 64;
-    if (idx >= ntile * kNumDirs * 64) return;
-    int c = (int)(idx % 64);
-    int64_t r = idx / 64;
-    int d = (int)(r % kNumDirs);
-    int64_t tile = r / kNumDirs;
-    int32_t v = cols[tile * 64 + c];
-    int32_t out = -1;
-    if (v >= 0) {
-        int32_t box = v / nrhs, rr = v % nrhs;
-        int32_t a = vdense[(int64_t)box * kNumDirs + d];
-        if (a >= 0 && send[a] > sbeg[a]) out = a * nrhs + rr;
-    }
-    src[idx] = out;
-}
 
 __global__ void k_sort_densities(const int64_t *perm, int64_t n, int nrhs, const float *q, const float *mu,
                                  const float *nx, const float *ny, const float *nz, float *qs, float *mx, float *my,
@@ -130,10 +111,14 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         P.p2m_items = upload(items, s);
         P.p2m_roff = upload(roff, s);
         P.p2m_rng = upload(rng, s);
+        GemmJob &j = P.p2m_proj;
+        std::vector<int32_t> cols = tile_columns(items, nrhs, kGemmCols, j.ntile);
+        j.nterm = 1;
+        j.cols = upload(cols, s);
+        j.src = upload(cols, s);
     }
 
-    const int ncol = gemm_ncol(GemmPrec::F32);
-    const int ncol64 = gemm_ncol(GemmPrec::F64);
+    const int ncol64 = kGemmCols;
     // M2M, bottom-up (float64 tiles)
     for (int l = t.nlev - 2; l >= 2; --l) {
         std::vector<int32_t> boxes;
@@ -172,17 +157,56 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
                     if (nsrc(t.V.h_idx[k]) > 0) ++P.m2l_pairs;
             }
         }
-        GemmJob &j = P.m2l;
-        std::vector<int32_t> cols = tile_columns(boxes, nrhs, ncol, j.ntile);
-        j.nterm = kNumDirs;
-        j.cols = upload(cols, s);
-        if (j.ntile > 0) {
-            j.src.alloc((size_t)j.ntile * kNumDirs * ncol);
-            int64_t total = (int64_t)j.ntile * kNumDirs * ncol;
-            hipLaunchKernelGGL(k_m2l_src, dim3(grid_for(total, kBlock)), dim3(kBlock), 0, s, j.cols.p,
-                               (int64_t)j.ntile * ncol, t.vdense.p, t.sbeg.p, t.send.p, nrhs, j.src.p);
-            FMM_HIP(hipGetLastError());
+        FMM_REQUIRE(m2l_supported(P.r_pad), "M2L: unsupported compressed state size");
+        // Tiles of m2l_ncol output vectors, each with its list of active
+        // directions. A box's V-list offsets are fixed by its octant inside
+        // its parent (189 of the 316), so tiles hold one octant only: the
+        // directions a tile runs are then (nearly) the ones every column needs.
+        std::vector<int32_t> vd((size_t)nb * kNumDirs);
+        d2h(vd.data(), t.vdense.p, vd.size(), s);
+        const int nc = m2l_ncol(P.r_pad);
+        int ntile = 0;
+        std::vector<int32_t> cols;
+        for (int o = 0; o < 8; ++o) {
+            std::vector<int32_t> grp;
+            for (int32_t b : boxes) {
+                const int32_t *an = &t.h_anchor[3 * (size_t)b];
+                if ((((an[0] & 1) << 2) | ((an[1] & 1) << 1) | (an[2] & 1)) == o) grp.push_back(b);
+            }
+            int nt = 0;
+            std::vector<int32_t> c = tile_columns(grp, nrhs, nc, nt);
+            cols.insert(cols.end(), c.begin(), c.end());
+            ntile += nt;
         }
+        std::vector<int64_t> toff{0};
+        std::vector<int32_t> tdir, tsrc, colsrc(nc);
+        for (int tl = 0; tl < ntile; ++tl) {
+            for (int d = 0; d < kNumDirs; ++d) {
+                bool any = false;
+                for (int c = 0; c < nc; ++c) {
+                    int32_t v = cols[(size_t)tl * nc + c], sv = -1;
+                    if (v >= 0) {
+                        int32_t a = vd[(size_t)(v / nrhs) * kNumDirs + d];
+                        if (a >= 0 && nsrc(a) > 0) {
+                            sv = a * nrhs + v % nrhs;
+                            any = true;
+                        }
+                    }
+                    colsrc[c] = sv;
+                }
+                if (!any) continue;
+                tdir.push_back(d);
+                tsrc.insert(tsrc.end(), colsrc.begin(), colsrc.end());
+            }
+            toff.push_back((int64_t)tdir.size());
+        }
+        P.m2l_ntile = ntile;
+        P.m2l_steps = (int64_t)tdir.size();
+        P.m2l_ncol = nc;
+        P.m2l_toff = upload(toff, s);
+        P.m2l_dir = upload(tdir, s);
+        P.m2l_src = upload(tsrc, s);
+        P.m2l_cols = upload(cols, s);
     }
 
     // P2L (X lists of boxes holding more than n_s targets)
@@ -205,6 +229,11 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         P.p2l_items = upload(items, s);
         P.p2l_roff = upload(roff, s);
         P.p2l_rng = upload(rng, s);
+        GemmJob &j = P.p2l_proj;
+        std::vector<int32_t> cols = tile_columns(items, nrhs, kGemmCols, j.ntile);
+        j.nterm = 1;
+        j.cols = upload(cols, s);
+        j.src = upload(cols, s);
     }
 
     // L2L, top-down, float64 tiles grouped by octant (one matrix per tile)
@@ -334,23 +363,24 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
     FMM_HIP(hipStreamSynchronize(s));
 }
 
-static void run_gemm(Plan &P, GemmJob &j, GemmPrec prec, const void *mats, const float *in, float *out,
+static void run_gemm(GemmJob &j, const double *mats, int m_pad, int k_pad, const float *in, float *out,
                      const double *scale, bool accumulate, hipStream_t s) {
     if (j.ntile == 0) return;
     GemmLaunch a;
-    a.n_pad = P.n_pad;
+    a.m_pad = m_pad;
+    a.k_pad = k_pad;
     a.ntile = j.ntile;
     a.nterm = j.nterm;
     a.tile_cols = j.cols.p;
     a.term_src = j.src.p;
     a.term_mat = j.use_mat ? j.mat.p : nullptr;
     a.mats = mats;
-    a.mat_elems = P.ops->mat_elems;
+    a.mat_elems = (size_t)m_pad * k_pad;
     a.in = in;
     a.out = out;
     a.col_scale = scale;
     a.accumulate = accumulate ? 1 : 0;
-    box_gemm(prec, a, s);
+    box_gemm_f64(a, s);
 }
 
 void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s) {
@@ -364,7 +394,8 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     hipLaunchKernelGGL(k_sort_densities, dim3(grid_for(t.n_src, kBlock)), dim3(kBlock), 0, s, t.src_perm.p, t.n_src,
                        nrhs, q, mu, t.snx.p, t.sny.p, t.snz.p, P.q_sorted.p, P.mx.p, P.my.p, P.mz.p);
     FMM_HIP(hipGetLastError());
-    if (P.dchk.n) FMM_HIP(hipMemsetAsync(P.dchk.p, 0, P.dchk.bytes(), s));
+    if (P.dt.n) FMM_HIP(hipMemsetAsync(P.dt.p, 0, P.dt.bytes(), s));
+    const int np = P.n_pad, rp = P.r_pad;
 
     PointSrc src;
     src.x = t.sx.p;
@@ -383,23 +414,35 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     g.half = t.half.p;
 
     mark(ST_P2M);
-    points_to_surface(nrhs, sl, dl, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, kRadOut, g, src, P.uchk.p,
+    points_to_surface(nrhs, sl, dl, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, kRadOut, g, src, P.chk.p,
                       false, s);
+    run_gemm(P.p2m_proj, op.pu_f64.p, rp, np, P.chk.p, P.ut.p, nullptr, false, s);
     mark(ST_M2M);
-    for (auto &j : P.m2m_jobs) run_gemm(P, j, GemmPrec::F64, op.m2m_f64.p, P.uchk.p, P.uchk.p, nullptr, false, s);
+    for (auto &j : P.m2m_jobs) run_gemm(j, op.m2m_f64.p, rp, rp, P.ut.p, P.ut.p, nullptr, false, s);
     mark(ST_P2L);
-    points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, kRadIn, g, src, P.dchk.p,
-                      true, s);
+    points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, kRadIn, g, src, P.chk.p,
+                      false, s);
+    run_gemm(P.p2l_proj, op.pv_f64.p, rp, np, P.chk.p, P.dt.p, nullptr, true, s);
     mark(ST_M2L);
-    if (P.m2l_prec == GemmPrec::BF16X6)
-        run_gemm(P, P.m2l, GemmPrec::BF16X6, op.m2l_bf.p, P.uchk.p, P.dchk.p, nullptr, true, s);
-    else
-        run_gemm(P, P.m2l, GemmPrec::F32, op.m2l_f32.p, P.uchk.p, P.dchk.p, nullptr, true, s);
+    {
+        M2LLaunch m;
+        m.r_pad = rp;
+        m.ntile = P.m2l_ntile;
+        m.ncol = P.m2l_ncol;
+        m.tile_term_off = P.m2l_toff.p;
+        m.term_dir = P.m2l_dir.p;
+        m.term_src = P.m2l_src.p;
+        m.tile_cols = P.m2l_cols.p;
+        m.mats = op.m2l_rm.p;
+        m.in = P.ut.p;
+        m.out = P.dt.p;
+        m2l_run(P.m2l_bf16, m, s);
+    }
     mark(ST_L2L);
-    for (auto &j : P.l2l_jobs) run_gemm(P, j, GemmPrec::F64, op.l2l_f64.p, P.dchk.p, P.dchk.p, nullptr, true, s);
+    for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, rp, rp, P.dt.p, P.dt.p, nullptr, true, s);
     mark(ST_C2E);
-    run_gemm(P, P.c2e_down, GemmPrec::F64, op.dc2e_f64.p, P.dchk.p, P.phi_d.p, P.col_scale.p, false, s);
-    run_gemm(P, P.c2e_up, GemmPrec::F64, op.uc2e_f64.p, P.uchk.p, P.phi_u.p, P.col_scale.p, false, s);
+    run_gemm(P.c2e_down, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_scale.p, false, s);
+    run_gemm(P.c2e_up, op.cu_f64.p, np, rp, P.ut.p, P.phi_u.p, P.col_scale.p, false, s);
     mark(ST_EVAL);
     EvalArgs e;
     e.wleaf = P.wleaf.p;

@@ -4,6 +4,7 @@
 #include <memory>
 
 #include "gemm.hpp"
+#include "m2l.hpp"
 #include "nbody.hpp"
 #include "operators.hpp"
 #include "tree.hpp"
@@ -25,10 +26,12 @@ struct Plan {
     bool alive = true;
     Tree t;
     std::shared_ptr<const Operators> ops;
-    int ns = 0, n_pad = 0;
-    GemmPrec m2l_prec = GemmPrec::F32;
+    int ns = 0, n_pad = 0, r = 0, r_pad = 0;
+    bool m2l_bf16 = false;
 
-    DBuf<float> uchk, dchk, phi_u, phi_d;   // [nb * nrhs][n_pad]
+    DBuf<float> ut, dt;                     // [nb * nrhs][r_pad] compressed upward / downward state
+    DBuf<float> chk;                        // [nb * nrhs][n_pad] check potentials made from points
+    DBuf<float> phi_u, phi_d;               // [nb * nrhs][n_pad] equivalent densities
     DBuf<float> q_sorted, mx, my, mz;       // [nrhs][n_src]
     DBuf<double> col_scale;                 // half-width per vector index
     DBuf<float> trg_nrm_user;               // [n_trg][3] target normals, caller's order
@@ -37,9 +40,15 @@ struct Plan {
     int n_p2m = 0;
     DBuf<int32_t> p2l_items, p2l_roff, p2l_rng;
     int n_p2l = 0;
+    GemmJob p2m_proj, p2l_proj;     // check potentials -> compressed state
     std::vector<GemmJob> m2m_jobs;  // bottom-up
     std::vector<GemmJob> l2l_jobs;  // top-down
-    GemmJob m2l, c2e_down, c2e_up;
+    GemmJob c2e_down, c2e_up;
+    // M2L: tiles with their active directions
+    int m2l_ntile = 0, m2l_ncol = 0;
+    int64_t m2l_steps = 0;  // (tile, direction) products the dedicated kernel runs
+    DBuf<int64_t> m2l_toff;
+    DBuf<int32_t> m2l_dir, m2l_src, m2l_cols;
 
     DBuf<int32_t> wleaf, wt0, soff, sbox, poff, prng;
     DBuf<int8_t> skind;
