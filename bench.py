@@ -22,7 +22,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FMM matvec Mpoints/s at 1e-6 rel err: split-BF16 MFMA M2L vs plain FP32"
-PEAK_TFLOPS = {"bf16": 2500.0, "fp32_mfma": 157.3, "fp32_valu": 157.3, "fp64": 78.6}
+# MI355X published dense peaks. The float32 vector peak counts packed FP32
+# (two FMAs per lane per cycle); with packed FP32 disabled, as this library
+# builds, one FMA per lane per cycle gives 256 CU x 64 lanes x 2 x 2.4 GHz.
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32_mfma": 157.3, "fp32_valu": 157.3, "fp32_valu_unpacked": 78.6, "fp64": 78.6}
 FLOPS_PER_PAIR = {"sl": 11, "dl": 13, "sl+dl": 16, "sl+field": 20}
 
 
@@ -61,10 +64,33 @@ def run_form(F, torch, x, nrm, q, mu, precision, order, leaf, steps, warmup):
     return {"ms": ms, "setup_s": setup_s, "info": info, "stages": stages, "pot": pot}
 
 
-def roofline(res, precision):
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_clustered4m_p8_s128.md")
+
+
+def measured_traffic(kernel, precision, args):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the summary is for another workload, form or kernel source."""
+    if (args.n, args.order, args.leaf) != (4_000_000, 8, 128) or precision != 1:
+        return None
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+        data = json.loads(txt[txt.index("```json") + 7:txt.rindex("```")])
+        ent = data[kernel]
+        if "source" in ent:
+            import hashlib
+            src = open(os.path.join(ROOT, ent["source"]), "rb").read()
+            if hashlib.sha256(src).hexdigest() != ent["source_sha256"]:
+                return None
+        return ent["hbm_bytes"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def roofline(res, precision, args):
     info, st = res["info"], res["stages"]
-    ns = info["n_surface"]
-    m2l_flops = 2.0 * ns * ns * info["m2l_pairs"]
+    ns, r = info["n_surface"], info["rank"]
+    # M2L acts on the compressed state: one r x r product per V pair
+    m2l_flops = 2.0 * r * r * info["m2l_pairs"]
     eval_flops = FLOPS_PER_PAIR["sl+dl"] * info["p2p_pairs"] + FLOPS_PER_PAIR["sl"] * info["surf_evals"]
     p2m_flops = FLOPS_PER_PAIR["sl+dl"] * info["p2m_evals"]
     cands = {
@@ -76,9 +102,21 @@ def roofline(res, precision):
     flops, ms, bound, peak = cands[name]
     achieved = flops / (ms * 1e-3) / 1e12
     out = {"kernel": name, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-           "frac": round(achieved / peak, 5), "traffic": None, "algorithmic_flops": flops, "avg_ms": round(ms, 4)}
-    if name == "M2L" and info.get("m2l_columns"):
-        out["m2l_fill"] = round(info["m2l_pairs"] / info["m2l_columns"], 4)
+           "frac": round(achieved / peak, 5), "traffic": measured_traffic(name, precision, args),
+           "algorithmic_flops": flops, "avg_ms": round(ms, 4)}
+    if name == "M2L":
+        out["rank"] = r
+        out["dense_equivalent_flops"] = 2.0 * ns * ns * info["m2l_pairs"]
+        if info.get("m2l_columns"):
+            out["m2l_fill"] = round(info["m2l_pairs"] / info["m2l_columns"], 4)
+            # MFMA work issued: padded r x r products over every column of every active step,
+            # times 6 bf16 products per float32 product in the split form
+            rp = (r + 31) // 32 * 32
+            issued = 2.0 * rp * rp * info["m2l_columns"] * (6 if precision == 1 else 1)
+            out["mfma_issued_tflops"] = round(issued / (ms * 1e-3) / 1e12, 3)
+            out["mfma_issued_frac"] = round(issued / (ms * 1e-3) / 1e12 / peak, 5)
+    if bound == "alu":
+        out["frac_unpacked"] = round(achieved / PEAK_TFLOPS["fp32_valu_unpacked"], 5)
     others = {}
     for k, (f, t, b, p) in cands.items():
         a = f / (t * 1e-3) / 1e12 if t > 0 else 0.0
@@ -95,9 +133,11 @@ def main():
     ap.add_argument("--n", type=int, default=4_000_000)
     ap.add_argument("--order", type=int, default=8)
     ap.add_argument("--leaf", type=int, default=128)
-    ap.add_argument("--sample", type=int, default=4000, help="targets checked against the float64 direct sum")
+    ap.add_argument("--sample", type=int, default=10000, help="targets checked against the float64 direct sum")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain float32 form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle (error and baseline)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -113,6 +153,15 @@ def main():
     if not os.path.exists(F.library_path()):
         raise SystemExit("the HIP library is not built; run: python __graft_entry__.py")
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}), flush=True)
+        return
     log(f"bench: generating clustered workload n={args.n}")
     d = W.clustered(args.n)
     x = torch.from_numpy(d["xyz"]).to(dev)
@@ -146,7 +195,7 @@ def main():
         if ref is not None:
             got = r["pot"].cpu().numpy()[sample].astype(np.float64)
             r["err"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-        r["roofline"], r["kernels"] = roofline(r, prec)
+        r["roofline"], r["kernels"] = roofline(r, prec, args)
         results[name] = r
         log(f"bench: form {name}: {r['ms']:.3f} ms/step, setup {r['setup_s']:.2f} s, err {r.get('err')}, "
             f"stages {json.dumps({k: round(v, 3) for k, v in r['stages'].items()})}")
