@@ -6,7 +6,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfmm_mi355x.so")
+# FMM_MI355X_LIB selects another build of the same library (for testing builds)
+LIB_PATH = os.environ.get("FMM_MI355X_LIB") or os.path.join(HERE, "libfmm_mi355x.so")
 
 c_int, c_int64, c_float, c_double, c_void_p = (ctypes.c_int, ctypes.c_int64, ctypes.c_float, ctypes.c_double,
                                                ctypes.c_void_p)

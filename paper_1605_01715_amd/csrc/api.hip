@@ -119,6 +119,7 @@ int fmm_setup(const float *src_xyz, const float *src_nrm, int64_t n_src, const f
             P.ut.alloc(nvec * P.r_pad);
             P.dt.alloc(nvec * P.r_pad);
             P.chk.alloc(nvec * P.n_pad);
+            if (P.m2l_bf16) P.ut_bf.alloc(m2l_split_vecs_elems(P.r_pad, (int64_t)nvec));
             P.phi_u.alloc(nvec * P.n_pad);
             P.phi_d.alloc(nvec * P.n_pad);
             // zero once: padding entries are never written, vectors of boxes

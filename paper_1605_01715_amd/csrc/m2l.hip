@@ -10,24 +10,31 @@
 //
 // Blocking. A workgroup (8 waves) owns a tile of 128 target boxes of one
 // octant; each wave takes one 32-column block and one half of the rows, and
-// the workgroup keeps the r_pad x 128
-// accumulator in registers across all directions, so every output is written
-// once. Each step of the tile is one (direction, 32-wide k-chunk): the 32
-// columns of M_d for that chunk are loaded once per workgroup as float32,
-// split into the operand format and staged in LDS (double-buffered when it
-// fits), and the waves multiply them against their own 32 source columns,
-// which each lane loads straight from HBM into registers. With
-// 32x32 MFMA tiles each staged matrix element is read from LDS once per 32
-// columns. The next step's loads are issued before the current step's MFMAs.
-// Tiles are ordered so that consecutive tiles run on the same XCD and share
-// its L2 for the gathered source vectors.
+// the workgroup keeps the r_pad x 128 accumulator in registers across all
+// directions, so every output is written once. Each step of the tile is one
+// (direction, 32-wide k-chunk): the 32 columns of M_d for that chunk are
+// loaded once per workgroup and staged in LDS (double-buffered when it fits),
+// and the waves multiply them against their own 32 source columns, which each
+// lane loads straight from memory into registers. With 32x32 MFMA tiles each
+// staged matrix element is read from LDS once per 32 columns. The next step's
+// loads are issued before the current step's MFMAs. Tiles are ordered so that
+// consecutive tiles run on the same XCD and share its L2 for the gathered
+// source vectors.
 //
 // The k index inside a chunk is permuted so that every lane's operand is a
 // run of consecutive values (16-byte loads); the dot product is the same.
 //
-// Forms: FP32 (v_mfma_f32_32x32x2_f32) and split-BF16 (both operands split
-// into three bfloat16 parts, six products hh hm mh mm hl lh accumulated in
-// float32 with v_mfma_f32_32x32x16_bf16).
+// Forms:
+//   FP32        v_mfma_f32_32x32x2_f32; the float32 matrix chunk is
+//               rearranged into fragment order on its way to LDS.
+//   split-BF16  both operands split into three bfloat16 parts x = h + m + l;
+//               the six products hh hm mh mm hl lh are accumulated in float32
+//               with v_mfma_f32_32x32x16_bf16 (the bf16x6 scheme of Henry,
+//               Tang and Heinecke, 2019). The split is done once, outside the
+//               inner loop: the matrices when the operators are built (stored
+//               chunk by chunk in the exact LDS image), the source vectors by
+//               one pass over the upward state per apply. The inner loop is
+//               then only copies and MFMAs.
 #include "m2l.hpp"
 
 namespace fmm {
@@ -35,21 +42,23 @@ namespace fmm {
 namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));  // plain vector: promotable to registers
+typedef float f32x4 __attribute__((ext_vector_type(4)));  // plain vectors: promotable to registers
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
-typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 512;  // 8 waves: 4 column blocks of 32 x 2 row halves
 constexpr int kCols = 128;
 constexpr int KC = 32;         // k per step
 
+// float32 -> bfloat16, round to nearest even (finite inputs)
 __device__ inline uint16_t f2bf(float x) {
     uint32_t u = __float_as_uint(x);
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// x = h + m + l up to 2^-24 |x| (each residual is exact in float32)
 __device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
     h = f2bf(x);
     float r1 = x - bf2f(h);
@@ -57,169 +66,219 @@ __device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
     l = f2bf(r1 - bf2f(m));
 }
 
-// LDS bytes of one staged A chunk (r_pad rows x 32 k)
+// One staged A chunk (r_pad rows x 32 k) in LDS, fragment order:
+//   BF16 (32x32x16): part p, row block rb, k-half h (16 k each), lane, 8 slots;
+//                    element (row, k) -> lane = row % 32 + 32 * ((k % 16) / 8), slot = k % 8
+//   FP32 (32x32x2):  row block rb, lane, 16 slots;
+//                    element (row, k) -> lane = row % 32 + 32 * (k / 16), slot = k % 16
 template <int NRB, bool BF16>
 constexpr int a_chunk_bytes() {
     return BF16 ? NRB * 32 * KC * 2 * 3 : NRB * 32 * KC * 4;
 }
 
-// A chunk in LDS, fragment order:
-//   BF16 (32x32x16): part p, row block rb, k-half h (16 k each), lane, 8 slots;
-//                    element (row, k) -> lane = row % 32 + 32 * ((k % 16) / 8), slot = k % 8
-//   FP32 (32x32x2):  row block rb, lane, 16 slots;
-//                    element (row, k) -> lane = row % 32 + 32 * (k / 16), slot = k % 16
+// Split-BF16 source vector layout: per vector, per 32-k chunk, 3 parts of 32
+// bfloat16 (192 bytes, so one lane's three parts of a run share cache lines).
+__host__ __device__ constexpr int64_t vec_bf_stride(int r_pad) { return 3 * (int64_t)r_pad; }
+
+// XCD-aware tile order: blocks are dealt to the 8 XCDs round-robin, so
+// block b runs on XCD b % 8. Each XCD gets a contiguous range of tiles
+// (neighbouring target boxes share source vectors in that XCD's L2).
+// XCD x receives cnt(x) blocks and owns tiles [start(x), start(x) + cnt(x)),
+// a bijection of [0, ntile). Returns -1 for blocks beyond it.
+__device__ inline int xcd_tile(int nb, int b) {
+    const int per = (nb + 7) / 8;
+    const int rem = nb - (per - 1) * 8;
+    const int x = b % 8, k = b / 8;
+    const int cnt = (x < rem) ? per : per - 1;
+    const int start = (x < rem) ? x * per : rem * per + (x - rem) * (per - 1);
+    return k < cnt ? start + k : -1;
+}
+
 template <int NRB, bool BF16, int NBUF>
 __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
-    constexpr int NF4 = NRB * 32 * KC / 4;                   // float4 per chunk
-    constexpr int NLOAD = (NF4 + kThreads - 1) / kThreads;   // float4 per thread per chunk
+    constexpr int RP = NRB * 32;
+    constexpr int NF4 = a_chunk_bytes<NRB, BF16>() / 16;     // 16-byte units per chunk
+    constexpr int NLOAD = (NF4 + kThreads - 1) / kThreads;   // per thread per chunk
     constexpr int PART = NRB * 2 * 64 * 8;                   // bf16 elements of one part
     constexpr int RBH = (NRB + 1) / 2;                       // row blocks per row half
+    constexpr int nkc = RP / KC;
+    constexpr int NB = BF16 ? 6 : 4;                         // 16-byte B registers per lane
     extern __shared__ __align__(16) unsigned char lds[];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);    // wave-uniform: scalar branches
     const int hf = lane >> 5, r32 = lane & 31;
     const int cblk = w & 3, rhalf = w >> 2;                  // wave -> (column block, row half)
     const int rb0 = rhalf * RBH;
     const int nrb = (rb0 + RBH <= NRB) ? RBH : NRB - rb0;    // row blocks of this wave
 
-    // XCD-aware tile order: blocks are dealt to the 8 XCDs round-robin, so
-    // block b runs on XCD b % 8. Each XCD gets a contiguous range of tiles
-    // (neighbouring target boxes share source vectors in that XCD's L2).
-    // XCD x receives cnt(x) blocks and owns tiles [start(x), start(x) + cnt(x)),
-    // a bijection of [0, ntile).
-    int tile;
-    {
-        const int nb = gridDim.x, b = blockIdx.x;
-        const int per = (nb + 7) / 8;
-        const int rem = nb - (per - 1) * 8;
-        const int x = b % 8, k = b / 8;
-        const int cnt = (x < rem) ? per : per - 1;
-        const int start = (x < rem) ? x * per : rem * per + (x - rem) * (per - 1);
-        if (k >= cnt) return;
-        tile = start + k;
-    }
+    const int tile = xcd_tile(gridDim.x, blockIdx.x);
+    if (tile < 0) return;
     const int64_t toff = a.tile_term_off[tile];
     const int nact = (int)(a.tile_term_off[tile + 1] - toff);
-    constexpr int nkc = (NRB * 32) / KC;
     const int nsteps = nact * nkc;
     const int my_col = 32 * cblk + r32;
     const int outv = a.tile_cols[(int64_t)tile * kCols + my_col];
+    // the tile's directions, in LDS for the whole tile
+    __shared__ int32_t s_dir[kNumDirs];
+    for (int i = t; i < nact; i += kThreads) s_dir[i] = a.term_dir[toff + i];
+    // Two load streams run ahead of the MFMAs: A (the matrix chunks) one
+    // step ahead, B (this lane's source column) two steps ahead. B tracks its
+    // direction's source index and fetches the next direction's one step
+    // after a direction starts, when the previous one is no longer live (so
+    // its register is reused and nothing waits for that load until it is used).
+    int a_e = 0, a_kc = 0;                   // step the A stream loads next
+    int b_e = 0, b_kc = 0;                   // step the B stream loads next
+    int cur_sv = -1, nxt_sv = -1;
+    if (nact > 0) {
+        cur_sv = a.term_src[toff * kCols + my_col];
+        nxt_sv = a.term_src[(toff + min(1, nact - 1)) * kCols + my_col];
+    }
+    __syncthreads();  // s_dir
 
     f32x16 acc[RBH];
 #pragma unroll
     for (int i = 0; i < RBH; ++i)
         for (int v = 0; v < 16; ++v) acc[i][v] = 0.f;
 
-    f32x4 areg[NLOAD];
-    f32x4 breg[4];
-    bool bnext_live = false;
+    // Register sets: the A chunk of the next step in 16-byte units (stored to
+    // LDS at the end of the step that loaded it), and three B operand sets
+    // (BF16: [k-half][part] runs of 8; FP32: 16 floats) with their zero masks,
+    // rotating with the step (the step loop is unrolled three times, so no
+    // copy crosses the loop edge): B is loaded two steps ahead of its MFMAs.
+    u32x4 a0[NLOAD];
+    u32x4 b0[NB], b1[NB], b2[NB];
+    uint32_t keep0 = 0, keep1 = 0, keep2 = 0;
+    bool live0 = false, live1 = false, live2 = false;
 
-    auto load_step = [&](int s) {
-        const int e = s / nkc, kc = s % nkc;
-        const int dir = a.term_dir[toff + e];
-        const float *M = a.mats + (size_t)dir * (NRB * 32) * (NRB * 32);
-        // every areg[j] is written unconditionally (a clamped index on the
+    auto load_a = [&](u32x4 (&ar)[NLOAD]) {
+        const int dir = __builtin_amdgcn_readfirstlane(s_dir[min(a_e, nact - 1)]);
+        const int kc = a_kc;
+        // every ar[j] is written unconditionally (a clamped index on the
         // ragged last pass; store_a drops it) so the array stays in registers
 #pragma unroll
         for (int j = 0; j < NLOAD; ++j) {
-            const int f = min(t + kThreads * j, NF4 - 1);  // float4 index within the chunk
-            const int row = f >> 3, k4 = (f & 7) * 4;
-            areg[j] = *(const f32x4 *)(M + (size_t)row * (NRB * 32) + kc * KC + k4);
-        }
-        const int sv = a.term_src[(toff + e) * kCols + my_col];
-        if (sv >= 0) {
-            const float *p = a.in + (size_t)sv * (NRB * 32) + kc * KC;
-            if (BF16) {  // k = 16 h2 + 8 hf + v for the two 16-k halves
-                breg[0] = *(const f32x4 *)(p + 8 * hf);
-                breg[1] = *(const f32x4 *)(p + 8 * hf + 4);
-                breg[2] = *(const f32x4 *)(p + 16 + 8 * hf);
-                breg[3] = *(const f32x4 *)(p + 16 + 8 * hf + 4);
-            } else {     // k = 16 hf + q
-                for (int q = 0; q < 4; ++q) breg[q] = *(const f32x4 *)(p + 16 * hf + 4 * q);
+            const int f = min(t + kThreads * j, NF4 - 1);
+            if (BF16) {
+                ar[j] = ((const u32x4 *)(a.mats_bf + ((int64_t)dir * nkc + kc) * 3 * PART))[f];
+            } else {
+                const int row = f >> 3, k4 = (f & 7) * 4;
+                ar[j] = *(const u32x4 *)(a.mats + ((size_t)dir * RP + row) * RP + kc * KC + k4);
             }
-        } else {
-            for (int q = 0; q < 4; ++q) breg[q] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
-        bnext_live = __ballot(sv >= 0) != 0;  // wave-uniform: some column of this wave has a source
+        if (++a_kc == nkc) {
+            a_kc = 0;
+            ++a_e;
+        }
     };
-    auto store_a = [&](int buf) {
+    auto load_b = [&](u32x4 (&bn)[NB], uint32_t &keep, bool &live) {
+        const int kc = b_kc, sv = cur_sv;
+        // unconditional loads (vector 0 stands in for a missing source and is
+        // masked to zero when consumed) keep the wait counts static
+        const int svl = max(sv, 0);
+        keep = sv >= 0 ? 0xffffffffu : 0u;
+        if (BF16) {  // k = 16 h2 + 8 hf + v in each of the two 16-k halves
+            const uint16_t *p = a.in_bf + svl * vec_bf_stride(RP) + kc * 3 * KC;
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) bn[3 * h2 + q] = *(const u32x4 *)(p + q * KC + 16 * h2 + 8 * hf);
+        } else {     // k = 16 hf + q
+            const float *p = a.in + (size_t)svl * RP + kc * KC;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bn[q] = *(const u32x4 *)(p + 16 * hf + 4 * q);
+        }
+        live = __ballot(sv >= 0) != 0;  // wave-uniform: some column of this wave has a source
+        if (++b_kc == nkc) {
+            b_kc = 0;
+            ++b_e;
+            cur_sv = nxt_sv;
+            if (nkc == 1) nxt_sv = a.term_src[(toff + min(b_e + 1, nact - 1)) * kCols + my_col];
+        } else if (b_kc == 1) {
+            nxt_sv = a.term_src[(toff + min(b_e + 1, nact - 1)) * kCols + my_col];
+        }
+    };
+    auto store_a = [&](const u32x4 (&ar)[NLOAD], int buf) {
         unsigned char *base = lds + buf * a_chunk_bytes<NRB, BF16>();
 #pragma unroll
         for (int j = 0; j < NLOAD; ++j) {
             const int f = t + kThreads * j;
             if (NF4 % kThreads != 0 && f >= NF4) continue;
-            const int row = f >> 3, k4 = (f & 7) * 4;
-            const int rb = row >> 5;
             if (BF16) {
-                const int h2 = k4 >> 4, fl = (row & 31) + 32 * ((k4 & 15) >> 3), slot = k4 & 7;
-                const float v[4] = {areg[j].x, areg[j].y, areg[j].z, areg[j].w};
-                u16x4 hh, mm, ll;
-                for (int q = 0; q < 4; ++q) {
-                    uint16_t x0, x1, x2;
-                    split3(v[q], x0, x1, x2);
-                    hh[q] = x0;
-                    mm[q] = x1;
-                    ll[q] = x2;
-                }
-                uint16_t *p = (uint16_t *)base;
-                const int off = ((rb * 2 + h2) * 64 + fl) * 8 + slot;
-                *(u16x4 *)(p + off) = hh;
-                *(u16x4 *)(p + PART + off) = mm;
-                *(u16x4 *)(p + 2 * PART + off) = ll;
+                ((u32x4 *)base)[f] = ar[j];  // the chunk is stored in its LDS image
             } else {
+                const int row = f >> 3, k4 = (f & 7) * 4;
+                const int rb = row >> 5;
                 const int fl = (row & 31) + 32 * (k4 >> 4), slot = k4 & 15;
-                *(f32x4 *)((float *)base + (rb * 64 + fl) * 16 + slot) = areg[j];
+                *(u32x4 *)((float *)base + (rb * 64 + fl) * 16 + slot) = ar[j];
             }
         }
     };
-
-    if (nsteps > 0) {
-        load_step(0);
-        store_a(0);
-    }
-    for (int s = 0; s < nsteps; ++s) {
+    // One step s: A(s) is in LDS buffer s % 2, B(s) in bc. Issues A(s+1) into
+    // registers and B(s+2) into bn, runs the MFMAs of step s, then stores
+    // A(s+1) to the other LDS buffer.
+    auto step = [&](int s, const u32x4 (&bc)[NB], uint32_t keep, bool live, u32x4 (&bn)[NB], uint32_t &keep_n,
+                    bool &live_n) {
         const int buf = NBUF == 2 ? (s & 1) : 0;
-        const bool live = bnext_live;
-        // consume this step's B registers before the prefetch overwrites them
-        bf16x8 bh[2], bm[2], bl[2];
-        float bv[16];
-        {
-            const float v[16] = {breg[0].x, breg[0].y, breg[0].z, breg[0].w, breg[1].x, breg[1].y,
-                                 breg[1].z, breg[1].w, breg[2].x, breg[2].y, breg[2].z, breg[2].w,
-                                 breg[3].x, breg[3].y, breg[3].z, breg[3].w};
-            if (BF16) {
-                for (int h2 = 0; h2 < 2; ++h2) {
-                    u16x8 x0, x1, x2;
-                    for (int q = 0; q < 8; ++q) {
-                        uint16_t a0, a1, a2;
-                        split3(v[8 * h2 + q], a0, a1, a2);
-                        x0[q] = a0;
-                        x1[q] = a1;
-                        x2[q] = a2;
-                    }
-                    bh[h2] = __builtin_bit_cast(bf16x8, x0);
-                    bm[h2] = __builtin_bit_cast(bf16x8, x1);
-                    bl[h2] = __builtin_bit_cast(bf16x8, x2);
-                }
-            } else {
-                for (int q = 0; q < 16; ++q) bv[q] = v[q];
-            }
-        }
-        __syncthreads();  // A(s) visible in LDS
-        if (s + 1 < nsteps) load_step(s + 1);
+        __syncthreads();  // A(s) visible in LDS; every wave is done with the other buffer
+        if (s + 1 < nsteps) load_a(a0);
+        if (s + 2 < nsteps) load_b(bn, keep_n, live_n);
         const unsigned char *base = lds + buf * a_chunk_bytes<NRB, BF16>();
         if (live) {
             if (BF16) {
                 const uint16_t *p = (const uint16_t *)base;
+                bf16x8 bh[2], bm[2], bl[2];
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    bh[h2] = __builtin_bit_cast(bf16x8, bc[3 * h2] & keep);
+                    bm[h2] = __builtin_bit_cast(bf16x8, bc[3 * h2 + 1] & keep);
+                    bl[h2] = __builtin_bit_cast(bf16x8, bc[3 * h2 + 2] & keep);
+                }
+#ifdef M2L_INTERLEAVE
+                // the row blocks' accumulation chains interleaved: consecutive
+                // MFMAs are independent
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    bf16x8 ah[RBH], am[RBH], al[RBH];
+#pragma unroll
+                    for (int i = 0; i < RBH; ++i) {
+                        if (i >= nrb) continue;
+                        const int off = (((rb0 + i) * 2 + h2) * 64 + lane) * 8;
+                        ah[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + off));
+                        am[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + PART + off));
+                        al[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + 2 * PART + off));
+                    }
+#pragma unroll
+                    for (int i = 0; i < RBH; ++i)
+                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[h2], acc[i], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < RBH; ++i)
+                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[h2], acc[i], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < RBH; ++i)
+                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[i], bm[h2], acc[i], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < RBH; ++i)
+                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[i], bh[h2], acc[i], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < RBH; ++i)
+                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bm[h2], acc[i], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < RBH; ++i)
+                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[h2], acc[i], 0, 0, 0);
+                }
+#else
 #pragma unroll
                 for (int i = 0; i < RBH; ++i) {
                     if (i >= nrb) continue;  // static index i keeps acc in registers
                     const int rb = rb0 + i;
                     f32x16 c = acc[i];
+#pragma unroll
                     for (int h2 = 0; h2 < 2; ++h2) {
                         const int off = ((rb * 2 + h2) * 64 + lane) * 8;
                         const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + off));
                         const bf16x8 am = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + PART + off));
                         const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + 2 * PART + off));
+                        // smallest products first
                         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[h2], c, 0, 0, 0);
                         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[h2], c, 0, 0, 0);
                         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm[h2], c, 0, 0, 0);
@@ -229,26 +288,42 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
                     }
                     acc[i] = c;
                 }
+#endif
             } else {
                 const float *p = (const float *)base;
+                f32x4 bv4[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) bv4[q] = __builtin_bit_cast(f32x4, bc[q] & keep);
 #pragma unroll
                 for (int i = 0; i < RBH; ++i) {
                     if (i >= nrb) continue;
                     const int rb = rb0 + i;
-                    const f32x4 *ap = (const f32x4 *)(p + (rb * 64 + lane) * 16);
-                    const f32x4 a0 = ap[0], a1 = ap[1], a2 = ap[2], a3 = ap[3];
-                    const float av[16] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
-                                          a2.x, a2.y, a2.z, a2.w, a3.x, a3.y, a3.z, a3.w};
+                    const f32x4 *ap4 = (const f32x4 *)(p + (rb * 64 + lane) * 16);
+                    const f32x4 av4[4] = {ap4[0], ap4[1], ap4[2], ap4[3]};
                     f32x16 c = acc[i];
-                    for (int q = 0; q < 16; ++q) c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bv[q], c, 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < 16; ++q)
+                        c = __builtin_amdgcn_mfma_f32_32x32x2f32(av4[q >> 2][q & 3], bv4[q >> 2][q & 3], c, 0, 0, 0);
                     acc[i] = c;
                 }
             }
         }
         if (s + 1 < nsteps) {
             if (NBUF == 1) __syncthreads();  // every wave is done with the single buffer
-            store_a(NBUF == 2 ? ((s + 1) & 1) : 0);
+            store_a(a0, NBUF == 2 ? buf ^ 1 : 0);
         }
+    };
+
+    if (nsteps > 0) {
+        load_a(a0);
+        load_b(b0, keep0, live0);
+        if (nsteps > 1) load_b(b1, keep1, live1);
+        store_a(a0, 0);
+    }
+    for (int s = 0; s < nsteps; s += 3) {
+        step(s, b0, keep0, live0, b2, keep2, live2);
+        if (s + 1 < nsteps) step(s + 1, b1, keep1, live1, b0, keep0, live0);
+        if (s + 2 < nsteps) step(s + 2, b2, keep2, live2, b1, keep1, live1);
     }
     // write back: element v of lane l in a 32x32 block is row 8 (v / 4) + 4 (l / 32) + v % 4
     if (outv >= 0) {
@@ -256,17 +331,58 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
         for (int i = 0; i < RBH; ++i) {
             if (i >= nrb) continue;
             const int rb = rb0 + i;
+#pragma unroll
             for (int v4 = 0; v4 < 4; ++v4) {
-                float4 *op = (float4 *)(a.out + (size_t)outv * (NRB * 32) + rb * 32 + 8 * v4 + 4 * hf);
-                float4 cur = *op;
-                cur.x += acc[i][4 * v4];
-                cur.y += acc[i][4 * v4 + 1];
-                cur.z += acc[i][4 * v4 + 2];
-                cur.w += acc[i][4 * v4 + 3];
+                f32x4 *op = (f32x4 *)(a.out + (size_t)outv * RP + rb * 32 + 8 * v4 + 4 * hf);
+                f32x4 cur = *op;
+                cur[0] += acc[i][4 * v4];
+                cur[1] += acc[i][4 * v4 + 1];
+                cur[2] += acc[i][4 * v4 + 2];
+                cur[3] += acc[i][4 * v4 + 3];
                 *op = cur;
             }
         }
     }
+}
+
+// Matrices [ndir][r_pad][r_pad] float32 -> split-BF16 chunks in LDS image order.
+__global__ void k_split_mats(const float *rm, int r_pad, int64_t total, uint16_t *out) {
+    int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;  // total = ndir * r_pad * r_pad
+    const int nrb = r_pad / 32, nkc = r_pad / KC;
+    const int64_t part_sz = (int64_t)nrb * 2 * 64 * 8;
+    // idx enumerates (dir, kc, rb, h2, lane, slot); each thread writes all three parts
+    const int slot = (int)(idx % 8);
+    int64_t r = idx / 8;
+    const int ln = (int)(r % 64);
+    r /= 64;
+    const int h2 = (int)(r % 2);
+    r /= 2;
+    const int rb = (int)(r % nrb);
+    r /= nrb;
+    const int kc = (int)(r % nkc);
+    const int64_t dir = r / nkc;
+    const int row = rb * 32 + (ln & 31);
+    const int k = kc * KC + 16 * h2 + 8 * (ln >> 5) + slot;
+    uint16_t h, m, l;
+    split3(rm[(dir * r_pad + row) * r_pad + k], h, m, l);
+    uint16_t *o = out + (dir * nkc + kc) * 3 * part_sz + ((int64_t)(rb * 2 + h2) * 64 + ln) * 8 + slot;
+    o[0] = h;
+    o[part_sz] = m;
+    o[2 * part_sz] = l;
+}
+
+__global__ void k_split_vecs(const float *in, int r_pad, int64_t total, uint16_t *out) {
+    int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;  // total = nvec * r_pad
+    const int64_t v = idx / r_pad;
+    const int k = (int)(idx % r_pad), kc = k / KC, kk = k % KC;
+    uint16_t h, m, l;
+    split3(in[idx], h, m, l);
+    uint16_t *o = out + v * vec_bf_stride(r_pad) + kc * 3 * KC + kk;
+    o[0] = h;
+    o[KC] = m;
+    o[2 * KC] = l;
 }
 
 template <int NRB, bool BF16>
@@ -302,10 +418,29 @@ int m2l_ncol(int r_pad) {
 
 bool m2l_supported(int r_pad) { return r_pad > 0 && r_pad % 32 == 0 && r_pad <= 512; }
 
+size_t m2l_split_mats_elems(int r_pad, int ndir) { return (size_t)ndir * 3 * r_pad * r_pad; }
+size_t m2l_split_vecs_elems(int r_pad, int64_t nvec) { return (size_t)nvec * vec_bf_stride(r_pad); }
+
+void m2l_split_mats(const float *rm, int r_pad, int ndir, uint16_t *out, hipStream_t s) {
+    FMM_REQUIRE(m2l_supported(r_pad), "m2l: unsupported state size");
+    const int64_t total = (int64_t)ndir * r_pad * r_pad;
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_split_mats, dim3(grid_for(total, 256)), dim3(256), 0, s, rm, r_pad, total, out);
+    FMM_HIP(hipGetLastError());
+}
+
+void m2l_split_vecs(const float *in, int r_pad, int64_t nvec, uint16_t *out, hipStream_t s) {
+    const int64_t total = nvec * r_pad;
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_split_vecs, dim3(grid_for(total, 256)), dim3(256), 0, s, in, r_pad, total, out);
+    FMM_HIP(hipGetLastError());
+}
+
 void m2l_run(bool bf16, const M2LLaunch &a, hipStream_t s) {
     if (a.ntile <= 0) return;
     FMM_REQUIRE(m2l_supported(a.r_pad), "m2l: unsupported state size");
     FMM_REQUIRE(a.ncol == m2l_ncol(a.r_pad), "m2l: tile width mismatch");
+    FMM_REQUIRE(bf16 ? (a.mats_bf && a.in_bf) : (a.mats && a.in), "m2l: operands missing for this form");
     if (bf16)
         dispatch<true>(a.r_pad / 32, a, s);
     else

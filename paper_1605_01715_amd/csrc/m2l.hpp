@@ -8,8 +8,10 @@ namespace fmm {
 // ntile workgroups; tile t owns output vectors tile_cols[t][0..ncol) (-1 = unused)
 // and the active directions term_dir[e] for e in [tile_term_off[t], tile_term_off[t+1]),
 // with source vectors term_src[e][0..ncol) (-1 = none). Vectors are rows of
-// r_pad floats (compressed far-field state); matrices are float32, row-major
-// r_pad x r_pad, one per direction. out += sum over the tile's terms.
+// r_pad floats (compressed far-field state); out += sum over the tile's terms.
+// FP32 form: mats are float32, row-major r_pad x r_pad, one per direction, and
+// in holds the source vectors. Split-BF16 form: mats_bf and in_bf hold the
+// same data split by m2l_split_mats and m2l_split_vecs.
 struct M2LLaunch {
     int r_pad = 0, ntile = 0, ncol = 0;
     const int64_t *tile_term_off = nullptr;
@@ -18,11 +20,19 @@ struct M2LLaunch {
     const int32_t *tile_cols = nullptr;
     const float *mats = nullptr;
     const float *in = nullptr;
+    const uint16_t *mats_bf = nullptr;
+    const uint16_t *in_bf = nullptr;
     float *out = nullptr;
 };
 
 int m2l_ncol(int r_pad);
 bool m2l_supported(int r_pad);  // any multiple of 32 up to 512
 void m2l_run(bool bf16, const M2LLaunch &a, hipStream_t s);
+
+// Split-BF16 operands: each float32 value becomes three bfloat16 parts.
+size_t m2l_split_mats_elems(int r_pad, int ndir);    // uint16 elements of the split matrices
+size_t m2l_split_vecs_elems(int r_pad, int64_t nvec);
+void m2l_split_mats(const float *rm, int r_pad, int ndir, uint16_t *out, hipStream_t s);
+void m2l_split_vecs(const float *in, int r_pad, int64_t nvec, uint16_t *out, hipStream_t s);
 
 }  // namespace fmm

@@ -115,31 +115,68 @@ __global__ __launch_bounds__(64) void k_points_to_surface(const int32_t *items, 
 }
 
 // ------------------------------------------------------------ leaf evaluation
-template <int NRHS, bool SL, bool DL, bool FIELD>
-__global__ __launch_bounds__(64) void k_eval(EvalArgs a, SurfaceGeom g, PointSrc src) {
-    constexpr int NOUT = FIELD ? 4 : 1;
-    constexpr int WS = 3 + NRHS;  // surface source record
-    constexpr int WP = 3 + (SL ? NRHS : 0) + (DL ? 3 * NRHS : 0);
-    constexpr int W = WP > WS ? WP : WS;
-    __shared__ float sh[64 * W];
-    const int lane = threadIdx.x;
-    const int leaf = a.wleaf[blockIdx.x];
-    const int64_t t_first = a.tbeg[leaf] + a.wt0[blockIdx.x];
-    const int nt = (int)min((int64_t)64, a.tend[leaf] - t_first);
-    int tp = 1;
-    while (tp < nt) tp <<= 1;
-    const int grp = lane / tp, ngrp = 64 / tp;
-    const int tl = lane % tp;
-    const bool tvalid = tl < nt;
-    const int64_t k = t_first + (tvalid ? tl : 0);
-    const float xg = a.tx[k], yg = a.ty[k], zg = a.tz[k];
-    const double cx = g.centre[3 * leaf], cy = g.centre[3 * leaf + 1], cz = g.centre[3 * leaf + 2];
-    const float xl = (float)((double)xg - cx), yl = (float)((double)yg - cy), zl = (float)((double)zg - cz);
-    float hi[NRHS][NOUT], lo[NRHS][NOUT];
-    for (int r = 0; r < NRHS; ++r)
-        for (int o = 0; o < NOUT; ++o) hi[r][o] = lo[r][o] = 0.f;
+//
+// One wave per work item (up to 64 targets of a leaf). Lanes are laid out as
+// S source slices x L lane-targets, each lane holding TPL targets (1 or 2,
+// chosen per item to keep most lanes busy: a 39-target item runs as 20 lanes
+// x 2 targets x 3 slices instead of 39 of 64 lanes). Sources are staged in
+// LDS 64 at a time (records padded to 16 bytes, the tail of a tile filled
+// with zero-density sources far away), so the loop over a tile has the same
+// trip count in every lane and no per-pair validity test. Slices are summed
+// through LDS at the end.
+constexpr int kFar = 1000000000;  // far-away coordinate of padding records (1e9)
 
-    // surfaces: L2P (own downward equivalent density) and M2P (W-list boxes)
+template <int NRHS, bool SL, bool DL, bool FIELD>
+struct EvalShape {
+    static constexpr int NOUT = FIELD ? 4 : 1;
+    static constexpr int WP = 3 + (SL ? NRHS : 0) + (DL ? 3 * NRHS : 0);  // point source record
+    static constexpr int WS = 3 + NRHS;                                   // surface source record
+    static constexpr int W = ((WP > WS ? WP : WS) + 3) / 4 * 4;           // floats, 16-byte aligned
+    static constexpr int NREC = 128;                                      // 64 + room for slice overrun
+};
+
+template <int TPL, int NRHS, bool SL, bool DL, bool FIELD>
+__device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSrc &src, int leaf, int64_t t_first,
+                          int nt, float *sh, float *red) {
+    using E = EvalShape<NRHS, SL, DL, FIELD>;
+    constexpr int NOUT = E::NOUT, W = E::W, NREC = E::NREC;
+    const int lane = threadIdx.x;
+    const int L = (nt + TPL - 1) / TPL;      // lanes per slice
+    const int S = 64 / L;                    // slices
+    const int slice = lane / L, tl = lane % L;
+    const int niter = (64 + S - 1) / S;      // uniform trip count over a tile
+    const bool active = slice < S;
+
+    float xg[TPL], yg[TPL], zg[TPL], xl[TPL], yl[TPL], zl[TPL];
+    const double cx = g.centre[3 * leaf], cy = g.centre[3 * leaf + 1], cz = g.centre[3 * leaf + 2];
+#pragma unroll
+    for (int u = 0; u < TPL; ++u) {
+        const int t = tl + u * L;
+        const int64_t k = t_first + (t < nt ? t : 0);
+        xg[u] = a.tx[k];
+        yg[u] = a.ty[k];
+        zg[u] = a.tz[k];
+        xl[u] = (float)((double)xg[u] - cx);
+        yl[u] = (float)((double)yg[u] - cy);
+        zl[u] = (float)((double)zg[u] - cz);
+    }
+    float hi[TPL][NRHS][NOUT], lo[TPL][NRHS][NOUT];
+#pragma unroll
+    for (int u = 0; u < TPL; ++u)
+        for (int r = 0; r < NRHS; ++r)
+            for (int o = 0; o < NOUT; ++o) hi[u][r][o] = lo[u][r][o] = 0.f;
+
+    // padding records: slots 64..127 once (every tile's overrun), slots
+    // [cnt, 64) per tile
+    auto pad = [&](int slot) {
+        float *p = sh + slot * W;
+        p[0] = p[1] = p[2] = (float)kFar;
+        for (int c = 3; c < W; ++c) p[c] = 0.f;
+    };
+    pad(64 + lane);
+
+    // surfaces: L2P (own downward equivalent density) and M2P (W-list boxes);
+    // surface points never coincide with targets (they lie outside the box)
     for (int e = a.soff[leaf]; e < a.soff[leaf + 1]; ++e) {
         const int box = a.sbox[e];
         const bool down = a.skind[e] == 0;
@@ -148,47 +185,65 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a, SurfaceGeom g, PointSrc
         const float *phi = (down ? a.phi_d : a.phi_u) + (int64_t)box * NRHS * g.n_pad;
         for (int m0 = 0; m0 < g.ns; m0 += 64) {
             const int m = m0 + lane;
-            const int cnt = min(64, g.ns - m0);
             if (m < g.ns) {
                 float *p = sh + lane * W;
                 p[0] = (float)(ox + rr * g.Y[3 * m]);
                 p[1] = (float)(oy + rr * g.Y[3 * m + 1]);
                 p[2] = (float)(oz + rr * g.Y[3 * m + 2]);
                 for (int r = 0; r < NRHS; ++r) p[3 + r] = phi[r * g.n_pad + m];
+            } else {
+                pad(lane);
             }
             __syncthreads();
-            float part[NRHS][NOUT];
-            for (int r = 0; r < NRHS; ++r)
-                for (int o = 0; o < NOUT; ++o) part[r][o] = 0.f;
-            for (int jj = grp; jj < cnt; jj += ngrp) {
-                const float *p = sh + jj * W;
-                float dx = xl - p[0], dy = yl - p[1], dz = zl - p[2];
-                float r2 = dx * dx + dy * dy + dz * dz;
-                float inv = r2 > 0.f ? rsq(r2) : 0.f;
-                float inv3 = inv * inv * inv;
-                for (int r = 0; r < NRHS; ++r) {
-                    float d = p[3 + r];
-                    part[r][0] += d * inv;
+            float part[TPL][NRHS][NOUT];
+#pragma unroll
+            for (int u = 0; u < TPL; ++u)
+                for (int r = 0; r < NRHS; ++r)
+                    for (int o = 0; o < NOUT; ++o) part[u][r][o] = 0.f;
+            for (int i = 0; i < niter; ++i) {
+                const float4 *p4 = (const float4 *)(sh + (slice + i * S) * W);
+                const float4 r0 = p4[0];
+                float ph[NRHS];
+                ph[0] = r0.w;
+                if (NRHS > 1) {
+                    const float4 r1 = p4[1];
+                    const float rest[3] = {r1.x, r1.y, r1.z};
+                    for (int r = 1; r < NRHS; ++r) ph[r] = rest[r - 1];
+                }
+#pragma unroll
+                for (int u = 0; u < TPL; ++u) {
+                    const float dx = xl[u] - r0.x, dy = yl[u] - r0.y, dz = zl[u] - r0.z;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float inv = rsq(r2);
                     if (FIELD) {
-                        float di3 = d * inv3;
-                        part[r][1] += di3 * dx;
-                        part[r][2] += di3 * dy;
-                        part[r][3] += di3 * dz;
+                        const float inv3 = inv * inv * inv;
+                        for (int r = 0; r < NRHS; ++r) {
+                            part[u][r][0] += ph[r] * inv;
+                            const float di3 = ph[r] * inv3;
+                            part[u][r][1] += di3 * dx;
+                            part[u][r][2] += di3 * dy;
+                            part[u][r][3] += di3 * dz;
+                        }
+                    } else {
+                        for (int r = 0; r < NRHS; ++r) part[u][r][0] += ph[r] * inv;
                     }
                 }
             }
-            for (int r = 0; r < NRHS; ++r)
-                for (int o = 0; o < NOUT; ++o) two_sum_into(hi[r][o], lo[r][o], part[r][o]);
+#pragma unroll
+            for (int u = 0; u < TPL; ++u)
+                for (int r = 0; r < NRHS; ++r)
+                    for (int o = 0; o < NOUT; ++o) two_sum_into(hi[u][r][o], lo[u][r][o], part[u][r][o]);
             __syncthreads();
         }
     }
 
-    // points: P2P (U list) and the direct W / X pairs
+    // points: P2P (U list) and the direct W / X pairs; r < delta excluded
+    // (delta2 > 0 also excludes r = 0)
+    const float delta2 = a.delta2;
     for (int e = a.poff[leaf]; e < a.poff[leaf + 1]; ++e) {
         const int s0 = a.prng[2 * e], s1 = a.prng[2 * e + 1];
         for (int j0 = s0; j0 < s1; j0 += 64) {
             const int j = j0 + lane;
-            const int cnt = min(64, s1 - j0);
             if (j < s1) {
                 float *p = sh + lane * W;
                 p[0] = src.x[j];
@@ -203,67 +258,125 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a, SurfaceGeom g, PointSrc
                         p[o++] = src.my[r * src.n + j];
                         p[o++] = src.mz[r * src.n + j];
                     }
+            } else {
+                pad(lane);
             }
             __syncthreads();
-            float part[NRHS][NOUT];
-            for (int r = 0; r < NRHS; ++r)
-                for (int o = 0; o < NOUT; ++o) part[r][o] = 0.f;
-            for (int jj = grp; jj < cnt; jj += ngrp) {
-                const float *p = sh + jj * W;
-                float dx = xg - p[0], dy = yg - p[1], dz = zg - p[2];
-                float r2 = dx * dx + dy * dy + dz * dz;
-                float inv = (r2 >= a.delta2 && r2 > 0.f) ? rsq(r2) : 0.f;
-                float inv3 = inv * inv * inv;
-                int o = 3;
-                for (int r = 0; r < NRHS; ++r) {
-                    if (SL) {
-                        float d = p[o++];
-                        part[r][0] += d * inv;
-                        if (FIELD) {
-                            float di3 = d * inv3;
-                            part[r][1] += di3 * dx;
-                            part[r][2] += di3 * dy;
-                            part[r][3] += di3 * dz;
+            float part[TPL][NRHS][NOUT];
+#pragma unroll
+            for (int u = 0; u < TPL; ++u)
+                for (int r = 0; r < NRHS; ++r)
+                    for (int o = 0; o < NOUT; ++o) part[u][r][o] = 0.f;
+            for (int i = 0; i < niter; ++i) {
+                const float *p = sh + (slice + i * S) * W;
+                float rec[W];
+#pragma unroll
+                for (int c = 0; c < W; c += 4) {
+                    const float4 v = *(const float4 *)(p + c);
+                    rec[c] = v.x;
+                    rec[c + 1] = v.y;
+                    rec[c + 2] = v.z;
+                    rec[c + 3] = v.w;
+                }
+#pragma unroll
+                for (int u = 0; u < TPL; ++u) {
+                    const float dx = xg[u] - rec[0], dy = yg[u] - rec[1], dz = zg[u] - rec[2];
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float inv = r2 >= delta2 ? rsq(r2) : 0.f;
+                    const float inv2 = inv * inv;
+                    int o = 3;
+                    float sl[NRHS];
+                    for (int r = 0; r < NRHS; ++r) sl[r] = SL ? rec[o + r] : 0.f;
+                    if (SL) o += NRHS;
+                    if (FIELD) {
+                        const float inv3 = inv2 * inv;
+                        for (int r = 0; r < NRHS; ++r) {
+                            part[u][r][0] += sl[r] * inv;
+                            const float di3 = sl[r] * inv3;
+                            part[u][r][1] += di3 * dx;
+                            part[u][r][2] += di3 * dy;
+                            part[u][r][3] += di3 * dz;
+                        }
+                    } else {
+                        for (int r = 0; r < NRHS; ++r) {
+                            // q / r + (m . d) / r^3 = (q + (m . d) / r^2) / r
+                            float t = sl[r];
+                            if (DL) {
+                                const float md = rec[o + 3 * r] * dx + rec[o + 3 * r + 1] * dy + rec[o + 3 * r + 2] * dz;
+                                t += md * inv2;
+                            }
+                            part[u][r][0] += t * inv;
                         }
                     }
                 }
-                if (DL) {
-                    int od = 3 + (SL ? NRHS : 0);
-                    for (int r = 0; r < NRHS; ++r) {
-                        float md = p[od] * dx + p[od + 1] * dy + p[od + 2] * dz;
-                        od += 3;
-                        part[r][0] += md * inv3;
-                    }
-                }
             }
-            for (int r = 0; r < NRHS; ++r)
-                for (int o = 0; o < NOUT; ++o) two_sum_into(hi[r][o], lo[r][o], part[r][o]);
+#pragma unroll
+            for (int u = 0; u < TPL; ++u)
+                for (int r = 0; r < NRHS; ++r)
+                    for (int o = 0; o < NOUT; ++o) two_sum_into(hi[u][r][o], lo[u][r][o], part[u][r][o]);
             __syncthreads();
         }
     }
 
-    // combine the lane groups that share a target
-    for (int off = tp; off < 64; off <<= 1) {
-        for (int r = 0; r < NRHS; ++r)
-            for (int o = 0; o < NOUT; ++o) {
-                float h2 = __shfl_xor(hi[r][o], off);
-                float l2 = __shfl_xor(lo[r][o], off);
-                two_sum_into(hi[r][o], lo[r][o], h2);
-                lo[r][o] += l2;
-            }
+    // sum the slices of each target through LDS, then slice 0 writes
+    constexpr int NV = TPL * NRHS * NOUT;
+    if (active && slice > 0) {
+        float *q = red + (size_t)lane * NV * 2;
+        int v = 0;
+#pragma unroll
+        for (int u = 0; u < TPL; ++u)
+            for (int r = 0; r < NRHS; ++r)
+                for (int o = 0; o < NOUT; ++o, ++v) {
+                    q[2 * v] = hi[u][r][o];
+                    q[2 * v + 1] = lo[u][r][o];
+                }
     }
-    if (grp == 0 && tvalid) {
-        const int64_t dst = a.trg_perm ? a.trg_perm[k] : k;
-        for (int r = 0; r < NRHS; ++r) {
-            if (a.pot) a.pot[r * a.n_trg + dst] = (hi[r][0] + lo[r][0]) * kInv4Pi;
-            if (FIELD && a.field) {
-                float *f = a.field + ((int64_t)r * a.n_trg + dst) * 3;
-                f[0] = (hi[r][1] + lo[r][1]) * kInv4Pi;
-                f[1] = (hi[r][2] + lo[r][2]) * kInv4Pi;
-                f[2] = (hi[r][3] + lo[r][3]) * kInv4Pi;
+    __syncthreads();
+    if (active && slice == 0) {
+        for (int sl2 = 1; sl2 < S; ++sl2) {
+            const float *q = red + (size_t)(sl2 * L + tl) * NV * 2;
+            int v = 0;
+#pragma unroll
+            for (int u = 0; u < TPL; ++u)
+                for (int r = 0; r < NRHS; ++r)
+                    for (int o = 0; o < NOUT; ++o, ++v) {
+                        two_sum_into(hi[u][r][o], lo[u][r][o], q[2 * v]);
+                        lo[u][r][o] += q[2 * v + 1];
+                    }
+        }
+#pragma unroll
+        for (int u = 0; u < TPL; ++u) {
+            const int t = tl + u * L;
+            if (t >= nt) continue;
+            const int64_t k = t_first + t;
+            const int64_t dst = a.trg_perm ? a.trg_perm[k] : k;
+            for (int r = 0; r < NRHS; ++r) {
+                if (a.pot) a.pot[r * a.n_trg + dst] = (hi[u][r][0] + lo[u][r][0]) * kInv4Pi;
+                if (FIELD && a.field) {
+                    float *f = a.field + ((int64_t)r * a.n_trg + dst) * 3;
+                    f[0] = (hi[u][r][1] + lo[u][r][1]) * kInv4Pi;
+                    f[1] = (hi[u][r][2] + lo[u][r][2]) * kInv4Pi;
+                    f[2] = (hi[u][r][3] + lo[u][r][3]) * kInv4Pi;
+                }
             }
         }
     }
+}
+
+template <int NRHS, bool SL, bool DL, bool FIELD>
+__global__ __launch_bounds__(64) void k_eval(EvalArgs a, SurfaceGeom g, PointSrc src) {
+    using E = EvalShape<NRHS, SL, DL, FIELD>;
+    __shared__ __align__(16) float sh[E::NREC * E::W];
+    __shared__ float red[64 * 2 * NRHS * E::NOUT * 2];
+    const int leaf = a.wleaf[blockIdx.x];
+    const int64_t t_first = a.tbeg[leaf] + a.wt0[blockIdx.x];
+    const int nt = (int)min((int64_t)64, a.tend[leaf] - t_first);
+    // targets per lane: 2 when that keeps more lanes busy (nt * S / (64 TPL))
+    const int s1 = 64 / nt, s2 = 64 / ((nt + 1) / 2);
+    if (nt * s2 >= 2 * nt * s1)
+        eval_item<2, NRHS, SL, DL, FIELD>(a, g, src, leaf, t_first, nt, sh, red);
+    else
+        eval_item<1, NRHS, SL, DL, FIELD>(a, g, src, leaf, t_first, nt, sh, red);
 }
 
 // ------------------------------------------------------------ all pairs

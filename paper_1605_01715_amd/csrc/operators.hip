@@ -234,6 +234,8 @@ std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
     build(pm2m, dPU, dVrSi, &op->m2m_f64, nullptr);
     build(pl2l, dPV, dUrSi, &op->l2l_f64, nullptr);
     build(pm2l, dPV, dVrSi, nullptr, &op->m2l_rm);
+    op->m2l_bf.alloc(m2l_split_mats_elems(rp, kNumDirs));
+    m2l_split_mats(op->m2l_rm.p, rp, kNumDirs, op->m2l_bf.p, s);
     FMM_HIP(hipStreamSynchronize(s));
     return op;
 }

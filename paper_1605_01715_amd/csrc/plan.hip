@@ -12,6 +12,8 @@
 // evaluated directly rather than through a surface (this never changes what
 // is computed, only how).
 #include <algorithm>
+#include <array>
+#include <limits>
 
 #include "plan.hpp"
 
@@ -167,12 +169,28 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         const int nc = m2l_ncol(P.r_pad);
         int ntile = 0;
         std::vector<int32_t> cols;
+        // Within an octant, boxes are ordered by their set of active
+        // directions (lexicographically, then by index), so a tile gathers
+        // boxes with similar V lists and runs few directions that most of
+        // its columns do not need.
+        constexpr int kMaskWords = (kNumDirs + 63) / 64;
+        auto dir_mask = [&](int32_t b) {
+            std::array<uint64_t, kMaskWords> m{};
+            for (int d = 0; d < kNumDirs; ++d) {
+                const int32_t a = vd[(size_t)b * kNumDirs + d];
+                if (a >= 0 && nsrc(a) > 0) m[d / 64] |= 1ull << (63 - d % 64);
+            }
+            return m;
+        };
         for (int o = 0; o < 8; ++o) {
-            std::vector<int32_t> grp;
+            std::vector<std::pair<std::array<uint64_t, kMaskWords>, int32_t>> keyed;
             for (int32_t b : boxes) {
                 const int32_t *an = &t.h_anchor[3 * (size_t)b];
-                if ((((an[0] & 1) << 2) | ((an[1] & 1) << 1) | (an[2] & 1)) == o) grp.push_back(b);
+                if ((((an[0] & 1) << 2) | ((an[1] & 1) << 1) | (an[2] & 1)) == o) keyed.push_back({dir_mask(b), b});
             }
+            std::sort(keyed.begin(), keyed.end());
+            std::vector<int32_t> grp;
+            for (auto &kb : keyed) grp.push_back(kb.second);
             int nt = 0;
             std::vector<int32_t> c = tile_columns(grp, nrhs, nc, nt);
             cols.insert(cols.end(), c.begin(), c.end());
@@ -425,6 +443,7 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     run_gemm(P.p2l_proj, op.pv_f64.p, rp, np, P.chk.p, P.dt.p, nullptr, true, s);
     mark(ST_M2L);
     {
+        if (P.m2l_bf16) m2l_split_vecs(P.ut.p, rp, t.nb * nrhs, P.ut_bf.p, s);
         M2LLaunch m;
         m.r_pad = rp;
         m.ntile = P.m2l_ntile;
@@ -435,6 +454,8 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         m.tile_cols = P.m2l_cols.p;
         m.mats = op.m2l_rm.p;
         m.in = P.ut.p;
+        m.mats_bf = op.m2l_bf.p;
+        m.in_bf = P.ut_bf.p;
         m.out = P.dt.p;
         m2l_run(P.m2l_bf16, m, s);
     }
@@ -469,7 +490,8 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     e.n_trg = t.n_trg;
     e.phi_d = P.phi_d.p;
     e.phi_u = P.phi_u.p;
-    e.delta2 = P.opt.cutoff * P.opt.cutoff;
+    // r < cutoff is excluded; a positive floor also excludes r = 0 when cutoff = 0
+    e.delta2 = std::max(P.opt.cutoff * P.opt.cutoff, std::numeric_limits<float>::min());
     e.pot = pot;
     e.field = field;
     eval_leaves(nrhs, sl, dl, e, g, src, s);

@@ -30,6 +30,7 @@ struct Plan {
     bool m2l_bf16 = false;
 
     DBuf<float> ut, dt;                     // [nb * nrhs][r_pad] compressed upward / downward state
+    DBuf<uint16_t> ut_bf;                   // ut split into bfloat16 parts (split-BF16 M2L)
     DBuf<float> chk;                        // [nb * nrhs][n_pad] check potentials made from points
     DBuf<float> phi_u, phi_d;               // [nb * nrhs][n_pad] equivalent densities
     DBuf<float> q_sorted, mx, my, mz;       // [nrhs][n_src]
