@@ -64,14 +64,16 @@ def run_form(F, torch, x, nrm, q, mu, precision, order, leaf, steps, warmup, eps
     return {"ms": ms, "setup_s": setup_s, "info": info, "stages": stages, "pot": pot}
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_clustered4m_p8_s128.md")
+def traffic_profile(n, cfg):
+    order, leaf, eps = cfg
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_clustered{n // 1_000_000}m_p{order}_s{leaf}_eps{eps:g}.md")
 
 
 def measured_traffic(kernel, precision, n, cfg):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when the summary is for another workload, form or kernel source."""
     try:
-        txt = open(TRAFFIC_PROFILE).read()
+        txt = open(traffic_profile(n, cfg)).read()
         data = json.loads(txt[txt.index("```json") + 7:txt.rindex("```")])
         run = data.get("config", {})
         if (n, precision, list(cfg)) != (run.get("n"), run.get("precision"), run.get("order_leaf_eps")):

@@ -233,40 +233,6 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
                     bm[h2] = __builtin_bit_cast(bf16x8, bc[3 * h2 + 1] & keep);
                     bl[h2] = __builtin_bit_cast(bf16x8, bc[3 * h2 + 2] & keep);
                 }
-#ifdef M2L_INTERLEAVE
-                // the row blocks' accumulation chains interleaved: consecutive
-                // MFMAs are independent
-#pragma unroll
-                for (int h2 = 0; h2 < 2; ++h2) {
-                    bf16x8 ah[RBH], am[RBH], al[RBH];
-#pragma unroll
-                    for (int i = 0; i < RBH; ++i) {
-                        if (i >= nrb) continue;
-                        const int off = (((rb0 + i) * 2 + h2) * 64 + lane) * 8;
-                        ah[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + off));
-                        am[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + PART + off));
-                        al[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + 2 * PART + off));
-                    }
-#pragma unroll
-                    for (int i = 0; i < RBH; ++i)
-                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[h2], acc[i], 0, 0, 0);
-#pragma unroll
-                    for (int i = 0; i < RBH; ++i)
-                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[h2], acc[i], 0, 0, 0);
-#pragma unroll
-                    for (int i = 0; i < RBH; ++i)
-                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[i], bm[h2], acc[i], 0, 0, 0);
-#pragma unroll
-                    for (int i = 0; i < RBH; ++i)
-                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[i], bh[h2], acc[i], 0, 0, 0);
-#pragma unroll
-                    for (int i = 0; i < RBH; ++i)
-                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bm[h2], acc[i], 0, 0, 0);
-#pragma unroll
-                    for (int i = 0; i < RBH; ++i)
-                        if (i < nrb) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[h2], acc[i], 0, 0, 0);
-                }
-#else
 #pragma unroll
                 for (int i = 0; i < RBH; ++i) {
                     if (i >= nrb) continue;  // static index i keeps acc in registers
@@ -288,7 +254,6 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
                     }
                     acc[i] = c;
                 }
-#endif
             } else {
                 const float *p = (const float *)base;
                 f32x4 bv4[4];

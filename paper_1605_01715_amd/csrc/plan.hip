@@ -171,8 +171,9 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         std::vector<int32_t> cols;
         // Within an octant, boxes are ordered by their set of active
         // directions (lexicographically, then by index), so a tile gathers
-        // boxes with similar V lists and runs few directions that most of
-        // its columns do not need.
+        // boxes with similar V lists and runs few directions that most of its
+        // columns do not need (measured: fill 0.69 -> 0.78 on the clustered
+        // cloud, worth more than the spatial locality it gives up).
         constexpr int kMaskWords = (kNumDirs + 63) / 64;
         auto dir_mask = [&](int32_t b) {
             std::array<uint64_t, kMaskWords> m{};
@@ -217,6 +218,35 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
                 tsrc.insert(tsrc.end(), colsrc.begin(), colsrc.end());
             }
             toff.push_back((int64_t)tdir.size());
+        }
+        // Launch order: the kernel gives XCD x the contiguous block range it
+        // dispatches to x (ranges of ceil or floor of ntile / 8 tiles, larger
+        // first). Tiles are dealt round-robin, heaviest first, into those
+        // ranges, so every XCD gets the same mix and starts its heaviest
+        // tiles first (longest-processing-time order: a short tail).
+        {
+            std::vector<int> byw(ntile);
+            for (int i = 0; i < ntile; ++i) byw[i] = i;
+            std::stable_sort(byw.begin(), byw.end(),
+                             [&](int x, int y) { return toff[x + 1] - toff[x] > toff[y + 1] - toff[y]; });
+            std::vector<int> order;
+            order.reserve(ntile);
+            for (int x = 0; x < 8; ++x)
+                for (int i = x; i < ntile; i += 8) order.push_back(byw[i]);
+            std::vector<int64_t> toff2{0};
+            std::vector<int32_t> tdir2, tsrc2, cols2;
+            for (int tl : order) {
+                for (int64_t e = toff[tl]; e < toff[tl + 1]; ++e) {
+                    tdir2.push_back(tdir[e]);
+                    tsrc2.insert(tsrc2.end(), tsrc.begin() + e * nc, tsrc.begin() + (e + 1) * nc);
+                }
+                toff2.push_back((int64_t)tdir2.size());
+                cols2.insert(cols2.end(), cols.begin() + (size_t)tl * nc, cols.begin() + (size_t)(tl + 1) * nc);
+            }
+            toff.swap(toff2);
+            tdir.swap(tdir2);
+            tsrc.swap(tsrc2);
+            cols.swap(cols2);
         }
         P.m2l_ntile = ntile;
         P.m2l_steps = (int64_t)tdir.size();
