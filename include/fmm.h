@@ -103,6 +103,28 @@ int fmm_setup(const float *src_xyz, const float *src_nrm, int64_t n_src,
               const fmm_options *opt, void *hip_stream, fmm_plan *out);
 
 /*
+ * Build one plan over many independent instances (separate bodies that never
+ * interact, e.g. a batch of ferromagnet surfaces each solved on its own,
+ * Sec. II.B with one body per instance). Every instance gets its own octree
+ * and lists; the plan runs each stage of fmm_apply as one launch over all of
+ * them. Inputs are the instances' points concatenated in instance order:
+ *   n_inst   host              number of instances, >= 1
+ *   src_off  host [n_inst + 1] prefix offsets into the sources (src_off[0] = 0)
+ *   trg_off  host [n_inst + 1] prefix offsets into the targets, or NULL
+ *                              (then trg_xyz must be NULL: targets are the sources)
+ *   src_xyz, src_nrm, trg_xyz, trg_nrm as in fmm_setup, concatenated
+ * fmm_apply then takes densities [nrhs][total sources] and returns outputs
+ * [nrhs][total targets] in the same concatenated order; gmres_solve solves the
+ * block-diagonal system. Each instance's root cube is derived from its own
+ * points unless opt->root gives one cube for all. Errors: as fmm_setup, plus
+ * FMM_ERR_ARG for n_inst < 1, offsets that do not start at 0 or decrease, and
+ * trg_off without trg_xyz (or the reverse).
+ */
+int fmm_setup_batch(int n_inst, const int64_t *src_off, const int64_t *trg_off, const float *src_xyz,
+                    const float *src_nrm, const float *trg_xyz, const float *trg_nrm, const fmm_options *opt,
+                    void *hip_stream, fmm_plan *out);
+
+/*
  * One FMM evaluation (Sec. II.A Eq. sum_fmm with the kernels above).
  *   q      device [nrhs][n_src]      single-layer densities (weights folded in), or NULL
  *   mu     device [nrhs][n_src]      double-layer strengths, or NULL

@@ -18,7 +18,7 @@ from ._lib import (FMM_ERR_ARG, FMM_ERR_DEVICE, FMM_ERR_NOMEM, FMM_ERR_NOT_CONVE
                    FMM_OP_DIELECTRIC, FMM_OP_FK, FMM_OUT_FIELD, FMM_OUT_POT, FMM_PREC_FP32, FMM_PREC_SPLIT_BF16,
                    FMM_SRC_DOUBLE, FMM_SRC_SINGLE, STAGES)
 
-__all__ = ["Plan", "FmmError", "fmm_default_options", "fmm_setup", "fmm_apply", "gmres_solve", "fmm_destroy",
+__all__ = ["fmm_setup_batch", "Plan", "FmmError", "fmm_default_options", "fmm_setup", "fmm_apply", "gmres_solve", "fmm_destroy",
            "fmm_last_error", "fmm_direct", "fmm_plan_info", "fmm_export_tree", "fmm_export_stage",
            "fmm_set_timing", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "library_path"]
 
@@ -114,6 +114,27 @@ def fmm_setup(src_xyz, src_nrm=None, trg_xyz=None, trg_nrm=None, options=None, s
                          _ptr(trg_xyz, f32, "trg_xyz"), _ptr(trg_nrm, f32, "trg_nrm"),
                          n_trg if trg_xyz is not None else 0, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return Plan(h.value, opts, n_src, n_trg)
+
+
+def fmm_setup_batch(src_off, src_xyz, src_nrm=None, trg_off=None, trg_xyz=None, trg_nrm=None, options=None,
+                    stream=None):
+    """One plan over independent instances; offsets are host sequences of n_inst + 1 prefix sums."""
+    import numpy as np
+    import torch
+
+    lib = L.load()
+    opts = options if options is not None else fmm_default_options()
+    so = np.ascontiguousarray(np.asarray(src_off, dtype=np.int64))
+    to = np.ascontiguousarray(np.asarray(trg_off, dtype=np.int64)) if trg_off is not None else None
+    n_inst = len(so) - 1
+    h = ctypes.c_void_p()
+    f32 = torch.float32
+    _check(lib.fmm_setup_batch(n_inst, so.ctypes.data, to.ctypes.data if to is not None else None,
+                               _ptr(src_xyz, f32, "src_xyz"), _ptr(src_nrm, f32, "src_nrm"),
+                               _ptr(trg_xyz, f32, "trg_xyz"), _ptr(trg_nrm, f32, "trg_nrm"), ctypes.byref(opts),
+                               _stream(stream), ctypes.byref(h)))
+    n_src = int(so[-1])
+    return Plan(h.value, opts, n_src, int(to[-1]) if to is not None else n_src)
 
 
 def fmm_apply(plan, q=None, mu=None, pot=None, field=None, stream=None):

@@ -48,6 +48,8 @@ SIGNATURES = {
     "fmm_default_options": (None, [ctypes.POINTER(FmmOptions)]),
     "fmm_setup": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_int64, ctypes.POINTER(FmmOptions),
                           c_void_p, ctypes.POINTER(c_void_p)]),
+    "fmm_setup_batch": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                ctypes.POINTER(FmmOptions), c_void_p, ctypes.POINTER(c_void_p)]),
     "fmm_apply": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gmres_solve": (c_int, [c_void_p, ctypes.POINTER(FmmOperator), c_void_p, c_void_p, c_double, c_int, c_int,
                             ctypes.POINTER(c_int), ctypes.POINTER(c_double), c_void_p]),

@@ -62,33 +62,102 @@ void fmm_default_options(fmm_options *opt) {
 
 const char *fmm_last_error(void) { return g_last_error.c_str(); }
 
+}  // extern "C"
+
+namespace {
+
+void check_options(const fmm_options *opt) {
+    using namespace fmm;
+    FMM_REQUIRE(opt != nullptr, "fmm_setup: options are NULL");
+    FMM_REQUIRE(opt->order >= 2 && opt->order <= 10, "fmm_setup: order must be in 2..10");
+    FMM_REQUIRE(opt->leaf_size >= 1, "fmm_setup: leaf_size must be >= 1");
+    FMM_REQUIRE(opt->max_depth >= 1 && opt->max_depth <= kMaxLevel, "fmm_setup: max_depth must be in 1..21");
+    FMM_REQUIRE(opt->uniform_depth >= 0 && opt->uniform_depth <= kMaxLevel,
+                "fmm_setup: uniform_depth must be in 0..21");
+    FMM_REQUIRE(opt->nrhs >= 1 && opt->nrhs <= 4, "fmm_setup: nrhs must be in 1..4");
+    FMM_REQUIRE(opt->precision == FMM_PREC_FP32 || opt->precision == FMM_PREC_SPLIT_BF16,
+                "fmm_setup: unknown precision");
+    FMM_REQUIRE((opt->src_kernels & ~3) == 0 && opt->src_kernels != 0,
+                "fmm_setup: src_kernels must be a nonzero FMM_SRC_* mask");
+    FMM_REQUIRE((opt->outputs & ~3) == 0 && opt->outputs != 0, "fmm_setup: outputs must be a nonzero FMM_OUT_* mask");
+    FMM_REQUIRE(!((opt->outputs & FMM_OUT_FIELD) && (opt->src_kernels & FMM_SRC_DOUBLE)),
+                "fmm_setup: the field output is defined for the single layer only");
+    FMM_REQUIRE(std::isfinite(opt->cutoff) && opt->cutoff >= 0.f, "fmm_setup: cutoff must be finite and >= 0");
+    FMM_REQUIRE(opt->root[3] <= 0.0 || (std::isfinite(opt->root[0]) && std::isfinite(opt->root[1]) &&
+                                        std::isfinite(opt->root[2]) && std::isfinite(opt->root[3])),
+                "fmm_setup: root cube is not finite");
+    FMM_REQUIRE(opt->pinv_eps >= 0.0 && std::isfinite(opt->pinv_eps), "fmm_setup: pinv_eps must be finite and >= 0");
+}
+
+fmm::TreeOptions tree_options(const fmm_options *opt) {
+    fmm::TreeOptions to;
+    to.leaf_size = opt->leaf_size;
+    to.uniform_depth = opt->uniform_depth;
+    to.max_depth = opt->max_depth;
+    for (int c = 0; c < 4; ++c) to.root[c] = opt->root[c];
+    return to;
+}
+
+void init_plan(fmm::Plan &P, const fmm_options *opt) {
+    P.opt = *opt;
+    P.nrhs = opt->nrhs;
+    P.sl = opt->src_kernels & FMM_SRC_SINGLE;
+    P.dl = opt->src_kernels & FMM_SRC_DOUBLE;
+    P.want_pot = opt->outputs & FMM_OUT_POT;
+    P.want_field = opt->outputs & FMM_OUT_FIELD;
+    P.m2l_bf16 = opt->precision == FMM_PREC_SPLIT_BF16;
+}
+
+// Everything after the tree: operators, per-box buffers, work lists.
+void finish_plan(fmm::Plan &P, const fmm_options *opt, const float *trg_nrm, hipStream_t s) {
+    using namespace fmm;
+    double eps = opt->pinv_eps > 0 ? opt->pinv_eps : default_pinv_eps(opt->order);
+    P.ops = get_operators(opt->order, eps, s);
+    P.ns = P.ops->ns;
+    P.n_pad = P.ops->n_pad;
+    P.r = P.ops->r;
+    P.r_pad = P.ops->r_pad;
+    const size_t nvec = (size_t)P.t.nb * P.nrhs;
+    P.ut.alloc(nvec * P.r_pad);
+    P.dt.alloc(nvec * P.r_pad);
+    P.chk.alloc(nvec * P.n_pad);
+    if (P.m2l_bf16) P.ut_bf.alloc(m2l_split_vecs_elems(P.r_pad, (int64_t)nvec));
+    P.phi_u.alloc(nvec * P.n_pad);
+    P.phi_d.alloc(nvec * P.n_pad);
+    // zero once: padding entries are never written, vectors of boxes
+    // a stage skips stay zero
+    for (DBuf<float> *b : {&P.ut, &P.chk, &P.phi_u, &P.phi_d})
+        if (b->n) FMM_HIP(hipMemsetAsync(b->p, 0, b->bytes(), s));
+    const size_t nsv = (size_t)P.nrhs * P.t.n_src;
+    if (P.sl) P.q_sorted.alloc(nsv);
+    if (P.dl) {
+        P.mx.alloc(nsv);
+        P.my.alloc(nsv);
+        P.mz.alloc(nsv);
+    }
+    if (trg_nrm && !P.t.tsm && P.t.n_src) {
+        P.trg_nrm_user.alloc(3 * (size_t)P.t.n_src);
+        FMM_HIP(hipMemcpyAsync(P.trg_nrm_user.p, trg_nrm, 3 * P.t.n_src * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    if (P.t.nb) plan_build_worklists(P, s);
+    FMM_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+extern "C" {
+
 int fmm_setup(const float *src_xyz, const float *src_nrm, int64_t n_src, const float *trg_xyz, const float *trg_nrm,
               int64_t n_trg, const fmm_options *opt, void *hip_stream, fmm_plan *out) {
     return guarded([&] {
         using namespace fmm;
         FMM_REQUIRE(out != nullptr, "fmm_setup: out is NULL");
         *out = nullptr;
-        FMM_REQUIRE(opt != nullptr, "fmm_setup: options are NULL");
+        check_options(opt);
         FMM_REQUIRE(n_src >= 0 && n_trg >= 0, "fmm_setup: negative point count");
         FMM_REQUIRE(n_src == 0 || src_xyz != nullptr, "fmm_setup: src_xyz is NULL");
-        FMM_REQUIRE(trg_xyz == nullptr || n_trg >= 0, "fmm_setup: bad target count");
-        FMM_REQUIRE(opt->order >= 2 && opt->order <= 10, "fmm_setup: order must be in 2..10");
-        FMM_REQUIRE(opt->leaf_size >= 1, "fmm_setup: leaf_size must be >= 1");
-        FMM_REQUIRE(opt->max_depth >= 1 && opt->max_depth <= kMaxLevel, "fmm_setup: max_depth must be in 1..21");
-        FMM_REQUIRE(opt->uniform_depth >= 0 && opt->uniform_depth <= kMaxLevel, "fmm_setup: uniform_depth must be in 0..21");
-        FMM_REQUIRE(opt->nrhs >= 1 && opt->nrhs <= 4, "fmm_setup: nrhs must be in 1..4");
-        FMM_REQUIRE(opt->precision == FMM_PREC_FP32 || opt->precision == FMM_PREC_SPLIT_BF16,
-                    "fmm_setup: unknown precision");
-        FMM_REQUIRE((opt->src_kernels & ~3) == 0 && opt->src_kernels != 0, "fmm_setup: src_kernels must be a nonzero FMM_SRC_* mask");
-        FMM_REQUIRE((opt->outputs & ~3) == 0 && opt->outputs != 0, "fmm_setup: outputs must be a nonzero FMM_OUT_* mask");
-        FMM_REQUIRE(!((opt->outputs & FMM_OUT_FIELD) && (opt->src_kernels & FMM_SRC_DOUBLE)),
-                    "fmm_setup: the field output is defined for the single layer only");
         FMM_REQUIRE(!(opt->src_kernels & FMM_SRC_DOUBLE) || n_src == 0 || src_nrm != nullptr,
                     "fmm_setup: the double layer needs source normals");
-        FMM_REQUIRE(std::isfinite(opt->cutoff) && opt->cutoff >= 0.f, "fmm_setup: cutoff must be finite and >= 0");
-        FMM_REQUIRE(opt->root[3] <= 0.0 || (std::isfinite(opt->root[0]) && std::isfinite(opt->root[1]) &&
-                                            std::isfinite(opt->root[2]) && std::isfinite(opt->root[3])),
-                    "fmm_setup: root cube is not finite");
         FMM_REQUIRE(n_src + n_trg < (int64_t(1) << 31), "fmm_setup: more than 2^31 - 1 points");
 
         auto t0 = std::chrono::steady_clock::now();
@@ -96,50 +165,63 @@ int fmm_setup(const float *src_xyz, const float *src_nrm, int64_t n_src, const f
         auto *h = new fmm_plan_s();
         try {
             Plan &P = h->p;
-            P.opt = *opt;
-            P.nrhs = opt->nrhs;
-            P.sl = opt->src_kernels & FMM_SRC_SINGLE;
-            P.dl = opt->src_kernels & FMM_SRC_DOUBLE;
-            P.want_pot = opt->outputs & FMM_OUT_POT;
-            P.want_field = opt->outputs & FMM_OUT_FIELD;
-            P.m2l_bf16 = opt->precision == FMM_PREC_SPLIT_BF16;
-            TreeOptions to;
-            to.leaf_size = opt->leaf_size;
-            to.uniform_depth = opt->uniform_depth;
-            to.max_depth = opt->max_depth;
-            for (int c = 0; c < 4; ++c) to.root[c] = opt->root[c];
-            build_tree(P.t, src_xyz, src_nrm, n_src, trg_xyz, trg_nrm, n_trg, to, s);
-            double eps = opt->pinv_eps > 0 ? opt->pinv_eps : default_pinv_eps(opt->order);
-            P.ops = get_operators(opt->order, eps, s);
-            P.ns = P.ops->ns;
-            P.n_pad = P.ops->n_pad;
-            P.r = P.ops->r;
-            P.r_pad = P.ops->r_pad;
-            const size_t nvec = (size_t)P.t.nb * P.nrhs;
-            P.ut.alloc(nvec * P.r_pad);
-            P.dt.alloc(nvec * P.r_pad);
-            P.chk.alloc(nvec * P.n_pad);
-            if (P.m2l_bf16) P.ut_bf.alloc(m2l_split_vecs_elems(P.r_pad, (int64_t)nvec));
-            P.phi_u.alloc(nvec * P.n_pad);
-            P.phi_d.alloc(nvec * P.n_pad);
-            // zero once: padding entries are never written, vectors of boxes
-            // a stage skips stay zero
-            for (DBuf<float> *b : {&P.ut, &P.chk, &P.phi_u, &P.phi_d})
-                if (b->n) FMM_HIP(hipMemsetAsync(b->p, 0, b->bytes(), s));
-            const size_t nsv = (size_t)P.nrhs * P.t.n_src;
-            if (P.sl) P.q_sorted.alloc(nsv);
-            if (P.dl) {
-                P.mx.alloc(nsv);
-                P.my.alloc(nsv);
-                P.mz.alloc(nsv);
+            init_plan(P, opt);
+            build_tree(P.t, src_xyz, src_nrm, n_src, trg_xyz, trg_nrm, n_trg, tree_options(opt), s);
+            finish_plan(P, opt, trg_nrm, s);
+            P.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+int fmm_setup_batch(int n_inst, const int64_t *src_off, const int64_t *trg_off, const float *src_xyz,
+                    const float *src_nrm, const float *trg_xyz, const float *trg_nrm, const fmm_options *opt,
+                    void *hip_stream, fmm_plan *out) {
+    return guarded([&] {
+        using namespace fmm;
+        FMM_REQUIRE(out != nullptr, "fmm_setup_batch: out is NULL");
+        *out = nullptr;
+        check_options(opt);
+        FMM_REQUIRE(n_inst >= 1, "fmm_setup_batch: n_inst must be >= 1");
+        FMM_REQUIRE(src_off != nullptr, "fmm_setup_batch: src_off is NULL");
+        FMM_REQUIRE((trg_xyz == nullptr) == (trg_off == nullptr),
+                    "fmm_setup_batch: trg_xyz and trg_off go together");
+        const bool tsm = trg_xyz != nullptr;
+        std::vector<int64_t> so(src_off, src_off + n_inst + 1), to(n_inst + 1, 0);
+        if (tsm) to.assign(trg_off, trg_off + n_inst + 1);
+        FMM_REQUIRE(so[0] == 0 && to[0] == 0, "fmm_setup_batch: offsets must start at 0");
+        for (int i = 0; i < n_inst; ++i) {
+            FMM_REQUIRE(so[i + 1] >= so[i], "fmm_setup_batch: src_off must be nondecreasing");
+            FMM_REQUIRE(to[i + 1] >= to[i], "fmm_setup_batch: trg_off must be nondecreasing");
+        }
+        const int64_t n_src = so[n_inst], n_trg = to[n_inst];
+        FMM_REQUIRE(n_src == 0 || src_xyz != nullptr, "fmm_setup_batch: src_xyz is NULL");
+        FMM_REQUIRE(!(opt->src_kernels & FMM_SRC_DOUBLE) || n_src == 0 || src_nrm != nullptr,
+                    "fmm_setup_batch: the double layer needs source normals");
+        FMM_REQUIRE(n_src + n_trg < (int64_t(1) << 31), "fmm_setup_batch: more than 2^31 - 1 points");
+
+        auto t0 = std::chrono::steady_clock::now();
+        hipStream_t s = as_stream(hip_stream);
+        auto *h = new fmm_plan_s();
+        try {
+            Plan &P = h->p;
+            init_plan(P, opt);
+            const TreeOptions topt = tree_options(opt);
+            std::vector<Tree> parts(n_inst);
+            for (int i = 0; i < n_inst; ++i) {
+                const int64_t ns = so[i + 1] - so[i];
+                const float *sx = src_xyz ? src_xyz + 3 * so[i] : nullptr;
+                const float *sn = src_nrm ? src_nrm + 3 * so[i] : nullptr;
+                const float *tx = tsm ? trg_xyz + 3 * to[i] : nullptr;
+                const float *tn = trg_nrm ? trg_nrm + 3 * (tsm ? to[i] : so[i]) : nullptr;
+                build_tree(parts[i], sx, sn, ns, tx, tn, tsm ? to[i + 1] - to[i] : 0, topt, s);
             }
-            if (trg_nrm && !P.t.tsm && n_src) {
-                P.trg_nrm_user.alloc(3 * (size_t)n_src);
-                FMM_HIP(hipMemcpyAsync(P.trg_nrm_user.p, trg_nrm, 3 * n_src * sizeof(float),
-                                       hipMemcpyDeviceToDevice, s));
-            }
-            if (P.t.nb) plan_build_worklists(P, s);
-            FMM_HIP(hipStreamSynchronize(s));
+            merge_forest(parts, so, to, src_nrm != nullptr, trg_nrm != nullptr, P.t, s);
+            P.n_inst = n_inst;
+            finish_plan(P, opt, trg_nrm, s);
             P.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         } catch (...) {
             delete h;

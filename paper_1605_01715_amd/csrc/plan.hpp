@@ -22,6 +22,7 @@ enum Stage { ST_P2M = 0, ST_M2M, ST_P2L, ST_M2L, ST_L2L, ST_C2E, ST_EVAL, ST_COU
 struct Plan {
     fmm_options opt{};
     int nrhs = 1;
+    int n_inst = 1;  // independent instances (fmm_setup_batch)
     bool sl = true, dl = false, want_pot = true, want_field = false;
     bool alive = true;
     Tree t;

@@ -483,6 +483,192 @@ static void derive_root(const double lo[3], const double hi[3], double x0[3], do
     }
 }
 
+namespace {
+
+__global__ void k_offset_copy(const int64_t *in, int64_t n, int64_t off, int64_t *out) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = in[i] + off;
+}
+
+}  // namespace
+
+void merge_forest(std::vector<Tree> &parts, const std::vector<int64_t> &src_off, const std::vector<int64_t> &trg_off,
+                  bool src_normals, bool trg_normals, Tree &t, hipStream_t s) {
+    const size_t ni = parts.size();
+    FMM_REQUIRE(ni > 0 && src_off.size() == ni + 1 && trg_off.size() == ni + 1, "merge_forest: bad offsets");
+    t = Tree();
+    t.tsm = parts[0].tsm;
+    for (int c = 0; c < 3; ++c) t.x0[c] = parts[0].x0[c];
+    t.w = parts[0].w;
+    // point offsets of each part in the merged sorted arrays
+    std::vector<int64_t> noff(ni + 1, 0), toff(ni + 1, 0), soff(ni + 1, 0);
+    for (size_t i = 0; i < ni; ++i) {
+        noff[i + 1] = noff[i] + parts[i].n;
+        toff[i + 1] = toff[i] + parts[i].n_trg;
+        soff[i + 1] = soff[i] + parts[i].n_src;
+    }
+    t.n = noff[ni];
+    t.n_trg = toff[ni];
+    t.n_src = soff[ni];
+    // level-major box order: level l holds part 0's level-l boxes, then part 1's, ...
+    int nlev = 0;
+    for (auto &p : parts) nlev = std::max(nlev, p.nlev);
+    t.nlev = nlev;
+    auto cnt = [&](size_t i, int l) { return l < parts[i].nlev ? parts[i].lvl_off[l + 1] - parts[i].lvl_off[l] : 0; };
+    std::vector<std::vector<int64_t>> base(ni, std::vector<int64_t>(std::max(nlev, 1), 0));
+    t.lvl_off.assign(nlev + 1, 0);
+    for (int l = 0; l < nlev; ++l) {
+        int64_t o = t.lvl_off[l];
+        for (size_t i = 0; i < ni; ++i) {
+            base[i][l] = o;
+            o += cnt(i, l);
+        }
+        t.lvl_off[l + 1] = o;
+    }
+    const int64_t nb = t.nb = t.lvl_off[nlev];
+    auto nid = [&](size_t i, int32_t b) -> int32_t {
+        if (b < 0) return -1;
+        const int l = parts[i].h_level[b];
+        return (int32_t)(base[i][l] + (b - parts[i].lvl_off[l]));
+    };
+    t.h_level.resize(nb);
+    t.h_parent.resize(nb);
+    t.h_child.resize(8 * nb);
+    t.h_anchor.resize(3 * nb);
+    t.h_begin.resize(nb);
+    t.h_end.resize(nb);
+    t.h_tbeg.resize(nb);
+    t.h_tend.resize(nb);
+    t.h_sbeg.resize(nb);
+    t.h_send.resize(nb);
+    t.h_leaf.resize(nb);
+    t.h_centre.resize(3 * nb);
+    t.h_half.resize(nb);
+    std::vector<int32_t> vd((size_t)kNumDirs * nb);
+    std::vector<int32_t> host_vd;
+    std::vector<int32_t> new_of_old;  // per part
+    for (size_t i = 0; i < ni; ++i) {
+        Tree &p = parts[i];
+        if (p.nb == 0) continue;
+        host_vd.resize((size_t)kNumDirs * p.nb);
+        d2h(host_vd.data(), p.vdense.p, host_vd.size(), s);
+        for (int64_t b = 0; b < p.nb; ++b) {
+            const int64_t q = nid(i, (int32_t)b);
+            t.h_level[q] = p.h_level[b];
+            t.h_parent[q] = nid(i, p.h_parent[b]);
+            for (int c = 0; c < 8; ++c) t.h_child[8 * q + c] = nid(i, p.h_child[8 * b + c]);
+            for (int c = 0; c < 3; ++c) {
+                t.h_anchor[3 * q + c] = p.h_anchor[3 * b + c];
+                t.h_centre[3 * q + c] = p.h_centre[3 * b + c];
+            }
+            t.h_begin[q] = p.h_begin[b] + noff[i];
+            t.h_end[q] = p.h_end[b] + noff[i];
+            t.h_tbeg[q] = p.h_tbeg[b] + toff[i];
+            t.h_tend[q] = p.h_tend[b] + toff[i];
+            t.h_sbeg[q] = p.h_sbeg[b] + soff[i];
+            t.h_send[q] = p.h_send[b] + soff[i];
+            t.h_leaf[q] = p.h_leaf[b];
+            t.h_half[q] = p.h_half[b];
+            for (int d = 0; d < kNumDirs; ++d)
+                vd[(size_t)q * kNumDirs + d] = nid(i, host_vd[(size_t)b * kNumDirs + d]);
+        }
+    }
+    // lists, rebuilt in the merged box order
+    auto merge_csr = [&](Csr Tree::*which, Csr &out) {
+        std::vector<int32_t> count(nb, 0);
+        std::vector<std::pair<size_t, int32_t>> owner(nb);  // merged box -> (part, old box)
+        for (size_t i = 0; i < ni; ++i)
+            for (int64_t b = 0; b < parts[i].nb; ++b) owner[nid(i, (int32_t)b)] = {i, (int32_t)b};
+        out.h_off.assign(nb + 1, 0);
+        for (int64_t q = 0; q < nb; ++q) {
+            const Csr &c = parts[owner[q].first].*which;
+            const int32_t b = owner[q].second;
+            out.h_off[q + 1] = out.h_off[q] + (c.h_off[b + 1] - c.h_off[b]);
+        }
+        out.h_idx.resize(out.h_off[nb]);
+        for (int64_t q = 0; q < nb; ++q) {
+            const size_t i = owner[q].first;
+            const Csr &c = parts[i].*which;
+            const int32_t b = owner[q].second;
+            int32_t o = out.h_off[q];
+            for (int32_t k = c.h_off[b]; k < c.h_off[b + 1]; ++k) out.h_idx[o++] = nid(i, c.h_idx[k]);
+            // merged ids keep each part's order within a level; keep lists sorted
+            std::sort(out.h_idx.begin() + out.h_off[q], out.h_idx.begin() + out.h_off[q + 1]);
+        }
+        out.total = out.h_off[nb];
+        out.off = upload(out.h_off, s);
+        out.idx = upload(out.h_idx, s);
+    };
+    merge_csr(&Tree::U, t.U);
+    merge_csr(&Tree::V, t.V);
+    merge_csr(&Tree::W, t.W);
+    merge_csr(&Tree::X, t.X);
+
+    // device box arrays
+    t.level = upload(t.h_level, s);
+    t.parent = upload(t.h_parent, s);
+    t.child = upload(t.h_child, s);
+    t.anchor = upload(t.h_anchor, s);
+    t.begin = upload(t.h_begin, s);
+    t.end = upload(t.h_end, s);
+    t.tbeg = upload(t.h_tbeg, s);
+    t.tend = upload(t.h_tend, s);
+    t.sbeg = upload(t.h_sbeg, s);
+    t.send = upload(t.h_send, s);
+    t.leaf = upload(t.h_leaf, s);
+    t.centre = upload(t.h_centre, s);
+    t.half = upload(t.h_half, s);
+    t.vdense = upload(vd, s);
+
+    // sorted point data, concatenated; permutations shifted to the caller's indices
+    auto cat_f = [&](DBuf<float> Tree::*m, int64_t total, const std::vector<int64_t> &off, DBuf<float> &out) {
+        out.alloc(total);
+        for (size_t i = 0; i < ni; ++i) {
+            const DBuf<float> &b = parts[i].*m;
+            const int64_t n = off[i + 1] - off[i];
+            if (n && b.p) FMM_HIP(hipMemcpyAsync(out.p + off[i], b.p, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+        }
+    };
+    auto cat_perm = [&](DBuf<int64_t> Tree::*m, int64_t total, const std::vector<int64_t> &off,
+                        const std::vector<int64_t> &user_off, DBuf<int64_t> &out) {
+        out.alloc(total);
+        for (size_t i = 0; i < ni; ++i) {
+            const int64_t n = off[i + 1] - off[i];
+            if (!n) continue;
+            hipLaunchKernelGGL(k_offset_copy, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, (parts[i].*m).p, n,
+                               user_off[i], out.p + off[i]);
+            FMM_HIP(hipGetLastError());
+        }
+    };
+    cat_f(&Tree::sx, t.n_src, soff, t.sx);
+    cat_f(&Tree::sy, t.n_src, soff, t.sy);
+    cat_f(&Tree::sz, t.n_src, soff, t.sz);
+    if (src_normals) {
+        cat_f(&Tree::snx, t.n_src, soff, t.snx);
+        cat_f(&Tree::sny, t.n_src, soff, t.sny);
+        cat_f(&Tree::snz, t.n_src, soff, t.snz);
+    }
+    cat_perm(&Tree::src_perm, t.n_src, soff, src_off, t.src_perm);
+    if (t.tsm) {
+        cat_f(&Tree::tx, t.n_trg, toff, t.tx);
+        cat_f(&Tree::ty, t.n_trg, toff, t.ty);
+        cat_f(&Tree::tz, t.n_trg, toff, t.tz);
+        cat_perm(&Tree::trg_perm, t.n_trg, toff, trg_off, t.trg_perm);
+    }
+    if (trg_normals) {
+        cat_f(&Tree::tnx, t.n_trg, toff, t.tnx);
+        cat_f(&Tree::tny, t.n_trg, toff, t.tny);
+        cat_f(&Tree::tnz, t.n_trg, toff, t.tnz);
+    }
+    t.keys.alloc(t.n);
+    for (size_t i = 0; i < ni; ++i)
+        if (parts[i].n)
+            FMM_HIP(hipMemcpyAsync(t.keys.p + noff[i], parts[i].keys.p, parts[i].n * sizeof(uint64_t),
+                                   hipMemcpyDeviceToDevice, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    parts.clear();
+}
+
 void build_tree(Tree &t, const float *src, const float *src_nrm, int64_t n_src, const float *trg,
                 const float *trg_nrm, int64_t n_trg, const TreeOptions &opt, hipStream_t s) {
     t.tsm = trg != nullptr;

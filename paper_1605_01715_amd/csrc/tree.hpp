@@ -1,6 +1,8 @@
 // Octree and interaction lists on the device.
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace fmm {
@@ -61,6 +63,16 @@ struct Tree {
 // NULL (targets = sources). Throws fmm::Error.
 void build_tree(Tree &t, const float *src, const float *src_nrm, int64_t n_src, const float *trg,
                 const float *trg_nrm, int64_t n_trg, const TreeOptions &opt, hipStream_t s);
+
+// Forest of independent instances: `parts` are trees built separately on
+// consecutive slices of the caller's arrays (part i's sources start at user
+// index src_off[i], its targets at trg_off[i]). The result is one tree whose
+// boxes are ordered by level, then by instance, with every index (boxes,
+// point ranges, permutations back to the caller's order) shifted so the plan
+// treats the batch as one box set; no list ever links two instances. The
+// root cube reported is part 0's. `parts` is consumed.
+void merge_forest(std::vector<Tree> &parts, const std::vector<int64_t> &src_off, const std::vector<int64_t> &trg_off,
+                  bool src_normals, bool trg_normals, Tree &out, hipStream_t s);
 
 // Device check that coordinates (and normals) are finite; returns false if not.
 bool all_finite(const float *a, int64_t n3, hipStream_t s);
