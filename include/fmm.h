@@ -232,6 +232,17 @@ int fmm_unit_surface(int p, double *out, int *ns);
  * (hipEvents recorded on the apply's stream; the apply then waits for them). */
 int fmm_set_timing(fmm_plan plan, int enable);
 
+/* Turn graph replay on or off for later applies of this plan. When on, the
+ * first fmm_apply records the whole apply (every kernel of every stage) into
+ * a HIP graph and later calls with the same density and output pointers
+ * replay it with one launch; other pointers re-record it. The graph runs on a
+ * stream the plan owns, ordered after the work already queued on the
+ * caller's stream and before the work queued after the call, so the call
+ * behaves like the ordinary apply. While stage timing is on (fmm_set_timing)
+ * applies run the ordinary way. Turning it off releases the graph. gmres_solve
+ * replays one graph per solve for its matvecs. */
+int fmm_set_graph(fmm_plan plan, int enable);
+
 /*
  * Copy per-box check potentials of the last apply to host memory, rhs 0.
  * The far field is carried in compressed form (r values per box, see

@@ -20,7 +20,7 @@ from ._lib import (FMM_ERR_ARG, FMM_ERR_DEVICE, FMM_ERR_NOMEM, FMM_ERR_NOT_CONVE
 
 __all__ = ["fmm_setup_batch", "Plan", "FmmError", "fmm_default_options", "fmm_setup", "fmm_apply", "gmres_solve", "fmm_destroy",
            "fmm_last_error", "fmm_direct", "fmm_plan_info", "fmm_export_tree", "fmm_export_stage",
-           "fmm_set_timing", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "library_path"]
+           "fmm_set_timing", "fmm_set_graph", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "library_path"]
 
 
 class FmmError(RuntimeError):
@@ -212,6 +212,10 @@ def fmm_export_stage(plan, which):
     out = np.zeros((info["n_boxes"], info["n_surface"]), np.float32)
     _check(L.load().fmm_export_stage(plan.handle, int(which), out.ctypes.data))
     return out
+
+
+def fmm_set_graph(plan, enable=True):
+    _check(L.load().fmm_set_graph(plan.handle, int(bool(enable))))
 
 
 def fmm_set_timing(plan, enable=True):

@@ -250,7 +250,19 @@ int fmm_apply(fmm_plan plan, const float *q, const float *mu, float *pot, float 
         if (P.timing && !P.ev[0]) {
             for (auto &e : P.ev) FMM_HIP(hipEventCreate(&e));
         }
-        plan_apply(P, q, mu, pot, field, s);
+        if (P.graph.enabled && !P.timing)  // stage timing needs the ordinary apply
+            plan_apply_graph(P, q, mu, pot, field, s);
+        else
+            plan_apply(P, q, mu, pot, field, s);
+    });
+}
+
+int fmm_set_graph(fmm_plan plan, int enable) {
+    return guarded([&] {
+        using namespace fmm;
+        Plan &P = live(plan);
+        P.graph.enabled = enable != 0;
+        if (!P.graph.enabled) plan_release_graph(P);
     });
 }
 
@@ -289,6 +301,7 @@ int gmres_solve(fmm_plan plan, const fmm_operator *op, const double *b, double *
 int fmm_destroy(fmm_plan plan) {
     if (!plan) return FMM_OK;
     return guarded([&] {
+        fmm::plan_release_graph(plan->p);
         for (auto &e : plan->p.ev)
             if (e) (void)hipEventDestroy(e);
         plan->p.alive = false;

@@ -106,10 +106,15 @@ struct Gmres {
     void matvec(const double *x, double *y) {
         hipLaunchKernelGGL(k_density, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, x, op.w, dens.p, n);
         FMM_HIP(hipGetLastError());
-        if (op.kind == FMM_OP_FK)
-            plan_apply(P, nullptr, dens.p, pot.p, nullptr, s);
+        // the same buffers every iteration: with graph replay on, one capture per solve
+        const float *q = op.kind == FMM_OP_FK ? nullptr : dens.p;
+        const float *mu = op.kind == FMM_OP_FK ? dens.p : nullptr;
+        float *pt = op.kind == FMM_OP_FK ? pot.p : nullptr;
+        float *fd = op.kind == FMM_OP_FK ? nullptr : field.p;
+        if (P.graph.enabled && !P.timing)
+            plan_apply_graph(P, q, mu, pt, fd, s);
         else
-            plan_apply(P, dens.p, nullptr, nullptr, field.p, s);
+            plan_apply(P, q, mu, pt, fd, s);
         hipLaunchKernelGGL(k_finish, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, op.kind, x, op.a, op.c, pot.p,
                            field.p, P.trg_nrm_user.p, y, n);
         FMM_HIP(hipGetLastError());

@@ -23,6 +23,12 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// plain fill (a memset node does not replay reliably inside captured graphs)
+__global__ void k_zero(float *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
 __global__ void k_sort_densities(const int64_t *perm, int64_t n, int nrhs, const float *q, const float *mu,
                                  const float *nx, const float *ny, const float *nz, float *qs, float *mx, float *my,
                                  float *mz) {
@@ -431,7 +437,7 @@ static void run_gemm(GemmJob &j, const double *mats, int m_pad, int k_pad, const
     box_gemm_f64(a, s);
 }
 
-void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s) {
+void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s, bool capturing) {
     Tree &t = P.t;
     const int nrhs = P.nrhs;
     const Operators &op = *P.ops;
@@ -442,7 +448,10 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     hipLaunchKernelGGL(k_sort_densities, dim3(grid_for(t.n_src, kBlock)), dim3(kBlock), 0, s, t.src_perm.p, t.n_src,
                        nrhs, q, mu, t.snx.p, t.sny.p, t.snz.p, P.q_sorted.p, P.mx.p, P.my.p, P.mz.p);
     FMM_HIP(hipGetLastError());
-    if (P.dt.n) FMM_HIP(hipMemsetAsync(P.dt.p, 0, P.dt.bytes(), s));
+    if (P.dt.n) {
+        hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)P.dt.n, kBlock)), dim3(kBlock), 0, s, P.dt.p, (int64_t)P.dt.n);
+        FMM_HIP(hipGetLastError());
+    }
     const int np = P.n_pad, rp = P.r_pad;
 
     PointSrc src;
@@ -526,15 +535,66 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     e.field = field;
     eval_leaves(nrhs, sl, dl, e, g, src, s);
     mark(ST_COUNT);
-    if (P.timing) {
-        FMM_HIP(hipEventSynchronize(P.ev[ST_COUNT]));
-        for (int k = 0; k < ST_COUNT; ++k) {
-            float ms = 0.f;
-            FMM_HIP(hipEventElapsedTime(&ms, P.ev[k], P.ev[k + 1]));
-            P.stage_ms[k] = ms;
-        }
-        P.have_times = true;
+    if (P.timing && !capturing) plan_collect_times(P);
+}
+
+void plan_collect_times(Plan &P) {
+    FMM_HIP(hipEventSynchronize(P.ev[ST_COUNT]));
+    for (int k = 0; k < ST_COUNT; ++k) {
+        float ms = 0.f;
+        FMM_HIP(hipEventElapsedTime(&ms, P.ev[k], P.ev[k + 1]));
+        P.stage_ms[k] = ms;
     }
+    P.have_times = true;
+}
+
+void plan_apply_graph(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s) {
+    auto &G = P.graph;
+    const std::array<const void *, 4> key = {q, mu, pot, field};
+    if (!G.stream) {
+        FMM_HIP(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
+        FMM_HIP(hipEventCreateWithFlags(&G.in, hipEventDisableTiming));
+        FMM_HIP(hipEventCreateWithFlags(&G.out, hipEventDisableTiming));
+    }
+    if (!G.exec || G.key != key) {
+        if (G.exec) {
+            FMM_HIP(hipGraphExecDestroy(G.exec));
+            G.exec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        FMM_HIP(hipStreamBeginCapture(G.stream, hipStreamCaptureModeThreadLocal));
+        try {
+            plan_apply(P, q, mu, pot, field, G.stream, true);
+        } catch (...) {
+            (void)hipStreamEndCapture(G.stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        FMM_HIP(hipStreamEndCapture(G.stream, &graph));
+        const hipError_t e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        FMM_HIP(e);
+        G.key = key;
+    }
+    // the graph runs on the plan's stream, ordered after the caller's work
+    // and before whatever the caller queues next
+    FMM_HIP(hipEventRecord(G.in, s));
+    FMM_HIP(hipStreamWaitEvent(G.stream, G.in, 0));
+    FMM_HIP(hipGraphLaunch(G.exec, G.stream));
+    FMM_HIP(hipEventRecord(G.out, G.stream));
+    FMM_HIP(hipStreamWaitEvent(s, G.out, 0));
+}
+
+void plan_release_graph(Plan &P) {
+    auto &G = P.graph;
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    if (G.stream) {
+        (void)hipStreamSynchronize(G.stream);
+        (void)hipStreamDestroy(G.stream);
+    }
+    if (G.in) (void)hipEventDestroy(G.in);
+    if (G.out) (void)hipEventDestroy(G.out);
+    G = Plan::Graph{};
 }
 
 }  // namespace fmm

@@ -1,6 +1,7 @@
 // Plan object shared by the API translation units.
 #pragma once
 
+#include <array>
 #include <memory>
 
 #include "gemm.hpp"
@@ -62,6 +63,15 @@ struct Plan {
     int64_t p2m_evals = 0;
     double setup_ms = 0;
 
+    // captured apply (fmm_set_graph): replayed while the argument pointers match
+    struct Graph {
+        bool enabled = false;
+        hipStream_t stream = nullptr;
+        hipEvent_t in = nullptr, out = nullptr;
+        hipGraphExec_t exec = nullptr;
+        std::array<const void *, 4> key{};
+    } graph;
+
     bool timing = false;
     hipEvent_t ev[ST_COUNT + 1] = {};
     double stage_ms[ST_COUNT] = {-1, -1, -1, -1, -1, -1, -1};
@@ -69,7 +79,14 @@ struct Plan {
 };
 
 void plan_build_worklists(Plan &P, hipStream_t s);
-void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s);
+void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s,
+                bool capturing = false);
+// The same apply as one captured HIP graph, replayed when called again with
+// the same pointers (re-captured otherwise). Runs on a plan-owned stream
+// ordered after and before the caller's stream s.
+void plan_apply_graph(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s);
+void plan_collect_times(Plan &P);
+void plan_release_graph(Plan &P);
 void plan_gmres(Plan &P, const fmm_operator &op, const double *b, double *x, double rtol, int restart, int max_iter,
                 int *iters, double *rel_res, int *status, hipStream_t s);
 
