@@ -21,7 +21,19 @@ form the GPU library's GMRES operator takes:
   c = deps, w = area. Right-hand side (Eq. rhs, no free charges, uniform
   field E0): b = -deps E0 . n.
 
-Pins: tests/test_oracle_operators.py (sphere closed forms in closed_forms).
+  Free charges and body forces (Sec. II.C, Eqs. rhs, Ef and the force
+  integral): with free surface charge sigma_f on the bodies (a charge Q_i on
+  sphere i of radius r_i is sigma_f = Q_i / (4 pi r_i^2)) and an optional
+  uniform external field E0,
+    b = (1 - ebar) sigma_f - deps (n . E_f) - deps (n . E0),
+  E_f the field of sigma_f discretised as Eq. pol_discret (the same self
+  term). The force on body i is the sum over its elements of
+  eps_m sigma_j E_j a_j with sigma = sigma_f + sigma_b and E the field of
+  sigma (with its self term) plus E0.
+
+Pins: tests/test_oracle_operators.py (sphere closed forms in closed_forms,
+Gauss's law for a charged sphere, Coulomb's law for distant spheres, the
+paper's force sign change between two charged dielectric spheres).
 """
 
 from __future__ import annotations
@@ -68,3 +80,37 @@ def dielectric_apply(x, xyz, normals, a, c, w, delta=1e-5, matvec_field=None):
         fld = matvec_field(dens)
     en = np.einsum("ij,ij->i", fld, np.asarray(normals, dtype=np.float64))
     return np.asarray(a, dtype=np.float64) * x + np.asarray(c, dtype=np.float64) * en
+
+
+def surface_field(xyz, normals, areas, curvature, sigma, delta=1e-5, matvec_field=None):
+    """E_j = sum_{k != j} (r_j - r_k) s_k a_k / (4 pi r^3) + s_j sqrt(pi a_j) H_j / (4 pi) n_j."""
+    areas = np.asarray(areas, dtype=np.float64)
+    s = np.asarray(sigma, dtype=np.float64)
+    dens = s * areas
+    if matvec_field is None:
+        _, fld = direct_sum(xyz, xyz, dens, None, delta, potential=False, field=True)
+    else:
+        fld = matvec_field(dens)
+    self_term = s * np.sqrt(np.pi * areas) * np.asarray(curvature, dtype=np.float64) / (4.0 * np.pi)
+    return fld + self_term[:, None] * np.asarray(normals, dtype=np.float64)
+
+
+def dielectric_rhs_free(xyz, normals, areas, curvature, sigma_f, eps_i, eps_m, e0=None, delta=1e-5):
+    """b = (1 - ebar) sigma_f - deps n . (E_f + E0)  (Eq. rhs with Eq. Ef, no volume charge)."""
+    eps_i = np.asarray(eps_i, dtype=np.float64)
+    ebar = 0.5 * (eps_i + eps_m)
+    deps = eps_m - eps_i
+    nrm = np.asarray(normals, dtype=np.float64)
+    ef = surface_field(xyz, nrm, areas, curvature, sigma_f, delta)
+    if e0 is not None:
+        ef = ef + np.asarray(e0, dtype=np.float64)
+    return (1.0 - ebar) * np.asarray(sigma_f, dtype=np.float64) - deps * np.einsum("ij,ij->i", ef, nrm)
+
+
+def body_forces(xyz, normals, areas, curvature, sigma, eps_m, body_off, e0=None, delta=1e-5):
+    """F_i = sum_{j in body i} eps_m sigma_j E_j a_j; bodies are the index ranges body_off[i]..body_off[i+1]."""
+    e = surface_field(xyz, normals, areas, curvature, sigma, delta)
+    if e0 is not None:
+        e = e + np.asarray(e0, dtype=np.float64)
+    f = eps_m * (np.asarray(sigma, dtype=np.float64) * np.asarray(areas, dtype=np.float64))[:, None] * e
+    return np.array([f[body_off[i]:body_off[i + 1]].sum(axis=0) for i in range(len(body_off) - 1)])

@@ -108,3 +108,63 @@ def test_ellipsoid_demag_factors():
     n = CF.ellipsoid_demag((2.0, 1.0, 0.5))
     assert n.sum() == pytest.approx(1.0, abs=1e-10)
     assert n[0] < n[1] < n[2]
+
+
+def _two_spheres(d, freq, eps=15.0, eps_m=1.0, charges=(1.0, 10.0)):
+    """Two unit spheres on the x axis, centres -d/2 and +d/2, free charges
+    charges[i] spread uniformly (sigma_f = Q / (4 pi r^2), Sec. II.C)."""
+    parts = [W.sphere_quadrature(freq, np.array([sx, 0.0, 0.0]), 1.0) for sx in (-d / 2, d / 2)]
+    xyz = np.concatenate([p[0] for p in parts]).astype(np.float64)
+    nrm = np.concatenate([p[1] for p in parts]).astype(np.float64)
+    a = np.concatenate([p[2] for p in parts]).astype(np.float64)
+    n1 = len(parts[0][2])
+    sf = np.concatenate([np.full(n1, charges[0] / (4 * np.pi)), np.full(len(a) - n1, charges[1] / (4 * np.pi))])
+    return xyz, nrm, a, np.ones(len(a)), sf, np.full(len(a), eps), eps_m, [0, n1, len(a)]
+
+
+def _forces(system, rtol=1e-9):
+    xyz, nrm, a, curv, sf, ei, eps_m, off = system
+    A, c, w = OP.dielectric_coeffs(a, curv, ei, eps_m)
+    b = OP.dielectric_rhs_free(xyz, nrm, a, curv, sf, ei, eps_m)
+    sb, it, rr, ok = gmres(lambda s: OP.dielectric_apply(s, xyz, nrm, A, c, w), b, rtol=rtol)
+    assert ok
+    return OP.body_forces(xyz, nrm, a, curv, sf + sb, eps_m, off), sb
+
+
+def test_charged_sphere_gauss_law(sphere):
+    """An isolated sphere with free charge Q in a medium eps_m carries total
+    charge Q / eps_m: sigma_b = (1/eps_m - 1) sigma_f, uniform."""
+    xyz, nrm, w = sphere
+    n = len(w)
+    eps_i, eps_m = 5.0, 2.0
+    sf = np.full(n, 3.0 / (4 * np.pi))
+    ei = np.full(n, eps_i)
+    a, c, ww = OP.dielectric_coeffs(w, np.ones(n), ei, eps_m)
+    b = OP.dielectric_rhs_free(xyz, nrm, w, np.ones(n), sf, ei, eps_m)
+    sb, it, rr, ok = gmres(lambda s: OP.dielectric_apply(s, xyz, nrm, a, c, ww), b, rtol=1e-10)
+    assert ok
+    assert D.rel_l2(sb, (1.0 / eps_m - 1.0) * sf) < 5e-3
+
+
+def test_distant_charged_spheres_coulomb():
+    """Far apart, the force is Coulomb's in the medium, Q1 Q2 / (4 pi eps_m d^2),
+    and the two forces balance."""
+    q1, q2, eps_m, d = 2.0, 3.0, 1.5, 12.0
+    (f1, f2), _ = _forces(_two_spheres(d, 8, eps=4.0, eps_m=eps_m, charges=(q1, q2)))
+    coulomb = q1 * q2 / (4 * np.pi * eps_m * d * d)
+    assert abs(f2[0] / coulomb - 1.0) < 1e-2
+    assert np.linalg.norm(f1 + f2) < 1e-3 * coulomb
+    assert abs(f2[1]) + abs(f2[2]) < 1e-3 * coulomb
+
+
+def test_two_dielectric_spheres_force_sign_change():
+    """Like-charged polarisable spheres (eps 15, charges q and 10q, eps_m 1)
+    attract when close: the force changes sign at the separation the paper
+    prints (Sec. IV.B), located by linear interpolation of the force."""
+    d_paper = _paper("force_sign_change_separation")
+    ds = [2.6, 2.7, 2.8, 2.9]
+    fx = [_forces(_two_spheres(d, 8))[0][1][0] for d in ds]
+    assert fx[0] < 0 and fx[-1] > 0
+    k = next(i for i in range(len(ds) - 1) if fx[i] < 0 <= fx[i + 1])
+    root = ds[k] + (ds[k + 1] - ds[k]) * (-fx[k]) / (fx[k + 1] - fx[k])
+    assert abs(root - d_paper) < 0.03, root
