@@ -167,6 +167,37 @@ int gmres_solve(fmm_plan plan, const fmm_operator *op, const double *b, double *
                 double rtol, int restart, int max_iter, int *iters, double *rel_res,
                 void *hip_stream);
 
+/*
+ * Dielectric bodies around the solve (Sec. II.C, epsilon_0 = 1). The plan must
+ * be single-layer with field output, targets = sources, nrhs = 1, and target
+ * normals given at setup (the element normals). The field of a surface charge
+ * s at element j is the plan's field of s.a plus the self-patch term
+ * s_j sqrt(pi a_j) H_j / (4 pi) n_j (Eq. pol_discret, the reading of the
+ * garbled term as the principal-value field of a uniformly charged cap).
+ *
+ * fmm_dielectric_rhs: b = (1 - ebar) sigma_f - deps n . (E_f + E0)
+ *   (Eq. rhs with Eq. Ef and no volume charge; ebar = (eps_i + eps_m)/2,
+ *   deps = eps_m - eps_i; a charge Q on a sphere of radius r is
+ *   sigma_f = Q / (4 pi r^2)).
+ *   sigma_f, areas, curvature (mean curvature H), eps_i: device float [n];
+ *   eps_m: medium permittivity; e0: host double [3] uniform external field or
+ *   NULL; b: device double [n], written. Synchronous on the stream.
+ * fmm_body_forces: F_i = sum over the elements of body i of
+ *   eps_m s_j a_j (E_j + E0), s = sigma_f + sigma_b, E the field of s
+ *   (Sec. II.C, force density eps_m sigma E).
+ *   sigma_b: device float [n] or NULL; body i is elements
+ *   body_off[i] .. body_off[i+1] - 1 (host int64 [n_body + 1], from 0 to n,
+ *   nondecreasing); forces: host double [n_body][3], written. Per-body sums
+ *   run in a fixed order (deterministic).
+ * Errors: FMM_ERR_ARG for NULL arguments, eps_m <= 0, a plan of the wrong kind
+ * and bad body offsets.
+ */
+int fmm_dielectric_rhs(fmm_plan plan, const float *sigma_f, const float *areas, const float *curvature,
+                       const float *eps_i, float eps_m, const double *e0, double *b, void *hip_stream);
+int fmm_body_forces(fmm_plan plan, const float *sigma_f, const float *sigma_b, const float *areas,
+                    const float *curvature, float eps_m, const double *e0, int n_body, const int64_t *body_off,
+                    double *forces, void *hip_stream);
+
 /* Release the plan and its device memory. NULL is a no-op. */
 int fmm_destroy(fmm_plan plan);
 

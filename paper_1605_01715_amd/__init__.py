@@ -20,7 +20,7 @@ from ._lib import (FMM_ERR_ARG, FMM_ERR_DEVICE, FMM_ERR_NOMEM, FMM_ERR_NOT_CONVE
 
 __all__ = ["fmm_setup_batch", "Plan", "FmmError", "fmm_default_options", "fmm_setup", "fmm_apply", "gmres_solve", "fmm_destroy",
            "fmm_last_error", "fmm_direct", "fmm_plan_info", "fmm_export_tree", "fmm_export_stage",
-           "fmm_set_timing", "fmm_set_graph", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "library_path"]
+           "fmm_set_timing", "fmm_set_graph", "fmm_dielectric_rhs", "fmm_body_forces", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "library_path"]
 
 
 class FmmError(RuntimeError):
@@ -211,6 +211,38 @@ def fmm_export_stage(plan, which):
     info = fmm_plan_info(plan)
     out = np.zeros((info["n_boxes"], info["n_surface"]), np.float32)
     _check(L.load().fmm_export_stage(plan.handle, int(which), out.ctypes.data))
+    return out
+
+
+def fmm_dielectric_rhs(plan, sigma_f, areas, curvature, eps_i, eps_m, e0=None, b=None, stream=None):
+    """Right-hand side of the dielectric system with free charges; returns b (device float64)."""
+    import numpy as np
+    import torch
+
+    f32 = torch.float32
+    if b is None:
+        b = torch.empty(sigma_f.shape[0], dtype=torch.float64, device=sigma_f.device)
+    e = np.ascontiguousarray(np.asarray(e0, dtype=np.float64)) if e0 is not None else None
+    _check(L.load().fmm_dielectric_rhs(plan.handle, _ptr(sigma_f, f32, "sigma_f"), _ptr(areas, f32, "areas"),
+                                       _ptr(curvature, f32, "curvature"), _ptr(eps_i, f32, "eps_i"), float(eps_m),
+                                       e.ctypes.data if e is not None else None, _ptr(b, torch.float64, "b"),
+                                       _stream(stream)))
+    return b
+
+
+def fmm_body_forces(plan, sigma_f, sigma_b, areas, curvature, eps_m, body_off, e0=None, stream=None):
+    """Forces on the bodies (host float64 [n_body, 3])."""
+    import numpy as np
+    import torch
+
+    f32 = torch.float32
+    off = np.ascontiguousarray(np.asarray(body_off, dtype=np.int64))
+    out = np.zeros((len(off) - 1, 3))
+    e = np.ascontiguousarray(np.asarray(e0, dtype=np.float64)) if e0 is not None else None
+    _check(L.load().fmm_body_forces(plan.handle, _ptr(sigma_f, f32, "sigma_f"), _ptr(sigma_b, f32, "sigma_b"),
+                                    _ptr(areas, f32, "areas"), _ptr(curvature, f32, "curvature"), float(eps_m),
+                                    e.ctypes.data if e is not None else None, len(off) - 1, off.ctypes.data,
+                                    out.ctypes.data, _stream(stream)))
     return out
 
 

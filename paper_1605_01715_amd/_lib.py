@@ -60,6 +60,10 @@ SIGNATURES = {
     "fmm_plan_info": (c_int, [c_void_p, ctypes.POINTER(FmmInfo)]),
     "fmm_export_tree": (c_int, [c_void_p, ctypes.POINTER(FmmTreeExport)]),
     "fmm_set_graph": (c_int, [c_void_p, c_int]),
+    "fmm_dielectric_rhs": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_void_p,
+                                   c_void_p]),
+    "fmm_body_forces": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_int,
+                                c_void_p, c_void_p, c_void_p]),
     "fmm_set_timing": (c_int, [c_void_p, c_int]),
     "fmm_export_stage": (c_int, [c_void_p, c_int, c_void_p]),
     "fmm_stage_times": (c_int, [c_void_p, ctypes.POINTER(c_double)]),

@@ -87,6 +87,13 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
 void plan_apply_graph(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s);
 void plan_collect_times(Plan &P);
 void plan_release_graph(Plan &P);
+// Dielectric problem (Sec. II.C): right-hand side with free charges (Eq. rhs)
+// into device b, and per-body forces eps_m sigma E a (sigma = sigma + sigma2,
+// sigma2 may be NULL) summed over the bodies' index ranges into host forces.
+void dielectric_rhs(Plan &P, const float *sigma_f, const float *areas, const float *curv, const float *eps_i,
+                    double eps_m, const double *e0, double *b, hipStream_t s);
+void body_forces(Plan &P, const float *sigma, const float *sigma2, const float *areas, const float *curv,
+                 double eps_m, const double *e0, int n_body, const int64_t *body_off, double *forces, hipStream_t s);
 void plan_gmres(Plan &P, const fmm_operator &op, const double *b, double *x, double rtol, int restart, int max_iter,
                 int *iters, double *rel_res, int *status, hipStream_t s);
 
