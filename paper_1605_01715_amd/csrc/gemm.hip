@@ -24,14 +24,21 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 
+// The tile's source vectors of one term are staged in LDS whole (float32,
+// [k][column], one barrier pair per term), and the matrix fragments of the
+// next 16-k chunk are loaded while the current chunk's MFMAs run.
+constexpr int kMaxK = 512;
+constexpr int kBStr = kGemmCols + 4;  // floats per k row in LDS
+
 template <int MAXRB>
 __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmLaunch a) {
-    constexpr int NCOL = kGemmCols, KC = 16, BSTR = 48;
-    __shared__ double Bs[KC * BSTR];
+    constexpr int NCOL = kGemmCols;
+    extern __shared__ float Bs[];  // [k_pad][kBStr]
     __shared__ int32_t cols[NCOL], srcs[NCOL];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int64_t tile = blockIdx.x;
-    const int nrb = a.m_pad / 16, nkc = a.k_pad / KC;
+    const int nrb = a.m_pad / 16, K = a.k_pad, nkc = K / 16;
     if (t < NCOL) cols[t] = a.tile_cols[tile * NCOL + t];
     f64x4 acc[MAXRB][2];
 #pragma unroll
@@ -47,30 +54,50 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmLaunch a) {
         if (!__syncthreads_or(mysrc >= 0)) continue;
         const int mat = a.term_mat ? a.term_mat[tile * a.nterm + term] : term;
         const double *M = a.mats + (size_t)mat * a.mat_elems;
-        for (int kc = 0; kc < nkc; ++kc) {
-            {
-                const int col = t >> 3, k2 = (t & 7) * 2;
-                const int sidx = srcs[col];
-                float2 x = make_float2(0.f, 0.f);
-                if (sidx >= 0) x = *(const float2 *)(a.in + (size_t)sidx * a.k_pad + kc * KC + k2);
-                Bs[k2 * BSTR + col] = (double)x.x;
-                Bs[(k2 + 1) * BSTR + col] = (double)x.y;
-            }
-            __syncthreads();
-            double bf[4][2];
-            for (int s = 0; s < 4; ++s)
-                for (int cb = 0; cb < 2; ++cb) bf[s][cb] = Bs[(4 * s + (lane >> 4)) * BSTR + cb * 16 + (lane & 15)];
+        // stage all K values of the 32 source vectors, transposed
+        const int kq = K / 4;
+        for (int idx = t; idx < NCOL * kq; idx += kThreads) {
+            const int col = idx / kq, k4 = (idx % kq) * 4;
+            const int sidx = srcs[col];
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (sidx >= 0) x = *(const float4 *)(a.in + (size_t)sidx * K + k4);
+            Bs[(k4 + 0) * kBStr + col] = x.x;
+            Bs[(k4 + 1) * kBStr + col] = x.y;
+            Bs[(k4 + 2) * kBStr + col] = x.z;
+            Bs[(k4 + 3) * kBStr + col] = x.w;
+        }
+        __syncthreads();
+        // matrix fragments: av[i][s] for row block w + 4 i, chunk kc
+        double av0[MAXRB][4], av1[MAXRB][4];
+        auto load_av = [&](double (&av)[MAXRB][4], int kc) {
 #pragma unroll
             for (int i = 0; i < MAXRB; ++i) {
-                const int rb = w + 4 * i;
-                if (rb >= nrb) continue;
+                const int rb = min(w + 4 * i, nrb - 1);  // clamped rows are loaded, never used
                 const double *ap = M + (((size_t)rb * nkc + kc) * 64 + lane) * 4;
-                const double av[4] = {ap[0], ap[1], ap[2], ap[3]};
+                for (int s = 0; s < 4; ++s) av[i][s] = ap[s];
+            }
+        };
+        auto mma = [&](const double (&av)[MAXRB][4], int kc) {
+            double bf[4][2];
+            for (int s = 0; s < 4; ++s)
+                for (int cb = 0; cb < 2; ++cb)
+                    bf[s][cb] = (double)Bs[(kc * 16 + 4 * s + (lane >> 4)) * kBStr + cb * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < MAXRB; ++i) {
+                if (w + 4 * i >= nrb) continue;
                 for (int s = 0; s < 4; ++s)
                     for (int cb = 0; cb < 2; ++cb)
-                        acc[i][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bf[s][cb], acc[i][cb], 0, 0, 0);
+                        acc[i][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s], bf[s][cb], acc[i][cb], 0, 0, 0);
             }
-            __syncthreads();
+        };
+        load_av(av0, 0);
+        for (int kc = 0; kc < nkc; kc += 2) {
+            if (kc + 1 < nkc) load_av(av1, kc + 1);
+            mma(av0, kc);
+            if (kc + 1 < nkc) {
+                if (kc + 2 < nkc) load_av(av0, kc + 2);
+                mma(av1, kc + 1);
+            }
         }
     }
 #pragma unroll
@@ -151,13 +178,20 @@ __global__ __launch_bounds__(256) void k_dgemm(const double *A, size_t sa, const
 
 void box_gemm_f64(const GemmLaunch &a, hipStream_t s) {
     if (a.ntile <= 0 || a.nterm <= 0) return;
-    FMM_REQUIRE(a.m_pad % 16 == 0 && a.k_pad % 16 == 0 && a.m_pad <= 512, "box_gemm: unsupported size");
+    FMM_REQUIRE(a.m_pad % 16 == 0 && a.k_pad % 16 == 0 && a.m_pad <= 512 && a.k_pad <= kMaxK,
+                "box_gemm: unsupported size");
     const int per = (a.m_pad / 16 + 3) / 4;
     dim3 g((unsigned)a.ntile), b(kThreads);
-    if (per <= 2) hipLaunchKernelGGL(k_gemm_f64<2>, g, b, 0, s, a);
-    else if (per <= 4) hipLaunchKernelGGL(k_gemm_f64<4>, g, b, 0, s, a);
-    else if (per <= 6) hipLaunchKernelGGL(k_gemm_f64<6>, g, b, 0, s, a);
-    else hipLaunchKernelGGL(k_gemm_f64<8>, g, b, 0, s, a);
+    const size_t sh = (size_t)a.k_pad * kBStr * sizeof(float);
+    auto go = [&](auto kern) {
+        FMM_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(kMaxK * kBStr * sizeof(float))));
+        hipLaunchKernelGGL(kern, g, b, sh, s, a);
+    };
+    if (per <= 2) go(k_gemm_f64<2>);
+    else if (per <= 4) go(k_gemm_f64<4>);
+    else if (per <= 6) go(k_gemm_f64<6>);
+    else go(k_gemm_f64<8>);
     FMM_HIP(hipGetLastError());
 }
 
