@@ -12,18 +12,23 @@
 // octant; each wave takes one 32-column block and one half of the rows, and
 // the workgroup keeps the r_pad x 128 accumulator in registers across all
 // directions, so every output is written once. Each step of the tile is one
-// (direction, 32-wide k-chunk) or two: the chunk of M_d and the tile's 128
-// source chunks are copied to LDS (double-buffered) and every wave multiplies
+// (direction, 32-wide k-chunk): the chunk of M_d and the tile's 128 source
+// chunks are copied from global memory straight into LDS (global_load_lds,
+// 16 bytes per lane, no registers on the way) and every wave multiplies
 // them. With 32x32 MFMA tiles each staged matrix element is read from LDS once
-// per 32 columns. The next step's loads are issued before the current step's
-// MFMAs. Tiles are dealt to the XCDs so that each XCD runs a contiguous range.
+// per 32 columns. With two LDS buffers (split-BF16) the copies of step s + 1
+// are issued right after the waves have read their step-s fragments into
+// registers, and run under step s's MFMAs; with one (float32), two
+// workgroups share each CU. The tiles of one octant run on one XCD (they
+// share most directions, so concurrently running tiles reuse the matrices in
+// that XCD's L2).
 //
 // The k index inside a chunk is permuted so that every lane's operand is a
-// run of consecutive values (16-byte loads); the dot product is the same.
+// run of consecutive values (16-byte reads); the dot product is the same.
 //
 // Forms:
-//   FP32        v_mfma_f32_32x32x2_f32; the float32 matrix chunk is
-//               rearranged into fragment order on its way to LDS.
+//   FP32        v_mfma_f32_32x32x2_f32; the float32 matrices are stored chunk
+//               by chunk in fragment order (the exact LDS image).
 //   split-BF16  both operands split into three bfloat16 parts x = h + m + l;
 //               the six products hh hm mh mm hl lh are accumulated in float32
 //               with v_mfma_f32_32x32x16_bf16 (the bf16x6 scheme of Henry,
@@ -32,6 +37,8 @@
 //               chunk by chunk in the exact LDS image), the source vectors by
 //               one pass over the upward state per apply. The inner loop is
 //               then only copies and MFMAs.
+#include <type_traits>
+
 #include "m2l.hpp"
 
 namespace fmm {
@@ -63,25 +70,20 @@ __device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
     l = f2bf(r1 - bf2f(m));
 }
 
-// One staged A chunk (r_pad rows x 32 k) in LDS, fragment order:
+// One A chunk (r_pad rows x 32 k) in LDS and in the global image, fragment order:
 //   BF16 (32x32x16): part p, row block rb, k-half h (16 k each), lane, 8 slots;
 //                    element (row, k) -> lane = row % 32 + 32 * ((k % 16) / 8), slot = k % 8
 //   FP32 (32x32x2):  row block rb, lane, 16 slots;
 //                    element (row, k) -> lane = row % 32 + 32 * (k / 16), slot = k % 16
-template <int NRB, bool BF16>
-constexpr int a_chunk_bytes() {
-    return BF16 ? NRB * 32 * KC * 2 * 3 : NRB * 32 * KC * 4;
-}
-
 // Split-BF16 source vector layout: per vector, per 32-k chunk, 3 parts of 32
-// bfloat16 (192 bytes, so one lane's three parts of a run share cache lines).
+// bfloat16 (192 bytes); float32 vectors are plain rows of r_pad values.
 __host__ __device__ constexpr int64_t vec_bf_stride(int r_pad) { return 3 * (int64_t)r_pad; }
 
 // XCD-aware tile order: blocks are dealt to the 8 XCDs round-robin, so
-// block b runs on XCD b % 8. Each XCD gets a contiguous range of tiles
-// (neighbouring target boxes share source vectors in that XCD's L2).
-// XCD x receives cnt(x) blocks and owns tiles [start(x), start(x) + cnt(x)),
-// a bijection of [0, ntile). Returns -1 for blocks beyond it.
+// block b runs on XCD b % 8. XCD x receives cnt(x) blocks and owns tiles
+// [start(x), start(x) + cnt(x)), a bijection of [0, ntile) (the plan pads
+// ntile to a multiple of 8, one range per octant). Returns -1 for blocks
+// beyond it.
 __device__ inline int xcd_tile(int nb, int b) {
     const int per = (nb + 7) / 8;
     const int rem = nb - (per - 1) * 8;
@@ -91,39 +93,48 @@ __device__ inline int xcd_tile(int nb, int b) {
     return k < cnt ? start + k : -1;
 }
 
-// A step covers GPS consecutive 32-k chunks ("granules") of one direction
-// (two when both fit in LDS double-buffered: more MFMA work between two
-// workgroup barriers; the last step of a direction holds fewer granules when
-// GPS does not divide r_pad / 32). Both operands are staged through LDS: each
-// step the workgroup copies the matrix granule and the 128 columns' source
-// granules with contiguous 16-byte pieces (12 or 8 lanes per column, measured
-// 18% faster than every lane gathering its own column), then every wave reads
-// its fragments from LDS. The column stride of the source granule in LDS is
-// padded by 16 bytes so the operand reads of 16 consecutive lanes hit
-// distinct banks.
-template <bool BF16>
-constexpr int b_col_stride() { return BF16 ? 192 + 16 : 128 + 16; }
+typedef __attribute__((address_space(3))) void lds_void;
 
-template <int NRB, bool BF16, int NBUF, int GPS>
+// 16 bytes per lane from global memory to LDS: lane i writes dst + 16 i
+// (dst wave-uniform)
+__device__ inline void copy_to_lds(const void *src, void *dst) {
+    __builtin_amdgcn_global_load_lds(src, (lds_void *)dst, 16, 0, 0);
+}
+
+template <int NRB, bool BF16>
+struct Shape {
+    static constexpr int RP = NRB * 32;
+    static constexpr int RBH = (NRB + 1) / 2;                  // row blocks per wave
+    static constexpr int CHUNK = BF16 ? NRB * 32 * KC * 2 * 3 : NRB * 32 * KC * 4;  // A chunk bytes
+    static constexpr int NIA = CHUNK / 1024;                   // 1 KB copies per A chunk
+    static constexpr int PPC = BF16 ? 12 : 8;                  // 16-byte pieces per column chunk
+    static constexpr int SPC = PPC + 1;                        // LDS slots per column (one pad slot)
+    static constexpr int BSTR = SPC * 16;                      // column stride in LDS: 16 lanes hit distinct banks
+    static constexpr int BCH = kCols * BSTR;                   // B chunk bytes in LDS
+    static constexpr int NIB = kCols * SPC / 64;               // 1 KB copies per B chunk
+    static constexpr int JA = (NIA + 7) / 8, JB = (NIB + 7) / 8;  // copies per wave (at most)
+    static constexpr int LDS2 = 2 * (CHUNK + BCH) + 4 * kNumDirs;
+    // Split-BF16: two buffers when they fit in LDS and a step's fragments in
+    // registers. Float32: one buffer (43 KB at r_pad 192), so two workgroups
+    // share a CU and each covers the other's barriers (measured 6% faster
+    // than two buffers; for split-BF16 two buffers are 6% faster at the
+    // tuned leaf size).
+    static constexpr int NBUF = (BF16 && LDS2 <= 160 * 1024 && RBH * 24 <= 96) ? 2 : 1;
+    static_assert(kCols * SPC % 64 == 0, "B slots must fill whole copies");
+};
+
+template <int NRB, bool BF16>
 __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
-    constexpr int RP = NRB * 32;
-    constexpr int CHUNK = a_chunk_bytes<NRB, BF16>();        // bytes of one A granule in LDS
-    constexpr int NF4 = CHUNK / 16;
-    constexpr int NLOAD = (NF4 + kThreads - 1) / kThreads;
-    constexpr int PART = NRB * 2 * 64 * 8;
-    constexpr int RBH = (NRB + 1) / 2;
-    constexpr int NGR = RP / KC;
-    constexpr int NST = (NGR + GPS - 1) / GPS;
-    constexpr int PPC = BF16 ? 12 : 8;                       // 16-byte pieces per column granule
-    constexpr int NBL = kCols * PPC / kThreads;              // pieces per thread per granule
-    constexpr int BSTR = b_col_stride<BF16>();
-    constexpr int BCH = kCols * BSTR;                        // bytes of one B granule in LDS
-    static_assert(kCols * PPC % kThreads == 0, "B pieces must divide evenly");
-    extern __shared__ __align__(16) unsigned char lds[];
-    unsigned char *ldsA = lds;
-    unsigned char *ldsB = lds + NBUF * GPS * CHUNK;
+    using S = Shape<NRB, BF16>;
+    constexpr int RP = S::RP, RBH = S::RBH, CHUNK = S::CHUNK, NIA = S::NIA, PPC = S::PPC, SPC = S::SPC,
+                  BSTR = S::BSTR, BCH = S::BCH, NIB = S::NIB, JA = S::JA, JB = S::JB, NBUF = S::NBUF;
+    constexpr int PART = NRB * 2 * 64 * 8;  // bfloat16 elements of one part of an A chunk
+    constexpr int NGR = RP / KC;            // steps per direction
+    __shared__ __align__(16) unsigned char sA[NBUF][CHUNK];
+    __shared__ __align__(16) unsigned char sB[NBUF][BCH];
+    __shared__ int32_t s_dir[kNumDirs];
     const int t = threadIdx.x, lane = t & 63;
-    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6) & 7;
     const int hf = lane >> 5, r32 = lane & 31;
     const int cblk = w & 3, rhalf = w >> 2;
     const int rb0 = rhalf * RBH;
@@ -133,22 +144,26 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
     if (tile < 0) return;
     const int64_t toff = a.tile_term_off[tile];
     const int nact = (int)(a.tile_term_off[tile + 1] - toff);
-    const int nsteps = nact * NST;
+    const int nsteps = nact * NGR;
     const int my_col = 32 * cblk + r32;
     const int outv = a.tile_cols[(int64_t)tile * kCols + my_col];
-    __shared__ int32_t s_dir[kNumDirs];
     for (int i = t; i < nact; i += kThreads) s_dir[i] = a.term_dir[toff + i];
-    // B stream: this thread's loader columns and their source indices for the
-    // direction being loaded and the next one; each lane's own column index
-    // only decides whether its wave has any source (skips dead MFMAs)
-    int a_e = 0, a_st = 0, b_e = 0, b_st = 0;
-    int cur_sv[NBL], nxt_sv[NBL], cur_own = -1, nxt_own = -1;
+
+    // B copies: copy i = w + 8 j fills LDS slots 64 i .. 64 i + 63; slot q is
+    // piece q % SPC of column q / SPC (piece PPC is the pad slot). Columns
+    // without a source for the direction, and pad slots, copy zeros.
+    int bcol[JB], bpiece[JB];
 #pragma unroll
-    for (int j = 0; j < NBL; ++j) cur_sv[j] = nxt_sv[j] = -1;
-    auto fetch_src = [&](int e, int (&sv)[NBL], int &own) {
+    for (int j = 0; j < JB; ++j) {
+        const int q = (w + 8 * j) * 64 + lane;
+        bcol[j] = min(q / SPC, kCols - 1);
+        bpiece[j] = q % SPC;
+    }
+    int cur_sv[JB], nxt_sv[JB], cur_own = -1, nxt_own = -1;
+    auto fetch_src = [&](int e, int (&sv)[JB], int &own) {
         const int64_t row = (toff + e) * kCols;
 #pragma unroll
-        for (int j = 0; j < NBL; ++j) sv[j] = a.term_src[row + (t + kThreads * j) / PPC];
+        for (int j = 0; j < JB; ++j) sv[j] = a.term_src[row + bcol[j]];
         own = a.term_src[row + my_col];
     };
     if (nact > 0) {
@@ -162,164 +177,139 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
     for (int i = 0; i < RBH; ++i)
         for (int v = 0; v < 16; ++v) acc[i][v] = 0.f;
 
-    u32x4 ar[GPS][NLOAD];
-    u32x4 br[GPS][NBL];
-    uint32_t bkeep[NBL];
-    bool live_next = false;
-    auto granules = [&](int st) { return min(GPS, NGR - st * GPS); };
-
-    auto load_a = [&]() {
-        const int dir = __builtin_amdgcn_readfirstlane(s_dir[min(a_e, nact - 1)]);
+    // issue the copies of the next step (direction e_ld, chunk st_ld) into buffer BUF
+    int e_ld = 0, st_ld = 0;
+    bool live_q[NBUF];
+    auto issue = [&](auto buf_tag) {
+        constexpr int BUF = decltype(buf_tag)::value;
+        const int dir = __builtin_amdgcn_readfirstlane(s_dir[min(e_ld, nact - 1)]);
+        const int kc = st_ld;
+        const unsigned char *ag = BF16 ? (const unsigned char *)(a.mats_bf + ((int64_t)dir * NGR + kc) * 3 * PART)
+                                       : (const unsigned char *)(a.mats + ((int64_t)dir * NGR + kc) * (CHUNK / 4));
 #pragma unroll
-        for (int g = 0; g < GPS; ++g) {
-            const int kc = a_st * GPS + (a_st * GPS + g < NGR ? g : 0);
-#pragma unroll
-            for (int j = 0; j < NLOAD; ++j) {
-                const int f = min(t + kThreads * j, NF4 - 1);
-                if (BF16) {
-                    ar[g][j] = ((const u32x4 *)(a.mats_bf + ((int64_t)dir * NGR + kc) * 3 * PART))[f];
-                } else {
-                    const int row = f >> 3, k4 = (f & 7) * 4;
-                    ar[g][j] = *(const u32x4 *)(a.mats + ((size_t)dir * RP + row) * RP + kc * KC + k4);
-                }
-            }
-        }
-        if (++a_st == NST) {
-            a_st = 0;
-            ++a_e;
-        }
-    };
-    auto load_b = [&]() {
-#pragma unroll
-        for (int g = 0; g < GPS; ++g) {
-            const int kc = b_st * GPS + (b_st * GPS + g < NGR ? g : 0);
-#pragma unroll
-            for (int j = 0; j < NBL; ++j) {
-                const int piece = (t + kThreads * j) % PPC;
-                const int svl = max(cur_sv[j], 0);
-                if (BF16)
-                    br[g][j] = *(const u32x4 *)(a.in_bf + svl * vec_bf_stride(RP) + kc * 3 * KC + 8 * piece);
-                else
-                    br[g][j] = *(const u32x4 *)(a.in + (size_t)svl * RP + kc * KC + 4 * piece);
-            }
+        for (int j = 0; j < JA; ++j) {
+            const int i = w + 8 * j;
+            if (NIA % 8 != 0 && i >= NIA) continue;  // wave-uniform
+            copy_to_lds(ag + (size_t)i * 1024 + lane * 16, &sA[BUF][i * 1024]);
         }
 #pragma unroll
-        for (int j = 0; j < NBL; ++j) bkeep[j] = cur_sv[j] >= 0 ? 0xffffffffu : 0u;
-        live_next = __ballot(cur_own >= 0) != 0;
-        if (++b_st == NST) {
-            b_st = 0;
-            ++b_e;
+        for (int j = 0; j < JB; ++j) {
+            const int i = w + 8 * j;
+            if (NIB % 8 != 0 && i >= NIB) continue;
+            const int pc = bpiece[j];
+            const unsigned char *src;
+            if (cur_sv[j] < 0 || pc == PPC)
+                src = (const unsigned char *)a.zero + 16 * (pc % PPC);
+            else if (BF16)
+                src = (const unsigned char *)(a.in_bf + cur_sv[j] * vec_bf_stride(RP) + kc * 3 * KC + 8 * pc);
+            else
+                src = (const unsigned char *)(a.in + (size_t)cur_sv[j] * RP + kc * KC + 4 * pc);
+            copy_to_lds(src, &sB[BUF][i * 1024]);
+        }
+        live_q[BUF] = __ballot(cur_own >= 0) != 0;  // does this wave's column block have any source?
+        if (++st_ld == NGR) {
+            st_ld = 0;
+            ++e_ld;
 #pragma unroll
-            for (int j = 0; j < NBL; ++j) cur_sv[j] = nxt_sv[j];
+            for (int j = 0; j < JB; ++j) cur_sv[j] = nxt_sv[j];
             cur_own = nxt_own;
-            if (NST == 1) fetch_src(min(b_e + 1, nact - 1), nxt_sv, nxt_own);
-        } else if (b_st == 1) {
-            fetch_src(min(b_e + 1, nact - 1), nxt_sv, nxt_own);
-        }
-    };
-    auto store_ab = [&](int buf, int ng) {
-#pragma unroll
-        for (int g = 0; g < GPS; ++g) {
-            if (g >= ng) continue;
-            unsigned char *base = ldsA + (buf * GPS + g) * CHUNK;
-#pragma unroll
-            for (int j = 0; j < NLOAD; ++j) {
-                const int f = t + kThreads * j;
-                if (NF4 % kThreads != 0 && f >= NF4) continue;
-                if (BF16) {
-                    ((u32x4 *)base)[f] = ar[g][j];
-                } else {
-                    const int row = f >> 3, k4 = (f & 7) * 4;
-                    const int rb = row >> 5;
-                    const int fl = (row & 31) + 32 * (k4 >> 4), slot = k4 & 15;
-                    *(u32x4 *)((float *)base + (rb * 64 + fl) * 16 + slot) = ar[g][j];
-                }
-            }
-            unsigned char *bb = ldsB + (buf * GPS + g) * BCH;
-#pragma unroll
-            for (int j = 0; j < NBL; ++j) {
-                const int f = t + kThreads * j;
-                *(u32x4 *)(bb + (f / PPC) * BSTR + (f % PPC) * 16) = br[g][j] & bkeep[j];
-            }
+            if (NGR == 1) fetch_src(min(e_ld + 1, nact - 1), nxt_sv, nxt_own);
+        } else if (st_ld == 1) {
+            fetch_src(min(e_ld + 1, nact - 1), nxt_sv, nxt_own);
         }
     };
 
-    bool live = false;
-    if (nsteps > 0) {
-        load_a();
-        load_b();
-        live = live_next;
-        store_ab(0, granules(0));
-    }
-    for (int s = 0; s < nsteps; ++s) {
-        const int buf = NBUF == 2 ? (s & 1) : 0;
-        const int ng = granules(s % NST);
-        const bool live_s = live;
-        __syncthreads();  // A(s), B(s) visible in LDS; every wave is done with the other buffer
-        if (s + 1 < nsteps) {
-            load_a();
-            load_b();
-            live = live_next;
+    // Operand fragments of one step. A read of LDS issued after an LDS copy
+    // waits for that copy, so with two buffers all of a step's fragments are
+    // read before the next step's copies are issued.
+    constexpr int NFA = BF16 ? 6 : 4;  // 16-byte A fragments per row block
+    constexpr int NFB = BF16 ? 6 : 4;
+    u32x4 fa[NBUF == 2 ? RBH : 1][NFA], fb[NFB];
+    auto read_b = [&](int buf) {
+        const unsigned char *bb = sB[buf] + my_col * BSTR;
+#pragma unroll
+        for (int f = 0; f < NFB; ++f)
+            fb[f] = BF16 ? *(const u32x4 *)(bb + (f % 3) * 64 + 32 * (f / 3) + 16 * hf)  // part f % 3, k-half f / 3
+                         : *(const u32x4 *)(bb + 64 * hf + 16 * f);
+    };
+    auto read_a = [&](int buf, int rb, u32x4 (&fr)[NFA]) {
+        if (BF16) {
+            const uint16_t *p = (const uint16_t *)sA[buf];
+#pragma unroll
+            for (int f = 0; f < NFA; ++f)
+                fr[f] = *(const u32x4 *)(p + (f % 3) * PART + ((rb * 2 + f / 3) * 64 + lane) * 8);
+        } else {
+            const float *p = (const float *)sA[buf];
+#pragma unroll
+            for (int f = 0; f < NFA; ++f) fr[f] = *(const u32x4 *)(p + (rb * 64 + lane) * 16 + 4 * f);
         }
-        if (live_s) {
+    };
+    // the products of one row block (index i) on fragments fr, chained on acc[i]
+    auto mfma_row = [&](int i, const u32x4 (&fr)[NFA]) {
+        f32x16 c = acc[i];
+        if (BF16) {
 #pragma unroll
-            for (int g = 0; g < GPS; ++g) {
-                if (g >= ng) continue;
-                const unsigned char *base = ldsA + (buf * GPS + g) * CHUNK;
-                const unsigned char *bb = ldsB + (buf * GPS + g) * BCH + my_col * BSTR;
-                if (BF16) {
-                    const uint16_t *p = (const uint16_t *)base;
-                    bf16x8 bh[2], bm[2], bl[2];
+            for (int h2 = 0; h2 < 2; ++h2) {
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, fr[3 * h2]), am = __builtin_bit_cast(bf16x8, fr[3 * h2 + 1]),
+                             al = __builtin_bit_cast(bf16x8, fr[3 * h2 + 2]);
+                const bf16x8 bh = __builtin_bit_cast(bf16x8, fb[3 * h2]), bm = __builtin_bit_cast(bf16x8, fb[3 * h2 + 1]),
+                             bl = __builtin_bit_cast(bf16x8, fb[3 * h2 + 2]);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, c, 0, 0, 0);
+            }
+        } else {
 #pragma unroll
-                    for (int h2 = 0; h2 < 2; ++h2) {
-                        bh[h2] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(bb + 0 * 64 + 32 * h2 + 16 * hf));
-                        bm[h2] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(bb + 1 * 64 + 32 * h2 + 16 * hf));
-                        bl[h2] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(bb + 2 * 64 + 32 * h2 + 16 * hf));
-                    }
+            for (int q = 0; q < 16; ++q)
+                c = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(f32x4, fr[q >> 2])[q & 3],
+                                                         __builtin_bit_cast(f32x4, fb[q >> 2])[q & 3], c, 0, 0, 0);
+        }
+        acc[i] = c;
+    };
+
+    if constexpr (NBUF == 2) {
+        if (nsteps > 0) issue(std::integral_constant<int, 0>{});
+        auto step = [&](auto buf_tag, int s) {
+            constexpr int BUF = decltype(buf_tag)::value;
+            const bool live_s = live_q[BUF];
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's copies of step s are in LDS
+            __syncthreads();                      // every wave's are; the other buffer is no longer read
+            if (live_s) {
+                read_b(BUF);
 #pragma unroll
-                    for (int i = 0; i < RBH; ++i) {
-                        if (i >= nrb) continue;
-                        const int rb = rb0 + i;
-                        f32x16 c = acc[i];
+                for (int i = 0; i < RBH; ++i) read_a(BUF, min(rb0 + i, NRB - 1), fa[i]);
+            }
+            if (s + 1 < nsteps) issue(std::integral_constant<int, 1 - BUF>{});
+            if (live_s) {
 #pragma unroll
-                        for (int h2 = 0; h2 < 2; ++h2) {
-                            const int off = ((rb * 2 + h2) * 64 + lane) * 8;
-                            const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + off));
-                            const bf16x8 am = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + PART + off));
-                            const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(p + 2 * PART + off));
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[h2], c, 0, 0, 0);
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[h2], c, 0, 0, 0);
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm[h2], c, 0, 0, 0);
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh[h2], c, 0, 0, 0);
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm[h2], c, 0, 0, 0);
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[h2], c, 0, 0, 0);
-                        }
-                        acc[i] = c;
-                    }
-                } else {
-                    const float *p = (const float *)base;
-                    f32x4 bv4[4];
+                for (int i = 0; i < RBH; ++i)
+                    if (i < nrb) mfma_row(i, fa[i]);  // a chain per row block (measured faster than interleaving)
+            }
+        };
+        for (int s = 0; s < nsteps; s += 2) {
+            step(std::integral_constant<int, 0>{}, s);
+            if (s + 1 < nsteps) step(std::integral_constant<int, 1>{}, s + 1);
+        }
+    } else {
+        if (nsteps > 0) issue(std::integral_constant<int, 0>{});
+        for (int s = 0; s < nsteps; ++s) {
+            const bool live_s = live_q[0];
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+            __syncthreads();                      // step s is in LDS
+            if (live_s) {
+                read_b(0);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) bv4[q] = *(const f32x4 *)(bb + 64 * hf + 16 * q);
-#pragma unroll
-                    for (int i = 0; i < RBH; ++i) {
-                        if (i >= nrb) continue;
-                        const int rb = rb0 + i;
-                        const f32x4 *ap4 = (const f32x4 *)(p + (rb * 64 + lane) * 16);
-                        const f32x4 av4[4] = {ap4[0], ap4[1], ap4[2], ap4[3]};
-                        f32x16 c = acc[i];
-#pragma unroll
-                        for (int q = 0; q < 16; ++q)
-                            c = __builtin_amdgcn_mfma_f32_32x32x2f32(av4[q >> 2][q & 3], bv4[q >> 2][q & 3], c, 0, 0,
-                                                                     0);
-                        acc[i] = c;
-                    }
+                for (int i = 0; i < RBH; ++i) {
+                    if (i >= nrb) continue;
+                    read_a(0, rb0 + i, fa[0]);
+                    mfma_row(i, fa[0]);
                 }
             }
-        }
-        if (s + 1 < nsteps) {
-            if (NBUF == 1) __syncthreads();
-            store_ab(NBUF == 2 ? buf ^ 1 : 0, granules((s + 1) % NST));
+            __syncthreads();  // every wave is done with the buffer
+            if (s + 1 < nsteps) issue(std::integral_constant<int, 0>{});
         }
     }
     if (outv >= 0) {
@@ -381,16 +371,29 @@ __global__ void k_split_vecs(const float *in, int r_pad, int64_t total, uint16_t
     o[2 * KC] = l;
 }
 
+// Matrices [ndir][r_pad][r_pad] float32 -> float32 chunks in LDS image order.
+__global__ void k_image_f32(const float *rm, int r_pad, int64_t total, float *out) {
+    int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;  // total = ndir * r_pad * r_pad
+    const int nrb = r_pad / 32, nkc = r_pad / KC;
+    // idx enumerates (dir, kc, rb, lane, slot)
+    const int slot = (int)(idx % 16);
+    int64_t r = idx / 16;
+    const int ln = (int)(r % 64);
+    r /= 64;
+    const int rb = (int)(r % nrb);
+    r /= nrb;
+    const int kc = (int)(r % nkc);
+    const int64_t dir = r / nkc;
+    const int row = rb * 32 + (ln & 31);
+    const int k = kc * KC + 16 * (ln >> 5) + slot;
+    out[idx] = rm[(dir * r_pad + row) * r_pad + k];
+}
+
 template <int NRB, bool BF16>
 void launch(const M2LLaunch &a, hipStream_t s) {
-    constexpr int chunk = a_chunk_bytes<NRB, BF16>() + kCols * b_col_stride<BF16>();  // A + B granule
-    constexpr int GPS = 4 * chunk <= 160 * 1024 ? 2 : 1;
-    constexpr int NBUF = 2 * GPS * chunk <= 160 * 1024 ? 2 : 1;
-    constexpr int bytes = NBUF * GPS * chunk;
-    static_assert(bytes <= 160 * 1024, "A and B granules do not fit in LDS");
-    auto k = k_m2l<NRB, BF16, NBUF, GPS>;
-    FMM_HIP(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-    hipLaunchKernelGGL(k, dim3(a.ntile), dim3(kThreads), bytes, s, a);
+    static_assert(Shape<NRB, BF16>::NBUF == 2 || Shape<NRB, BF16>::LDS2 / 2 <= 160 * 1024, "chunks do not fit in LDS");
+    hipLaunchKernelGGL((k_m2l<NRB, BF16>), dim3(a.ntile), dim3(kThreads), 0, s, a);
     FMM_HIP(hipGetLastError());
 }
 
@@ -426,6 +429,14 @@ void m2l_split_mats(const float *rm, int r_pad, int ndir, uint16_t *out, hipStre
     FMM_HIP(hipGetLastError());
 }
 
+void m2l_image_mats(const float *rm, int r_pad, int ndir, float *out, hipStream_t s) {
+    FMM_REQUIRE(m2l_supported(r_pad), "m2l: unsupported state size");
+    const int64_t total = (int64_t)ndir * r_pad * r_pad;
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_image_f32, dim3(grid_for(total, 256)), dim3(256), 0, s, rm, r_pad, total, out);
+    FMM_HIP(hipGetLastError());
+}
+
 void m2l_split_vecs(const float *in, int r_pad, int64_t nvec, uint16_t *out, hipStream_t s) {
     const int64_t total = nvec * r_pad;
     if (total == 0) return;
@@ -438,6 +449,7 @@ void m2l_run(bool bf16, const M2LLaunch &a, hipStream_t s) {
     FMM_REQUIRE(m2l_supported(a.r_pad), "m2l: unsupported state size");
     FMM_REQUIRE(a.ncol == m2l_ncol(a.r_pad), "m2l: tile width mismatch");
     FMM_REQUIRE(bf16 ? (a.mats_bf && a.in_bf) : (a.mats && a.in), "m2l: operands missing for this form");
+    FMM_REQUIRE(a.zero, "m2l: zero source chunk missing");
     if (bf16)
         dispatch<true>(a.r_pad / 32, a, s);
     else

@@ -9,9 +9,13 @@ namespace fmm {
 // and the active directions term_dir[e] for e in [tile_term_off[t], tile_term_off[t+1]),
 // with source vectors term_src[e][0..ncol) (-1 = none). Vectors are rows of
 // r_pad floats (compressed far-field state); out += sum over the tile's terms.
-// FP32 form: mats are float32, row-major r_pad x r_pad, one per direction, and
-// in holds the source vectors. Split-BF16 form: mats_bf and in_bf hold the
-// same data split by m2l_split_mats and m2l_split_vecs.
+// Block b runs tile (b % 8) * ntile / 8 + b / 8: ntile is a multiple of 8 and
+// each eighth of the tiles runs on one XCD.
+// FP32 form: mats holds the r_pad x r_pad float32 matrices (one per direction)
+// rearranged by m2l_image_mats, and in the source vectors. Split-BF16 form:
+// mats_bf and in_bf hold the same data split by m2l_split_mats and
+// m2l_split_vecs. zero points to 192 bytes of zeros (16-byte aligned), read
+// for columns without a source.
 struct M2LLaunch {
     int r_pad = 0, ntile = 0, ncol = 0;
     const int64_t *tile_term_off = nullptr;
@@ -22,6 +26,7 @@ struct M2LLaunch {
     const float *in = nullptr;
     const uint16_t *mats_bf = nullptr;
     const uint16_t *in_bf = nullptr;
+    const void *zero = nullptr;
     float *out = nullptr;
 };
 
@@ -29,6 +34,8 @@ int m2l_ncol(int r_pad);
 bool m2l_supported(int r_pad);  // any multiple of 32 up to 512
 void m2l_run(bool bf16, const M2LLaunch &a, hipStream_t s);
 
+// FP32 operands: row-major [ndir][r_pad][r_pad] -> the kernel's chunk order.
+void m2l_image_mats(const float *rm, int r_pad, int ndir, float *out, hipStream_t s);
 // Split-BF16 operands: each float32 value becomes three bfloat16 parts.
 size_t m2l_split_mats_elems(int r_pad, int ndir);    // uint16 elements of the split matrices
 size_t m2l_split_vecs_elems(int r_pad, int64_t nvec);

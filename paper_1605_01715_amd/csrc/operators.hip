@@ -233,10 +233,15 @@ std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
                     pm2l.insert(pm2l.end(), {0.0, 0.0, 0.0, kRadIn, 2.0 * i, 2.0 * j, 2.0 * k, kRadIn, 1.0});
     build(pm2m, dPU, dVrSi, &op->m2m_f64, nullptr);
     build(pl2l, dPV, dUrSi, &op->l2l_f64, nullptr);
-    build(pm2l, dPV, dVrSi, nullptr, &op->m2l_rm);
-    op->m2l_bf.alloc(m2l_split_mats_elems(rp, kNumDirs));
-    m2l_split_mats(op->m2l_rm.p, rp, kNumDirs, op->m2l_bf.p, s);
-    FMM_HIP(hipStreamSynchronize(s));
+    {
+        DBuf<float> rm;  // row-major float32 translations, rearranged for the M2L kernel below
+        build(pm2l, dPV, dVrSi, nullptr, &rm);
+        op->m2l_f32.alloc(rr * kNumDirs);
+        m2l_image_mats(rm.p, rp, kNumDirs, op->m2l_f32.p, s);
+        op->m2l_bf.alloc(m2l_split_mats_elems(rp, kNumDirs));
+        m2l_split_mats(rm.p, rp, kNumDirs, op->m2l_bf.p, s);
+        FMM_HIP(hipStreamSynchronize(s));
+    }
     return op;
 }
 

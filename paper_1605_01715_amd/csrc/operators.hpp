@@ -28,7 +28,7 @@ struct Operators {
     double eps = 0;
     std::vector<double> Y;         // [ns][3]
     DBuf<double> dY;
-    DBuf<float> m2l_rm;            // [316][r_pad][r_pad] float32 row-major (M2L kernel, FP32 form)
+    DBuf<float> m2l_f32;           // [316] r_pad x r_pad float32, M2L kernel chunk order (FP32 form)
     DBuf<uint16_t> m2l_bf;         // the same, split into bfloat16 parts (M2L kernel, split-BF16 form)
     DBuf<double> m2m_f64, l2l_f64; // [8] r_pad x r_pad, float64 fragment layout
     DBuf<double> pu_f64, pv_f64;   // r_pad x n_pad fragment layout

@@ -175,6 +175,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         const int nc = m2l_ncol(P.r_pad);
         int ntile = 0;
         std::vector<int32_t> cols;
+        std::vector<int> tile_oct;  // octant of each tile
         // Within an octant, boxes are ordered by their set of active
         // directions (lexicographically, then by index), so a tile gathers
         // boxes with similar V lists and runs few directions that most of its
@@ -202,6 +203,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             std::vector<int32_t> c = tile_columns(grp, nrhs, nc, nt);
             cols.insert(cols.end(), c.begin(), c.end());
             ntile += nt;
+            tile_oct.insert(tile_oct.end(), nt, o);
         }
         std::vector<int64_t> toff{0};
         std::vector<int32_t> tdir, tsrc, colsrc(nc);
@@ -225,23 +227,34 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             }
             toff.push_back((int64_t)tdir.size());
         }
-        // Launch order: the kernel gives XCD x the contiguous block range it
-        // dispatches to x (ranges of ceil or floor of ntile / 8 tiles, larger
-        // first). Tiles are dealt round-robin, heaviest first, into those
-        // ranges, so every XCD gets the same mix and starts its heaviest
-        // tiles first (longest-processing-time order: a short tail).
+        // Launch order: the kernel gives XCD x the x-th eighth of the tiles.
+        // XCD x runs the tiles of octant x: they draw on the same 189
+        // directions in the same order, so tiles running at the same time
+        // share the matrices in that XCD's L2 (measured: 23% less traffic
+        // beyond L2 than an even mix of octants). Within an XCD the heaviest
+        // tiles start first (longest-processing-time order: a short tail);
+        // the eighths are padded to equal length with empty tiles.
         {
             std::vector<int> byw(ntile);
             for (int i = 0; i < ntile; ++i) byw[i] = i;
             std::stable_sort(byw.begin(), byw.end(),
                              [&](int x, int y) { return toff[x + 1] - toff[x] > toff[y + 1] - toff[y]; });
-            std::vector<int> order;
-            order.reserve(ntile);
+            std::vector<std::vector<int>> per_oct(8);
+            for (int i : byw) per_oct[tile_oct[i]].push_back(i);
+            size_t len = 0;
+            for (auto &v : per_oct) len = std::max(len, v.size());
+            std::vector<int> order;  // -1: empty tile
+            order.reserve(8 * len);
             for (int x = 0; x < 8; ++x)
-                for (int i = x; i < ntile; i += 8) order.push_back(byw[i]);
+                for (size_t k = 0; k < len; ++k) order.push_back(k < per_oct[x].size() ? per_oct[x][k] : -1);
             std::vector<int64_t> toff2{0};
             std::vector<int32_t> tdir2, tsrc2, cols2;
             for (int tl : order) {
+                if (tl < 0) {
+                    toff2.push_back((int64_t)tdir2.size());
+                    cols2.insert(cols2.end(), (size_t)nc, -1);
+                    continue;
+                }
                 for (int64_t e = toff[tl]; e < toff[tl + 1]; ++e) {
                     tdir2.push_back(tdir[e]);
                     tsrc2.insert(tsrc2.end(), tsrc.begin() + e * nc, tsrc.begin() + (e + 1) * nc);
@@ -253,6 +266,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             tdir.swap(tdir2);
             tsrc.swap(tsrc2);
             cols.swap(cols2);
+            ntile = (int)order.size();
         }
         P.m2l_ntile = ntile;
         P.m2l_steps = (int64_t)tdir.size();
@@ -261,6 +275,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         P.m2l_dir = upload(tdir, s);
         P.m2l_src = upload(tsrc, s);
         P.m2l_cols = upload(cols, s);
+        P.m2l_zero = upload(std::vector<float>(48, 0.f), s);
     }
 
     // P2L (X lists of boxes holding more than n_s targets)
@@ -491,10 +506,11 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         m.term_dir = P.m2l_dir.p;
         m.term_src = P.m2l_src.p;
         m.tile_cols = P.m2l_cols.p;
-        m.mats = op.m2l_rm.p;
+        m.mats = op.m2l_f32.p;
         m.in = P.ut.p;
         m.mats_bf = op.m2l_bf.p;
         m.in_bf = P.ut_bf.p;
+        m.zero = P.m2l_zero.p;
         m.out = P.dt.p;
         m2l_run(P.m2l_bf16, m, s);
     }

@@ -52,6 +52,7 @@ struct Plan {
     int64_t m2l_steps = 0;  // (tile, direction) products the dedicated kernel runs
     DBuf<int64_t> m2l_toff;
     DBuf<int32_t> m2l_dir, m2l_src, m2l_cols;
+    DBuf<float> m2l_zero;  // a zero source chunk (columns without a source)
 
     DBuf<int32_t> wleaf, wt0, soff, sbox, poff, prng;
     DBuf<int8_t> skind;
