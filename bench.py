@@ -249,7 +249,8 @@ def main():
                                f"uniform in the unit cube), single + double layer potential, order {order}, "
                                f"leaf size {leaf}, pseudo-inverse threshold {eps:g}, adaptive octree, split-BF16 M2L",
                    "n_points": info["n_points"], "order": order, "leaf_size": leaf, "pinv_eps": eps,
-                   "rank": info["rank"], "boxes": info["n_boxes"], "levels": info["n_levels"]},
+                   "rank": info["rank"], "boxes": info["n_boxes"], "levels": info["n_levels"],
+                   "m2l_pieces_per_tile": info["m2l_pieces"]},
         "autotune": {"target_rel_l2": args.target, "split_bf16": main_r["tune"],
                      "fp32": results["fp32"]["tune"] if "fp32" in results else None},
         "rel_l2_error": main_r.get("err"),

@@ -227,6 +227,8 @@ typedef struct {
                                             included (m2l_pairs / m2l_columns is its fill) */
     int64_t rank;                        /* r: singular values of the check-from-equivalent map kept;
                                             the far-field state of a box is r values per rhs */
+    int64_t m2l_pieces;                  /* M2L work items per tile of 128 target boxes (load
+                                            balance across CUs; pieces add up in a fixed order) */
     double root[4];                      /* root cube actually used */
     double setup_ms;                     /* wall time of fmm_setup */
 } fmm_info;

@@ -372,6 +372,7 @@ int fmm_plan_info(fmm_plan plan, fmm_info *info) {
         r.p2m_evals = P.p2m_evals;
         r.m2l_columns = P.m2l_steps * P.m2l_ncol;
         r.rank = P.r;
+        r.m2l_pieces = P.m2l_pieces_per_tile;
         for (int c = 0; c < 3; ++c) r.root[c] = P.t.x0[c];
         r.root[3] = P.t.w;
         r.setup_ms = P.setup_ms;

@@ -312,7 +312,20 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
             if (s + 1 < nsteps) issue(std::integral_constant<int, 0>{});
         }
     }
-    if (outv >= 0) {
+    const int slot = a.piece_slot ? a.piece_slot[tile] : -1;
+    if (slot >= 0 && outv >= 0) {  // a piece of a cut tile: its partial sum, added to out by k_m2l_reduce
+#pragma unroll
+        for (int i = 0; i < RBH; ++i) {
+            if (i >= nrb) continue;
+            const int rb = rb0 + i;
+#pragma unroll
+            for (int v4 = 0; v4 < 4; ++v4) {
+                f32x4 v;
+                for (int c = 0; c < 4; ++c) v[c] = acc[i][4 * v4 + c];
+                *(f32x4 *)(a.partial + ((size_t)slot * kCols + my_col) * RP + rb * 32 + 8 * v4 + 4 * hf) = v;
+            }
+        }
+    } else if (outv >= 0) {
 #pragma unroll
         for (int i = 0; i < RBH; ++i) {
             if (i >= nrb) continue;
@@ -328,6 +341,24 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
                 *op = cur;
             }
         }
+    }
+}
+
+// Cut tiles: out[cols[c]] += partial[slot0] + partial[slot0 + 1] + ... (in
+// piece order, so the result does not depend on which piece ran first).
+__global__ void k_m2l_reduce(int r_pad, int ncol, const int32_t *cols, const int32_t *slot0, const int32_t *kpieces,
+                             const float *partial, float *out) {
+    const int tl = blockIdx.x;
+    const int k = kpieces[tl];
+    const size_t per = (size_t)ncol * r_pad;
+    const float *p = partial + (size_t)slot0[tl] * per;
+    for (int idx = threadIdx.x; idx < ncol * r_pad; idx += 256) {
+        const int c = idx / r_pad;
+        const int v = cols[(size_t)tl * ncol + c];
+        if (v < 0) continue;
+        float sum = p[idx];
+        for (int q = 1; q < k; ++q) sum += p[q * per + idx];
+        out[(size_t)v * r_pad + idx % r_pad] += sum;
     }
 }
 
@@ -398,6 +429,18 @@ void launch(const M2LLaunch &a, hipStream_t s) {
 }
 
 template <bool BF16, int NRB = 1>
+int blocks_per_cu(int nrb) {
+    if constexpr (NRB <= 16) {
+        if (nrb != NRB) return blocks_per_cu<BF16, NRB + 1>(nrb);
+        int n = 0;
+        FMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_m2l<NRB, BF16>, kThreads, 0));
+        return n > 0 ? n : 1;
+    } else {
+        return 1;
+    }
+}
+
+template <bool BF16, int NRB = 1>
 void dispatch(int nrb, const M2LLaunch &a, hipStream_t s) {
     if constexpr (NRB <= 16) {
         if (nrb == NRB)
@@ -441,6 +484,18 @@ void m2l_split_vecs(const float *in, int r_pad, int64_t nvec, uint16_t *out, hip
     const int64_t total = nvec * r_pad;
     if (total == 0) return;
     hipLaunchKernelGGL(k_split_vecs, dim3(grid_for(total, 256)), dim3(256), 0, s, in, r_pad, total, out);
+    FMM_HIP(hipGetLastError());
+}
+
+int m2l_blocks_per_cu(bool bf16, int r_pad) {
+    FMM_REQUIRE(m2l_supported(r_pad), "m2l: unsupported state size");
+    return bf16 ? blocks_per_cu<true>(r_pad / 32) : blocks_per_cu<false>(r_pad / 32);
+}
+
+void m2l_reduce(int r_pad, int ntile, int ncol, const int32_t *cols, const int32_t *slot0, const int32_t *kpieces,
+                const float *partial, float *out, hipStream_t s) {
+    if (ntile <= 0) return;
+    hipLaunchKernelGGL(k_m2l_reduce, dim3(ntile), dim3(256), 0, s, r_pad, ncol, cols, slot0, kpieces, partial, out);
     FMM_HIP(hipGetLastError());
 }
 

@@ -27,10 +27,16 @@ struct M2LLaunch {
     const uint16_t *mats_bf = nullptr;
     const uint16_t *in_bf = nullptr;
     const void *zero = nullptr;
+    const int32_t *piece_slot = nullptr;  // per tile: -1, or the slot of partial it writes instead of adding to out
+    float *partial = nullptr;             // [slot][ncol][r_pad]
     float *out = nullptr;
 };
 
 int m2l_ncol(int r_pad);
+int m2l_blocks_per_cu(bool bf16, int r_pad);  // workgroups of the kernel that fit on one CU
+// cut tiles: out[cols[t][c]] += sum over q < kpieces[t] of partial[slot0[t] + q][c] (q in order)
+void m2l_reduce(int r_pad, int ntile, int ncol, const int32_t *cols, const int32_t *slot0, const int32_t *kpieces,
+                const float *partial, float *out, hipStream_t s);
 bool m2l_supported(int r_pad);  // any multiple of 32 up to 512
 void m2l_run(bool bf16, const M2LLaunch &a, hipStream_t s);
 

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <array>
 #include <limits>
+#include <queue>
 
 #include "plan.hpp"
 
@@ -227,46 +228,114 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             }
             toff.push_back((int64_t)tdir.size());
         }
-        // Launch order: the kernel gives XCD x the x-th eighth of the tiles.
-        // XCD x runs the tiles of octant x: they draw on the same 189
+        // Launch order: the kernel gives XCD x the x-th eighth of the work
+        // items. XCD x runs the tiles of octant x: they draw on the same 189
         // directions in the same order, so tiles running at the same time
         // share the matrices in that XCD's L2 (measured: 23% less traffic
-        // beyond L2 than an even mix of octants). Within an XCD the heaviest
-        // tiles start first (longest-processing-time order: a short tail);
-        // the eighths are padded to equal length with empty tiles.
+        // beyond L2 than an even mix of octants).
+        //
+        // Balance: an XCD holds about 87 tiles (at 4M points) for 32 CUs, so
+        // whole tiles leave a tail (a simulated 89% of the ideal time). A
+        // tile's active directions are therefore cut into k contiguous
+        // pieces, k the same for all tiles and chosen by simulating the
+        // dispatch (pieces heaviest first, each started on the first free
+        // workgroup slot) for k = 1..6. Pieces of a cut tile write partial
+        // sums, added to the output in piece order by a second kernel.
         {
-            std::vector<int> byw(ntile);
-            for (int i = 0; i < ntile; ++i) byw[i] = i;
-            std::stable_sort(byw.begin(), byw.end(),
-                             [&](int x, int y) { return toff[x + 1] - toff[x] > toff[y + 1] - toff[y]; });
-            std::vector<std::vector<int>> per_oct(8);
-            for (int i : byw) per_oct[tile_oct[i]].push_back(i);
-            size_t len = 0;
-            for (auto &v : per_oct) len = std::max(len, v.size());
-            std::vector<int> order;  // -1: empty tile
-            order.reserve(8 * len);
-            for (int x = 0; x < 8; ++x)
-                for (size_t k = 0; k < len; ++k) order.push_back(k < per_oct[x].size() ? per_oct[x][k] : -1);
-            std::vector<int64_t> toff2{0};
-            std::vector<int32_t> tdir2, tsrc2, cols2;
-            for (int tl : order) {
-                if (tl < 0) {
-                    toff2.push_back((int64_t)tdir2.size());
-                    cols2.insert(cols2.end(), (size_t)nc, -1);
-                    continue;
+            const int slots = 32 * m2l_blocks_per_cu(P.m2l_bf16, P.r_pad);  // concurrent workgroups per XCD
+            auto ndir = [&](int tl) { return (int)(toff[tl + 1] - toff[tl]); };
+            // makespan of one XCD in steps, with a cost of 2 directions per piece of a cut tile
+            auto makespan = [&](int k) {
+                double worst = 0.0;
+                for (int x = 0; x < 8; ++x) {
+                    std::vector<double> w;
+                    for (int tl = 0; tl < ntile; ++tl) {
+                        if (tile_oct[tl] != x) continue;
+                        const int kk = std::min(k, ndir(tl));
+                        for (int q = 0; q < kk; ++q) w.push_back((double)ndir(tl) / kk + (kk > 1 ? 2.0 : 0.0));
+                    }
+                    std::sort(w.begin(), w.end(), std::greater<double>());
+                    std::priority_queue<double, std::vector<double>, std::greater<double>> busy;
+                    for (int q = 0; q < slots; ++q) busy.push(0.0);
+                    double end = 0.0;
+                    for (double v : w) {
+                        const double t0 = busy.top();
+                        busy.pop();
+                        busy.push(t0 + v);
+                        end = std::max(end, t0 + v);
+                    }
+                    worst = std::max(worst, end);
                 }
-                for (int64_t e = toff[tl]; e < toff[tl + 1]; ++e) {
-                    tdir2.push_back(tdir[e]);
-                    tsrc2.insert(tsrc2.end(), tsrc.begin() + e * nc, tsrc.begin() + (e + 1) * nc);
+                return worst;
+            };
+            int kbest = 1;
+            double best = makespan(1);
+            for (int k = 2; k <= 6; ++k) {
+                const double m = makespan(k);
+                if (m < best * 0.995) {
+                    best = m;
+                    kbest = k;
                 }
-                toff2.push_back((int64_t)tdir2.size());
-                cols2.insert(cols2.end(), cols.begin() + (size_t)tl * nc, cols.begin() + (size_t)(tl + 1) * nc);
             }
+            P.m2l_pieces_per_tile = kbest;
+            // pieces: (tile, first direction, last direction + 1, partial slot or -1)
+            struct Piece {
+                int tile, e0, e1, slot;
+            };
+            std::vector<std::vector<Piece>> per_oct(8);
+            std::vector<int32_t> red_cols, red_slot0, red_k;
+            int nslot = 0;
+            for (int tl = 0; tl < ntile; ++tl) {
+                const int n = ndir(tl), kk = std::max(1, std::min(kbest, n));
+                if (n == 0) continue;
+                const int slot0 = kk > 1 ? nslot : -1;
+                if (kk > 1) {
+                    red_cols.insert(red_cols.end(), cols.begin() + (size_t)tl * nc, cols.begin() + (size_t)(tl + 1) * nc);
+                    red_slot0.push_back(slot0);
+                    red_k.push_back(kk);
+                    nslot += kk;
+                }
+                for (int q = 0; q < kk; ++q)
+                    per_oct[tile_oct[tl]].push_back(
+                        {tl, (int)toff[tl] + n * q / kk, (int)toff[tl] + n * (q + 1) / kk, kk > 1 ? slot0 + q : -1});
+            }
+            size_t len = 0;
+            for (auto &v : per_oct) {
+                std::stable_sort(v.begin(), v.end(), [](const Piece &x, const Piece &y) { return x.e1 - x.e0 > y.e1 - y.e0; });
+                len = std::max(len, v.size());
+            }
+            std::vector<int64_t> toff2{0};
+            std::vector<int32_t> tdir2, tsrc2, cols2, slot2;
+            for (int x = 0; x < 8; ++x)
+                for (size_t k = 0; k < len; ++k) {
+                    if (k >= per_oct[x].size()) {  // empty work item
+                        toff2.push_back((int64_t)tdir2.size());
+                        cols2.insert(cols2.end(), (size_t)nc, -1);
+                        slot2.push_back(-1);
+                        continue;
+                    }
+                    const Piece &pc = per_oct[x][k];
+                    for (int e = pc.e0; e < pc.e1; ++e) {
+                        tdir2.push_back(tdir[e]);
+                        tsrc2.insert(tsrc2.end(), tsrc.begin() + (size_t)e * nc, tsrc.begin() + (size_t)(e + 1) * nc);
+                    }
+                    toff2.push_back((int64_t)tdir2.size());
+                    cols2.insert(cols2.end(), cols.begin() + (size_t)pc.tile * nc, cols.begin() + (size_t)(pc.tile + 1) * nc);
+                    slot2.push_back(pc.slot);
+                }
             toff.swap(toff2);
             tdir.swap(tdir2);
             tsrc.swap(tsrc2);
             cols.swap(cols2);
-            ntile = (int)order.size();
+            ntile = (int)(8 * len);
+            P.m2l_slot = upload(slot2, s);
+            P.m2l_nsplit = (int)red_k.size();
+            if (P.m2l_nsplit > 0) {
+                P.m2l_partial.alloc((size_t)nslot * nc * P.r_pad);
+                P.m2l_red_cols = upload(red_cols, s);
+                P.m2l_red_slot0 = upload(red_slot0, s);
+                P.m2l_red_k = upload(red_k, s);
+            }
         }
         P.m2l_ntile = ntile;
         P.m2l_steps = (int64_t)tdir.size();
@@ -511,8 +580,13 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         m.mats_bf = op.m2l_bf.p;
         m.in_bf = P.ut_bf.p;
         m.zero = P.m2l_zero.p;
+        m.piece_slot = P.m2l_slot.p;
+        m.partial = P.m2l_partial.p;
         m.out = P.dt.p;
         m2l_run(P.m2l_bf16, m, s);
+        if (P.m2l_nsplit > 0)
+            m2l_reduce(rp, P.m2l_nsplit, P.m2l_ncol, P.m2l_red_cols.p, P.m2l_red_slot0.p, P.m2l_red_k.p, P.m2l_partial.p,
+                       P.dt.p, s);
     }
     mark(ST_L2L);
     for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, rp, rp, P.dt.p, P.dt.p, nullptr, true, s);

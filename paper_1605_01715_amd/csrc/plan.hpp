@@ -53,6 +53,10 @@ struct Plan {
     DBuf<int64_t> m2l_toff;
     DBuf<int32_t> m2l_dir, m2l_src, m2l_cols;
     DBuf<float> m2l_zero;  // a zero source chunk (columns without a source)
+    DBuf<int32_t> m2l_slot;  // per work item: partial-sum slot, or -1 (adds into dt)
+    int m2l_nsplit = 0, m2l_pieces_per_tile = 1;  // tiles cut into pieces; pieces per cut tile
+    DBuf<float> m2l_partial;                      // [slot][ncol][r_pad] partial sums of cut tiles
+    DBuf<int32_t> m2l_red_cols, m2l_red_slot0, m2l_red_k;  // per cut tile: columns, first slot, pieces
 
     DBuf<int32_t> wleaf, wt0, soff, sbox, poff, prng;
     DBuf<int8_t> skind;
