@@ -6,14 +6,18 @@
 // of point-generated check potentials onto the compressed basis and the
 // check-to-equivalent expansions. They are cheap next to M2L and they feed
 // every M2L, so they run in float64 (v_mfma_f64_16x16x4_f64) on float32 data.
-// The kernel is target-stationary: a workgroup owns a tile of 32 output
-// vectors, keeps their accumulator in registers across all terms and writes
-// each output once.
+// The kernel is target-stationary: a workgroup owns 64 rows of a tile of 32
+// output vectors, keeps their accumulator in registers across all terms and
+// writes each output once.
 //
-// Layout (4 waves of 64 lanes): wave w computes row blocks w, w+4, ... of 16
-// rows against both 16-column blocks. Matrices are stored in the fragment
-// order of the instruction; the source vectors of the tile are staged in LDS
-// once per k-chunk and shared by the four waves.
+// Layout (4 waves of 64 lanes): the workgroup (tile, g) computes row blocks
+// 4g .. 4g+3 of 16 rows, wave w row block 4g + w against both 16-column
+// blocks. Splitting the rows over workgroups keeps the chain of float64
+// MFMAs of one tile short: most tree levels have fewer tiles than the chip
+// has CUs, so a level costs about one tile's latency (measured 3x faster
+// than one workgroup per tile). Matrices are stored in the fragment order of
+// the instruction; the source vectors of the tile are staged in LDS and
+// shared by the four waves.
 #include "gemm.hpp"
 
 namespace fmm {
@@ -36,7 +40,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmLaunch a) {
     extern __shared__ float Bs[];  // [k_pad][kBStr]
     __shared__ int32_t cols[NCOL], srcs[NCOL];
     const int t = threadIdx.x, lane = t & 63;
-    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6) + 4 * MAXRB * (int)blockIdx.y;  // first row block
     const int64_t tile = blockIdx.x;
     const int nrb = a.m_pad / 16, K = a.k_pad, nkc = K / 16;
     if (t < NCOL) cols[t] = a.tile_cols[tile * NCOL + t];
@@ -180,18 +184,14 @@ void box_gemm_f64(const GemmLaunch &a, hipStream_t s) {
     if (a.ntile <= 0 || a.nterm <= 0) return;
     FMM_REQUIRE(a.m_pad % 16 == 0 && a.k_pad % 16 == 0 && a.m_pad <= 512 && a.k_pad <= kMaxK,
                 "box_gemm: unsupported size");
-    const int per = (a.m_pad / 16 + 3) / 4;
-    dim3 g((unsigned)a.ntile), b(kThreads);
+    dim3 g((unsigned)a.ntile, (unsigned)((a.m_pad / 16 + 3) / 4)), b(kThreads);  // one row block per wave
     const size_t sh = (size_t)a.k_pad * kBStr * sizeof(float);
     auto go = [&](auto kern) {
         FMM_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(kMaxK * kBStr * sizeof(float))));
         hipLaunchKernelGGL(kern, g, b, sh, s, a);
     };
-    if (per <= 2) go(k_gemm_f64<2>);
-    else if (per <= 4) go(k_gemm_f64<4>);
-    else if (per <= 6) go(k_gemm_f64<6>);
-    else go(k_gemm_f64<8>);
+    go(k_gemm_f64<1>);
     FMM_HIP(hipGetLastError());
 }
 
