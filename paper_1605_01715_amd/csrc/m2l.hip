@@ -17,9 +17,8 @@
 // 16 bytes per lane, no registers on the way) and every wave multiplies
 // them. With 32x32 MFMA tiles each staged matrix element is read from LDS once
 // per 32 columns. With two LDS buffers (split-BF16) the copies of step s + 1
-// are issued right after the waves have read their step-s fragments into
-// registers, and run under step s's MFMAs; with one (float32), two
-// workgroups share each CU. The tiles of one octant run on one XCD (they
+// are issued at the start of step s and run under its MFMAs; with one
+// (float32), two workgroups share each CU. The tiles of one octant run on one XCD (they
 // share most directions, so concurrently running tiles reuse the matrices in
 // that XCD's L2).
 //
@@ -114,12 +113,11 @@ struct Shape {
     static constexpr int NIB = kCols * SPC / 64;               // 1 KB copies per B chunk
     static constexpr int JA = (NIA + 7) / 8, JB = (NIB + 7) / 8;  // copies per wave (at most)
     static constexpr int LDS2 = 2 * (CHUNK + BCH) + 4 * kNumDirs;
-    // Split-BF16: two buffers when they fit in LDS and a step's fragments in
-    // registers. Float32: one buffer (43 KB at r_pad 192), so two workgroups
+    // Split-BF16: two buffers when they fit in LDS. Float32: one buffer (43 KB at r_pad 192), so two workgroups
     // share a CU and each covers the other's barriers (measured 6% faster
     // than two buffers; for split-BF16 two buffers are 6% faster at the
     // tuned leaf size).
-    static constexpr int NBUF = (BF16 && LDS2 <= 160 * 1024 && RBH * 24 <= 96) ? 2 : 1;
+    static constexpr int NBUF = (BF16 && LDS2 <= 160 * 1024) ? 2 : 1;
     static_assert(kCols * SPC % 64 == 0, "B slots must fill whole copies");
 };
 
@@ -130,8 +128,10 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
                   BSTR = S::BSTR, BCH = S::BCH, NIB = S::NIB, JA = S::JA, JB = S::JB, NBUF = S::NBUF;
     constexpr int PART = NRB * 2 * 64 * 8;  // bfloat16 elements of one part of an A chunk
     constexpr int NGR = RP / KC;            // steps per direction
-    __shared__ __align__(16) unsigned char sA[NBUF][CHUNK];
-    __shared__ __align__(16) unsigned char sB[NBUF][BCH];
+    __shared__ __align__(16) unsigned char sA0[CHUNK], sA1[NBUF == 2 ? CHUNK : 16];
+    __shared__ __align__(16) unsigned char sB0[BCH], sB1[NBUF == 2 ? BCH : 16];
+    unsigned char *sA[2] = {sA0, sA1};
+    unsigned char *sB[2] = {sB0, sB1};
     __shared__ int32_t s_dir[kNumDirs];
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6) & 7;
@@ -219,12 +219,13 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
         }
     };
 
-    // Operand fragments of one step. A read of LDS issued after an LDS copy
-    // waits for that copy, so with two buffers all of a step's fragments are
-    // read before the next step's copies are issued.
+    // Operand fragments of one step. The two buffers are distinct LDS
+    // objects, so the compiler can tell that reads of one do not wait for
+    // copies into the other: the next step's copies are issued first and
+    // the fragments are read one row block at a time under the MFMAs.
     constexpr int NFA = BF16 ? 6 : 4;  // 16-byte A fragments per row block
     constexpr int NFB = BF16 ? 6 : 4;
-    u32x4 fa[NBUF == 2 ? RBH : 1][NFA], fb[NFB];
+    u32x4 fa[NFA], fb[NFB];
     auto read_b = [&](int buf) {
         const unsigned char *bb = sB[buf] + my_col * BSTR;
 #pragma unroll
@@ -277,16 +278,15 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
             const bool live_s = live_q[BUF];
             __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's copies of step s are in LDS
             __syncthreads();                      // every wave's are; the other buffer is no longer read
+            if (s + 1 < nsteps) issue(std::integral_constant<int, 1 - BUF>{});
             if (live_s) {
                 read_b(BUF);
 #pragma unroll
-                for (int i = 0; i < RBH; ++i) read_a(BUF, min(rb0 + i, NRB - 1), fa[i]);
-            }
-            if (s + 1 < nsteps) issue(std::integral_constant<int, 1 - BUF>{});
-            if (live_s) {
-#pragma unroll
-                for (int i = 0; i < RBH; ++i)
-                    if (i < nrb) mfma_row(i, fa[i]);  // a chain per row block (measured faster than interleaving)
+                for (int i = 0; i < RBH; ++i) {
+                    if (i >= nrb) continue;
+                    read_a(BUF, rb0 + i, fa);
+                    mfma_row(i, fa);
+                }
             }
         };
         for (int s = 0; s < nsteps; s += 2) {
@@ -304,8 +304,8 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
 #pragma unroll
                 for (int i = 0; i < RBH; ++i) {
                     if (i >= nrb) continue;
-                    read_a(0, rb0 + i, fa[0]);
-                    mfma_row(i, fa[0]);
+                    read_a(0, rb0 + i, fa);
+                    mfma_row(i, fa);
                 }
             }
             __syncthreads();  // every wave is done with the buffer
