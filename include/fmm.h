@@ -77,6 +77,8 @@ typedef struct {
     float cutoff;       /* tolerance radius (Sec. III.A.1), e.g. 1e-5; r < cutoff excluded, r == 0 always */
     double root[4];     /* root cube x0, y0, z0, width; width <= 0: derived from the points */
     double pinv_eps;    /* relative SVD truncation of the check-to-equivalent maps; <= 0: default */
+    int m2l_pieces;     /* M2L work items per tile of target boxes, 1..8; 0: chosen at setup by
+                           simulating the dispatch on the GPU's compute units (the default) */
 } fmm_options;
 
 /* Fill `opt` with defaults: order 6, leaf_size 64, adaptive, max_depth 21, FP32,

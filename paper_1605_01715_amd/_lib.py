@@ -23,7 +23,7 @@ STAGES = ("P2M", "M2M", "P2L", "M2L", "L2L", "C2E", "EVAL")
 class FmmOptions(ctypes.Structure):
     _fields_ = [("order", c_int), ("leaf_size", c_int), ("uniform_depth", c_int), ("max_depth", c_int),
                 ("precision", c_int), ("src_kernels", c_int), ("outputs", c_int), ("nrhs", c_int),
-                ("cutoff", c_float), ("root", c_double * 4), ("pinv_eps", c_double)]
+                ("cutoff", c_float), ("root", c_double * 4), ("pinv_eps", c_double), ("m2l_pieces", c_int)]
 
 
 class FmmOperator(ctypes.Structure):

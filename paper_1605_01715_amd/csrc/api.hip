@@ -58,6 +58,7 @@ void fmm_default_options(fmm_options *opt) {
     opt->cutoff = 1e-5f;
     opt->root[0] = opt->root[1] = opt->root[2] = opt->root[3] = 0.0;
     opt->pinv_eps = 0.0;
+    opt->m2l_pieces = 0;
 }
 
 const char *fmm_last_error(void) { return g_last_error.c_str(); }
@@ -87,6 +88,7 @@ void check_options(const fmm_options *opt) {
                                         std::isfinite(opt->root[2]) && std::isfinite(opt->root[3])),
                 "fmm_setup: root cube is not finite");
     FMM_REQUIRE(opt->pinv_eps >= 0.0 && std::isfinite(opt->pinv_eps), "fmm_setup: pinv_eps must be finite and >= 0");
+    FMM_REQUIRE(opt->m2l_pieces >= 0 && opt->m2l_pieces <= 8, "fmm_setup: m2l_pieces must be in 0..8");
 }
 
 fmm::TreeOptions tree_options(const fmm_options *opt) {

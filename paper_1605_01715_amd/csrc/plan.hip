@@ -239,7 +239,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         // tile's active directions are therefore cut into k contiguous
         // pieces, k the same for all tiles and chosen by simulating the
         // dispatch (pieces heaviest first, each started on the first free
-        // workgroup slot) for k = 1..6. Pieces of a cut tile write partial
+        // workgroup slot) for k = 1..6 unless the options force k. Pieces of a cut tile write partial
         // sums, added to the output in piece order by a second kernel.
         {
             const int slots = 32 * m2l_blocks_per_cu(P.m2l_bf16, P.r_pad);  // concurrent workgroups per XCD
@@ -268,13 +268,16 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
                 }
                 return worst;
             };
-            int kbest = 1;
-            double best = makespan(1);
-            for (int k = 2; k <= 6; ++k) {
-                const double m = makespan(k);
-                if (m < best * 0.995) {
-                    best = m;
-                    kbest = k;
+            int kbest = P.opt.m2l_pieces;  // forced, or 0: simulated
+            if (kbest == 0) {
+                kbest = 1;
+                double best = makespan(1);
+                for (int k = 2; k <= 6; ++k) {
+                    const double m = makespan(k);
+                    if (m < best * 0.995) {
+                        best = m;
+                        kbest = k;
+                    }
                 }
             }
             P.m2l_pieces_per_tile = kbest;

@@ -148,6 +148,31 @@ def test_fmm_adaptive_single_double_layer(precision):
     assert e8 < 3e-6
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_m2l_pieces_agree(precision):
+    """M2L work items: tiles cut into k pieces of their direction list, whose
+    partial sums are added in piece order, give the potentials of whole tiles
+    up to float32 summation order, for forced k and the simulated choice; the
+    same k gives bit-identical results run to run."""
+    say(f"test_m2l_pieces_agree: n=30000 s=40 p=8 precision={precision}")
+    x, nrm, q, mu = _cloud(30000, 7)
+    ref, _ = D.direct_sum(x, x, q, mu[:, None].astype(np.float64) * nrm)
+    base = fmm_run(x, q=q, mu=mu, nrm=nrm, order=8, leaf=40, precision=precision, m2l_pieces=1)
+    assert base["info"]["m2l_pieces"] == 1
+    runs = {}
+    for k in (0, 2, 5, 8):
+        r = fmm_run(x, q=q, mu=mu, nrm=nrm, order=8, leaf=40, precision=precision, m2l_pieces=k)
+        got = r["info"]["m2l_pieces"]
+        assert (k == 0 and 1 <= got <= 6) or got == k
+        d = D.rel_l2(r["pot"][0], base["pot"][0])
+        e = D.rel_l2(r["pot"][0], ref)
+        say(f"  m2l_pieces={k} (used {got}): vs whole tiles {d:.2e}, vs direct sum {e:.2e}")
+        assert d < 1e-6 and e < 3e-6
+        runs[k] = r["pot"]
+    again = fmm_run(x, q=q, mu=mu, nrm=nrm, order=8, leaf=40, precision=precision, m2l_pieces=5)
+    assert np.array_equal(again["pot"], runs[5])
+
+
 def test_fmm_matches_oracle_kifmm_and_its_stages():
     """Same tree, lists and pseudo-inverse threshold: the GPU float32 result
     and its check potentials against the oracle's float64 KIFMM."""
