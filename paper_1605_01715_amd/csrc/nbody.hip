@@ -15,6 +15,8 @@
 // near field uses the float32 input coordinates directly (x - y of two close
 // float32 values is exact). Per-target sums are accumulated per LDS tile in
 // float32 and folded into a (hi, lo) pair with Knuth's TwoSum.
+#include <type_traits>
+
 #include "nbody.hpp"
 
 namespace fmm {
@@ -238,9 +240,13 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
     }
 
     // points: P2P (U list) and the direct W / X pairs; r < delta excluded
-    // (delta2 > 0 also excludes r = 0)
+    // (delta2 > 0 also excludes r = 0). Ranges [poff, pmid) may hold a pair
+    // closer than delta and are tested pair by pair; for ranges [pmid,
+    // poff + 1) the setup has shown that the points' bounding boxes are
+    // farther apart than delta, and the test is skipped.
     const float delta2 = a.delta2;
-    for (int e = a.poff[leaf]; e < a.poff[leaf + 1]; ++e) {
+    auto range = [&](auto test_tag, int e) {
+        constexpr bool TEST = decltype(test_tag)::value;
         const int s0 = a.prng[2 * e], s1 = a.prng[2 * e + 1];
         for (int j0 = s0; j0 < s1; j0 += 64) {
             const int j = j0 + lane;
@@ -282,7 +288,7 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
                 for (int u = 0; u < TPL; ++u) {
                     const float dx = xg[u] - rec[0], dy = yg[u] - rec[1], dz = zg[u] - rec[2];
                     const float r2 = dx * dx + dy * dy + dz * dz;
-                    const float inv = r2 >= delta2 ? rsq(r2) : 0.f;
+                    const float inv = TEST ? (r2 >= delta2 ? rsq(r2) : 0.f) : rsq(r2);
                     const float inv2 = inv * inv;
                     int o = 3;
                     float sl[NRHS];
@@ -316,7 +322,10 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
                     for (int o = 0; o < NOUT; ++o) two_sum_into(hi[u][r][o], lo[u][r][o], part[u][r][o]);
             __syncthreads();
         }
-    }
+    };
+    const int pmid = a.pmid ? a.pmid[leaf] : a.poff[leaf + 1];
+    for (int e = a.poff[leaf]; e < pmid; ++e) range(std::true_type{}, e);
+    for (int e = pmid; e < a.poff[leaf + 1]; ++e) range(std::false_type{}, e);
 
     // sum the slices of each target through LDS, then slice 0 writes
     constexpr int NV = TPL * NRHS * NOUT;

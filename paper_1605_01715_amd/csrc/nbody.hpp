@@ -41,6 +41,7 @@ struct EvalArgs {
     const int32_t *soff = nullptr, *sbox = nullptr;
     const int8_t *skind = nullptr;
     const int32_t *poff = nullptr, *prng = nullptr;
+    const int32_t *pmid = nullptr;  // per box: ranges [poff, pmid) need the r < delta test (NULL: all)
     const int64_t *tbeg = nullptr, *tend = nullptr;
     const float *tx = nullptr, *ty = nullptr, *tz = nullptr;
     const int64_t *trg_perm = nullptr;  // NULL: identity

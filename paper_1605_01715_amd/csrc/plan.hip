@@ -12,6 +12,7 @@
 // evaluated directly rather than through a surface (this never changes what
 // is computed, only how).
 #include <algorithm>
+#include <cmath>
 #include <array>
 #include <limits>
 #include <queue>
@@ -25,6 +26,32 @@ namespace {
 constexpr int kBlock = 256;
 
 // plain fill (a memset node does not replay reliably inside captured graphs)
+// Tight bounding boxes of the points of listed boxes: one wave per box,
+// out[6 b .. 6 b + 5] = min x, y, z, max x, y, z over [beg[box], end[box]).
+__global__ __launch_bounds__(64) void k_point_boxes(const int32_t *boxes, const int64_t *beg, const int64_t *end,
+                                                    const float *x, const float *y, const float *z, float *out) {
+    const int b = blockIdx.x, lane = threadIdx.x;
+    const int32_t box = boxes[b];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = beg[box] + lane; i < end[box]; i += 64) {
+        const float v[3] = {x[i], y[i], z[i]};
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fminf(lo[c], v[c]);
+            hi[c] = fmaxf(hi[c], v[c]);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fminf(lo[c], __shfl_xor(lo[c], o));
+            hi[c] = fmaxf(hi[c], __shfl_xor(hi[c], o));
+        }
+    if (lane == 0)
+        for (int c = 0; c < 3; ++c) {
+            out[6 * b + c] = lo[c];
+            out[6 * b + 3 + c] = hi[c];
+        }
+}
+
 __global__ void k_zero(float *p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) p[i] = 0.f;
@@ -414,10 +441,70 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
     // check-to-equivalent maps and the leaf evaluation lists
     std::vector<int32_t> down_boxes;
     std::vector<uint8_t> up_needed(nb, 0);
-    std::vector<int32_t> wleaf, wt0, soff{0}, sbox, poff{0}, prng;
+    std::vector<int32_t> wleaf, wt0, soff{0}, sbox, poff{0}, prng, pmid;
     std::vector<int8_t> skind;
+    // Which point ranges need the r < delta test: tight bounding boxes of the
+    // target points of every target leaf and of the source points of every
+    // box that supplies points to one; a range is tested when it is the
+    // leaf's own box or the two boxes come within sqrt(1.1) delta (the margin
+    // covers the float32 rounding of r^2).
+    std::vector<int32_t> tb_index(nb, -1), sb_index(nb, -1);
+    std::vector<float> tbox, sboxes;
+    {
+        std::vector<int32_t> tl, sl;
+        std::vector<uint8_t> is_src(nb, 0);
+        auto mark_src = [&](int32_t a) {
+            if (!is_src[a] && nsrc(a) > 0) {
+                is_src[a] = 1;
+                sb_index[a] = (int32_t)sl.size();
+                sl.push_back(a);
+            }
+        };
+        for (int64_t b = 0; b < nb; ++b) {
+            if (!leaf(b) || ntrg(b) == 0) continue;
+            tb_index[b] = (int32_t)tl.size();
+            tl.push_back((int32_t)b);
+            for (int32_t k = U.h_off[b]; k < U.h_off[b + 1]; ++k) mark_src(U.h_idx[k]);
+            for (int32_t k = W.h_off[b]; k < W.h_off[b + 1]; ++k)
+                if (nsrc(W.h_idx[k]) <= ns) mark_src(W.h_idx[k]);
+            for (int64_t anc = b; anc >= 0; anc = t.h_parent[anc]) {
+                if (ntrg(anc) > ns) continue;
+                for (int32_t k = X.h_off[anc]; k < X.h_off[anc + 1]; ++k) mark_src(X.h_idx[k]);
+            }
+        }
+        auto boxes_of = [&](const std::vector<int32_t> &list, const DBuf<int64_t> &beg, const DBuf<int64_t> &end,
+                            const DBuf<float> &x, const DBuf<float> &y, const DBuf<float> &z) {
+            std::vector<float> h(6 * list.size());
+            if (list.empty()) return h;
+            DBuf<int32_t> dl = upload(list, s);
+            DBuf<float> out(h.size());
+            hipLaunchKernelGGL(k_point_boxes, dim3((unsigned)list.size()), dim3(64), 0, s, dl.p, beg.p, end.p, x.p,
+                               y.p, z.p, out.p);
+            FMM_HIP(hipGetLastError());
+            d2h(h.data(), out.p, h.size(), s);
+            return h;
+        };
+        tbox = t.tsm ? boxes_of(tl, t.tbeg, t.tend, t.tx, t.ty, t.tz) : boxes_of(tl, t.sbeg, t.send, t.sx, t.sy, t.sz);
+        sboxes = boxes_of(sl, t.sbeg, t.send, t.sx, t.sy, t.sz);
+    }
+    const double delta2 = std::max((double)P.opt.cutoff * P.opt.cutoff, (double)std::numeric_limits<float>::min());
+    auto needs_test = [&](int64_t b, int32_t a) {
+        if (a == b) return true;
+        const float *tb = &tbox[6 * (size_t)tb_index[b]], *sb = &sboxes[6 * (size_t)sb_index[a]];
+        double g2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double gap = std::max(0.0, std::max((double)sb[c] - tb[3 + c], (double)tb[c] - sb[3 + c]));
+            g2 += gap * gap;
+        }
+        return g2 <= 1.1 * delta2;
+    };
+    int64_t tested_pairs = 0;
     for (int64_t b = 0; b < nb; ++b) {
         if (!leaf(b) || ntrg(b) == 0) continue;
+        std::vector<int32_t> rt, rf;  // ranges that need the test, ranges that do not
+        auto add_src = [&](int32_t a) {
+            if (nsrc(a) > 0) add_range(needs_test(b, a) ? rt : rf, t.h_sbeg[a], t.h_send[a]);
+        };
         if (lvl(b) >= 2) {
             down_boxes.push_back((int32_t)b);
             sbox.push_back((int32_t)b);
@@ -425,15 +512,12 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             P.surf_evals += ntrg(b) * ns;
         }
         size_t from = prng.size();
-        for (int32_t k = U.h_off[b]; k < U.h_off[b + 1]; ++k) {
-            int32_t a = U.h_idx[k];
-            add_range(prng, t.h_sbeg[a], t.h_send[a]);
-        }
+        for (int32_t k = U.h_off[b]; k < U.h_off[b + 1]; ++k) add_src(U.h_idx[k]);
         for (int32_t k = W.h_off[b]; k < W.h_off[b + 1]; ++k) {
             int32_t a = W.h_idx[k];
             if (nsrc(a) == 0) continue;
             if (nsrc(a) <= ns) {
-                add_range(prng, t.h_sbeg[a], t.h_send[a]);
+                add_src(a);
             } else {
                 sbox.push_back(a);
                 skind.push_back(1);
@@ -443,15 +527,18 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         }
         for (int64_t anc = b; anc >= 0; anc = t.h_parent[anc]) {
             if (ntrg(anc) > ns) continue;
-            for (int32_t k = X.h_off[anc]; k < X.h_off[anc + 1]; ++k) {
-                int32_t a = X.h_idx[k];
-                add_range(prng, t.h_sbeg[a], t.h_send[a]);
-            }
+            for (int32_t k = X.h_off[anc]; k < X.h_off[anc + 1]; ++k) add_src(X.h_idx[k]);
         }
-        merge_ranges(prng, from);
-        int64_t npts = 0;
+        merge_ranges(rt, 0);
+        merge_ranges(rf, 0);
+        prng.insert(prng.end(), rt.begin(), rt.end());
+        pmid.push_back((int32_t)(prng.size() / 2));
+        prng.insert(prng.end(), rf.begin(), rf.end());
+        int64_t npts = 0, ntest = 0;
         for (size_t e = from; e < prng.size(); e += 2) npts += prng[e + 1] - prng[e];
+        for (size_t e = 0; e < rt.size(); e += 2) ntest += rt[e + 1] - rt[e];
         P.p2p_pairs += npts * ntrg(b);
+        tested_pairs += ntest * ntrg(b);
         soff.push_back((int32_t)sbox.size());
         poff.push_back((int32_t)(prng.size() / 2));
         for (int64_t t0 = 0; t0 < ntrg(b); t0 += 64) {
@@ -461,13 +548,15 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
     }
     // soff/poff are indexed by leaf id: expand to all boxes
     {
-        std::vector<int32_t> so(nb + 1, 0), po(nb + 1, 0);
+        std::vector<int32_t> so(nb + 1, 0), po(nb + 1, 0), pm(nb, 0);
         size_t li = 0;
         int32_t cs = 0, cp = 0;
         for (int64_t b = 0; b < nb; ++b) {
             so[b] = cs;
             po[b] = cp;
+            pm[b] = cp;
             if (leaf(b) && ntrg(b) > 0) {
+                pm[b] = pmid[li];
                 cs = soff[li + 1];
                 cp = poff[li + 1];
                 ++li;
@@ -477,6 +566,8 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         po[nb] = cp;
         P.soff = upload(so, s);
         P.poff = upload(po, s);
+        P.pmid = upload(pm, s);
+        P.p2p_tested = tested_pairs;
     }
     P.nwork = (int)wleaf.size();
     P.wleaf = upload(wleaf, s);
@@ -606,6 +697,7 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     e.skind = P.skind.p;
     e.poff = P.poff.p;
     e.prng = P.prng.p;
+    e.pmid = P.pmid.p;
     e.tbeg = t.tbeg.p;
     e.tend = t.tend.p;
     if (t.tsm) {

@@ -59,6 +59,8 @@ struct Plan {
     DBuf<int32_t> m2l_red_cols, m2l_red_slot0, m2l_red_k;  // per cut tile: columns, first slot, pieces
 
     DBuf<int32_t> wleaf, wt0, soff, sbox, poff, prng;
+    DBuf<int32_t> pmid;       // per box: its point ranges [poff, pmid) need the r < delta test
+    int64_t p2p_tested = 0;   // target x source pairs in those ranges
     DBuf<int8_t> skind;
     int nwork = 0;
 

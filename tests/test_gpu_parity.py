@@ -264,6 +264,33 @@ def test_fmm_three_right_hand_sides():
         np.testing.assert_allclose(r["pot"][k], single["pot"][0], rtol=0, atol=1e-6 * np.abs(single["pot"]).max())
 
 
+def test_close_pairs_across_leaf_boundaries():
+    """The tolerance radius (Sec. III.A.1) where pairs straddle leaf
+    boundaries: pairs 0.6 delta apart across the planes x, y, z = 1/2 (a leaf
+    boundary at every level of the unit root) must be excluded, pairs 1.2
+    delta apart included; the setup skips the per-pair test only for point
+    ranges it has shown to be farther apart than delta."""
+    say("test_close_pairs_across_leaf_boundaries: n=21200, p=8, leaf=40, root = unit cube")
+    rng = np.random.default_rng(11)
+    delta = 1e-5
+    pts = [rng.random((20000, 3))]
+    for axis in range(3):
+        for sep in (0.6 * delta, 1.2 * delta):
+            base = rng.random((100, 3))
+            base[:, axis] = 0.5 - sep / 2
+            twin = base.copy()
+            twin[:, axis] = 0.5 + sep / 2
+            pts += [base, twin]
+    x = np.concatenate(pts).astype(np.float32)
+    q = rng.standard_normal(len(x)).astype(np.float32)
+    ref, _ = D.direct_sum(x, x, q, None, delta=delta)
+    r = fmm_run(x, q=q, order=8, leaf=40, root=(0.0, 0.0, 0.0, 1.0), cutoff=delta)
+    e = D.rel_l2(r["pot"][0], ref)
+    worst = np.abs(r["pot"][0] - ref).max() / np.abs(ref).max()
+    say(f"  rel L2 {e:.3e}, worst point {worst:.3e}")
+    assert e < 3e-6 and worst < 1e-4
+
+
 # ------------------------------------------------------------------ edge cases
 def test_edge_cases():
     say("test_edge_cases")
