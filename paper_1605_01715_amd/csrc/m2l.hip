@@ -346,19 +346,23 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
 
 // Cut tiles: out[cols[c]] += partial[slot0] + partial[slot0 + 1] + ... (in
 // piece order, so the result does not depend on which piece ran first).
-__global__ void k_m2l_reduce(int r_pad, int ncol, const int32_t *cols, const int32_t *slot0, const int32_t *kpieces,
-                             const float *partial, float *out) {
+// Block (tile, g) adds columns 16 g .. 16 g + 15, four values per thread.
+constexpr int kRedCols = 16;
+__global__ __launch_bounds__(256) void k_m2l_reduce(int r_pad, int ncol, const int32_t *cols, const int32_t *slot0,
+                                                    const int32_t *kpieces, const float *partial, float *out) {
     const int tl = blockIdx.x;
     const int k = kpieces[tl];
-    const size_t per = (size_t)ncol * r_pad;
-    const float *p = partial + (size_t)slot0[tl] * per;
-    for (int idx = threadIdx.x; idx < ncol * r_pad; idx += 256) {
-        const int c = idx / r_pad;
+    const size_t per = (size_t)ncol * r_pad;  // floats per slot
+    const int q4 = r_pad / 4;
+    for (int idx = threadIdx.x; idx < kRedCols * q4; idx += 256) {
+        const int c = blockIdx.y * kRedCols + idx / q4, r4 = (idx % q4) * 4;
         const int v = cols[(size_t)tl * ncol + c];
         if (v < 0) continue;
-        float sum = p[idx];
-        for (int q = 1; q < k; ++q) sum += p[q * per + idx];
-        out[(size_t)v * r_pad + idx % r_pad] += sum;
+        const float *p = partial + (size_t)slot0[tl] * per + (size_t)c * r_pad + r4;
+        f32x4 sum = *(const f32x4 *)p;
+        for (int q = 1; q < k; ++q) sum += *(const f32x4 *)(p + q * per);
+        f32x4 *o = (f32x4 *)(out + (size_t)v * r_pad + r4);
+        *o = *o + sum;
     }
 }
 
@@ -495,7 +499,9 @@ int m2l_blocks_per_cu(bool bf16, int r_pad) {
 void m2l_reduce(int r_pad, int ntile, int ncol, const int32_t *cols, const int32_t *slot0, const int32_t *kpieces,
                 const float *partial, float *out, hipStream_t s) {
     if (ntile <= 0) return;
-    hipLaunchKernelGGL(k_m2l_reduce, dim3(ntile), dim3(256), 0, s, r_pad, ncol, cols, slot0, kpieces, partial, out);
+    FMM_REQUIRE(ncol % kRedCols == 0 && r_pad % 4 == 0, "m2l_reduce: unsupported tile shape");
+    hipLaunchKernelGGL(k_m2l_reduce, dim3(ntile, ncol / kRedCols), dim3(256), 0, s, r_pad, ncol, cols, slot0, kpieces,
+                       partial, out);
     FMM_HIP(hipGetLastError());
 }
 

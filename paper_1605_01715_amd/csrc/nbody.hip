@@ -85,19 +85,22 @@ __global__ __launch_bounds__(64) void k_points_to_surface(const int32_t *items, 
 #pragma unroll
                 for (int i = 0; i < TPL; ++i) {
                     if (i >= ntpl) continue;  // static index keeps acc in registers
-                    float dx = xm[i] - sx, dy = ym[i] - sy, dz = zm[i] - sz;
-                    float r2 = dx * dx + dy * dy + dz * dz;
-                    float inv = r2 > 0.f ? rsq(r2) : 0.f;
-                    int o = 3;
-                    if (SL)
-                        for (int r = 0; r < NRHS; ++r) acc[i][r] += (double)(p[o++] * inv);
-                    if (DL) {
-                        float inv3 = inv * inv * inv;
-                        for (int r = 0; r < NRHS; ++r) {
-                            float md = p[o] * dx + p[o + 1] * dy + p[o + 2] * dz;
-                            o += 3;
-                            acc[i][r] += (double)(md * inv3);
+                    const float dx = xm[i] - sx, dy = ym[i] - sy, dz = zm[i] - sz;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    // check points lie outside every box that feeds them (P2M: radius 2.95 around the
+                    // sources' own box; P2L: X-list boxes are a box width away), so r > 0; the floor
+                    // only keeps a degenerate input finite
+                    const float inv = rsq(fmaxf(r2, 1e-30f));
+                    const float inv2 = inv * inv;
+#pragma unroll
+                    for (int r = 0; r < NRHS; ++r) {
+                        // q / r + (m . d) / r^3 = (q + (m . d) / r^2) / r, one float64 add per pair
+                        float t = SL ? p[3 + r] : 0.f;
+                        if (DL) {
+                            const int o = 3 + (SL ? NRHS : 0) + 3 * r;
+                            t += (p[o] * dx + p[o + 1] * dy + p[o + 2] * dz) * inv2;
                         }
+                        acc[i][r] += (double)(t * inv);
                     }
                 }
             }
