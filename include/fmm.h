@@ -231,6 +231,8 @@ typedef struct {
                                             the far-field state of a box is r values per rhs */
     int64_t m2l_pieces;                  /* M2L work items per tile of 128 target boxes (load
                                             balance across CUs; pieces add up in a fixed order) */
+    int64_t m2l_pair_tiles;              /* M2L work items of one direction whose columns are
+                                            (target, source) pairs (sparse V lists) */
     double root[4];                      /* root cube actually used */
     double setup_ms;                     /* wall time of fmm_setup */
 } fmm_info;

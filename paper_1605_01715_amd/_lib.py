@@ -33,7 +33,7 @@ class FmmOperator(ctypes.Structure):
 class FmmInfo(ctypes.Structure):
     _fields_ = [(n, c_int64) for n in ("n_src", "n_trg", "n_points", "n_boxes", "n_leaves", "n_levels", "n_u", "n_v",
                                        "n_w", "n_x", "n_surface", "p2p_pairs", "m2l_pairs", "surf_evals",
-                                       "p2m_evals", "m2l_columns", "rank", "m2l_pieces")] + [("root", c_double * 4),
+                                       "p2m_evals", "m2l_columns", "rank", "m2l_pieces", "m2l_pair_tiles")] + [("root", c_double * 4),
                                                                                  ("setup_ms", c_double)]
 
 

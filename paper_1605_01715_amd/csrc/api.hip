@@ -375,6 +375,7 @@ int fmm_plan_info(fmm_plan plan, fmm_info *info) {
         r.m2l_columns = P.m2l_steps * P.m2l_ncol;
         r.rank = P.r;
         r.m2l_pieces = P.m2l_pieces_per_tile;
+        r.m2l_pair_tiles = P.m2l_pair_tiles;
         for (int c = 0; c < 3; ++c) r.root[c] = P.t.x0[c];
         r.root[3] = P.t.w;
         r.setup_ms = P.setup_ms;

@@ -366,6 +366,22 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(int r_pad, int ncol, const i
     }
 }
 
+// Pair tiles: out[targets[t]] += the partial rows rows[off[t]] .. rows[off[t+1] - 1]
+// (row i at partial + i * r_pad), in the given (direction) order. One wave per
+// target, four values per lane.
+__global__ __launch_bounds__(256) void k_m2l_gather(int r_pad, int n, const int32_t *targets, const int32_t *off,
+                                                    const int32_t *rows, const float *partial, float *out) {
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (t >= n) return;
+    const int v = targets[t], e0 = off[t], e1 = off[t + 1];
+    for (int r4 = 4 * lane; r4 < r_pad; r4 += 256) {
+        f32x4 sum = *(const f32x4 *)(partial + (size_t)rows[e0] * r_pad + r4);
+        for (int e = e0 + 1; e < e1; ++e) sum += *(const f32x4 *)(partial + (size_t)rows[e] * r_pad + r4);
+        f32x4 *o = (f32x4 *)(out + (size_t)v * r_pad + r4);
+        *o = *o + sum;
+    }
+}
+
 // Matrices [ndir][r_pad][r_pad] float32 -> split-BF16 chunks in LDS image order.
 __global__ void k_split_mats(const float *rm, int r_pad, int64_t total, uint16_t *out) {
     int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -502,6 +518,14 @@ void m2l_reduce(int r_pad, int ntile, int ncol, const int32_t *cols, const int32
     FMM_REQUIRE(ncol % kRedCols == 0 && r_pad % 4 == 0, "m2l_reduce: unsupported tile shape");
     hipLaunchKernelGGL(k_m2l_reduce, dim3(ntile, ncol / kRedCols), dim3(256), 0, s, r_pad, ncol, cols, slot0, kpieces,
                        partial, out);
+    FMM_HIP(hipGetLastError());
+}
+
+void m2l_gather(int r_pad, int n, const int32_t *targets, const int32_t *off, const int32_t *rows,
+                const float *partial, float *out, hipStream_t s) {
+    if (n <= 0) return;
+    FMM_REQUIRE(r_pad % 4 == 0, "m2l_gather: unsupported state size");
+    hipLaunchKernelGGL(k_m2l_gather, dim3((n + 3) / 4), dim3(256), 0, s, r_pad, n, targets, off, rows, partial, out);
     FMM_HIP(hipGetLastError());
 }
 

@@ -37,6 +37,9 @@ int m2l_blocks_per_cu(bool bf16, int r_pad);  // workgroups of the kernel that f
 // cut tiles: out[cols[t][c]] += sum over q < kpieces[t] of partial[slot0[t] + q][c] (q in order)
 void m2l_reduce(int r_pad, int ntile, int ncol, const int32_t *cols, const int32_t *slot0, const int32_t *kpieces,
                 const float *partial, float *out, hipStream_t s);
+// pair tiles: out[targets[t]] += sum over e in [off[t], off[t+1]) of partial row rows[e] (in order)
+void m2l_gather(int r_pad, int n, const int32_t *targets, const int32_t *off, const int32_t *rows,
+                const float *partial, float *out, hipStream_t s);
 bool m2l_supported(int r_pad);  // any multiple of 32 up to 512
 void m2l_run(bool bf16, const M2LLaunch &a, hipStream_t s);
 

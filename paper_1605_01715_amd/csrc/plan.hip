@@ -255,6 +255,83 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             }
             toff.push_back((int64_t)tdir.size());
         }
+        // Sparse tiles become pair tiles. Where boxes have few and varied V
+        // partners (points on surfaces), a tile runs every direction for
+        // only a fraction of its columns (fill 0.2-0.3 on the sphere
+        // workloads). The (direction, target, source) triples of tiles with
+        // fill below kPairFill are regrouped by octant and direction into
+        // tiles of one direction whose columns are pairs, all live; each
+        // writes its products to a partial-sum slot, and a gather adds each
+        // target's partials in direction order. Costs: a tile does 6 steps per
+        // direction; a pair tile 6 steps plus writing and reading back its
+        // partials (about 3 more), so the switch pays below fill 0.6.
+        constexpr double kPairFill = 0.6;
+        std::vector<uint8_t> pair_tile(ntile, 0);
+        {
+            struct PairE {
+                int32_t dir, v, sv;
+            };
+            std::vector<std::vector<PairE>> pool(8);
+            std::vector<uint8_t> keep(ntile, 1);
+            bool moved = false;
+            for (int tl = 0; tl < ntile; ++tl) {
+                const int64_t n = toff[tl + 1] - toff[tl];
+                int64_t live = 0;
+                for (int64_t e = toff[tl]; e < toff[tl + 1]; ++e)
+                    for (int c = 0; c < nc; ++c) live += tsrc[(size_t)e * nc + c] >= 0;
+                if (n == 0 || (double)live >= kPairFill * (double)n * nc) continue;
+                keep[tl] = 0;
+                moved = true;
+                for (int64_t e = toff[tl]; e < toff[tl + 1]; ++e)
+                    for (int c = 0; c < nc; ++c) {
+                        const int32_t sv = tsrc[(size_t)e * nc + c];
+                        if (sv >= 0) pool[tile_oct[tl]].push_back({tdir[e], cols[(size_t)tl * nc + c], sv});
+                    }
+            }
+            if (moved) {
+                std::vector<int64_t> toff2{0};
+                std::vector<int32_t> tdir2, tsrc2, cols2;
+                std::vector<int> oct2;
+                std::vector<uint8_t> pair2;
+                for (int tl = 0; tl < ntile; ++tl) {
+                    if (!keep[tl]) continue;
+                    for (int64_t e = toff[tl]; e < toff[tl + 1]; ++e) {
+                        tdir2.push_back(tdir[e]);
+                        tsrc2.insert(tsrc2.end(), tsrc.begin() + (size_t)e * nc, tsrc.begin() + (size_t)(e + 1) * nc);
+                    }
+                    toff2.push_back((int64_t)tdir2.size());
+                    cols2.insert(cols2.end(), cols.begin() + (size_t)tl * nc, cols.begin() + (size_t)(tl + 1) * nc);
+                    oct2.push_back(tile_oct[tl]);
+                    pair2.push_back(0);
+                }
+                for (int o = 0; o < 8; ++o) {
+                    auto &v = pool[o];
+                    std::sort(v.begin(), v.end(), [](const PairE &x, const PairE &y) {
+                        return x.dir != y.dir ? x.dir < y.dir : x.v < y.v;
+                    });
+                    for (size_t i = 0; i < v.size();) {
+                        size_t j = i;
+                        while (j < v.size() && j - i < (size_t)nc && v[j].dir == v[i].dir) ++j;
+                        tdir2.push_back(v[i].dir);
+                        for (size_t q = i; q < i + nc; ++q) {
+                            cols2.push_back(q < j ? v[q].v : -1);
+                            tsrc2.push_back(q < j ? v[q].sv : -1);
+                        }
+                        toff2.push_back((int64_t)tdir2.size());
+                        oct2.push_back(o);
+                        pair2.push_back(1);
+                        i = j;
+                    }
+                }
+                toff.swap(toff2);
+                tdir.swap(tdir2);
+                tsrc.swap(tsrc2);
+                cols.swap(cols2);
+                tile_oct.swap(oct2);
+                pair_tile.swap(pair2);
+                ntile = (int)pair_tile.size();
+            }
+        }
         // Launch order: the kernel gives XCD x the x-th eighth of the work
         // items. XCD x runs the tiles of octant x: they draw on the same 189
         // directions in the same order, so tiles running at the same time
@@ -314,10 +391,23 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             };
             std::vector<std::vector<Piece>> per_oct(8);
             std::vector<int32_t> red_cols, red_slot0, red_k;
+            struct GatherE {
+                int32_t v, dir, idx;  // target vector, direction, partial row slot * nc + column
+            };
+            std::vector<GatherE> gather;
             int nslot = 0;
             for (int tl = 0; tl < ntile; ++tl) {
                 const int n = ndir(tl), kk = std::max(1, std::min(kbest, n));
                 if (n == 0) continue;
+                if (pair_tile[tl]) {  // one direction, its own slot, summed by the gather
+                    const int slot = nslot++;
+                    for (int c = 0; c < nc; ++c) {
+                        const int32_t v = cols[(size_t)tl * nc + c];
+                        if (v >= 0) gather.push_back({v, tdir[toff[tl]], slot * nc + c});
+                    }
+                    per_oct[tile_oct[tl]].push_back({tl, (int)toff[tl], (int)toff[tl + 1], slot});
+                    continue;
+                }
                 const int slot0 = kk > 1 ? nslot : -1;
                 if (kk > 1) {
                     red_cols.insert(red_cols.end(), cols.begin() + (size_t)tl * nc, cols.begin() + (size_t)(tl + 1) * nc);
@@ -360,11 +450,31 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             ntile = (int)(8 * len);
             P.m2l_slot = upload(slot2, s);
             P.m2l_nsplit = (int)red_k.size();
+            if (nslot > 0) P.m2l_partial.alloc((size_t)nslot * nc * P.r_pad);
             if (P.m2l_nsplit > 0) {
-                P.m2l_partial.alloc((size_t)nslot * nc * P.r_pad);
                 P.m2l_red_cols = upload(red_cols, s);
                 P.m2l_red_slot0 = upload(red_slot0, s);
                 P.m2l_red_k = upload(red_k, s);
+            }
+            // pair tiles: per target vector, its partial rows in direction order
+            std::sort(gather.begin(), gather.end(), [](const GatherE &x, const GatherE &y) {
+                return x.v != y.v ? x.v < y.v : x.dir < y.dir;
+            });
+            std::vector<int32_t> gt, goff{0}, gidx;
+            for (size_t i = 0; i < gather.size(); ++i) {
+                if (i == 0 || gather[i].v != gather[i - 1].v) {
+                    if (i > 0) goff.push_back((int32_t)i);
+                    gt.push_back(gather[i].v);
+                }
+                gidx.push_back(gather[i].idx);
+            }
+            if (!gather.empty()) goff.push_back((int32_t)gather.size());
+            P.m2l_ngather = (int)gt.size();
+            P.m2l_pair_tiles = (int)std::count(pair_tile.begin(), pair_tile.end(), 1);
+            if (P.m2l_ngather > 0) {
+                P.m2l_gt = upload(gt, s);
+                P.m2l_goff = upload(goff, s);
+                P.m2l_gidx = upload(gidx, s);
             }
         }
         P.m2l_ntile = ntile;
@@ -681,6 +791,8 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         if (P.m2l_nsplit > 0)
             m2l_reduce(rp, P.m2l_nsplit, P.m2l_ncol, P.m2l_red_cols.p, P.m2l_red_slot0.p, P.m2l_red_k.p, P.m2l_partial.p,
                        P.dt.p, s);
+        if (P.m2l_ngather > 0)
+            m2l_gather(rp, P.m2l_ngather, P.m2l_gt.p, P.m2l_goff.p, P.m2l_gidx.p, P.m2l_partial.p, P.dt.p, s);
     }
     mark(ST_L2L);
     for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, rp, rp, P.dt.p, P.dt.p, nullptr, true, s);

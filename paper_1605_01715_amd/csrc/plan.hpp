@@ -57,6 +57,8 @@ struct Plan {
     int m2l_nsplit = 0, m2l_pieces_per_tile = 1;  // tiles cut into pieces; pieces per cut tile
     DBuf<float> m2l_partial;                      // [slot][ncol][r_pad] partial sums of cut tiles
     DBuf<int32_t> m2l_red_cols, m2l_red_slot0, m2l_red_k;  // per cut tile: columns, first slot, pieces
+    int m2l_ngather = 0, m2l_pair_tiles = 0;              // pair tiles: targets gathered, tiles
+    DBuf<int32_t> m2l_gt, m2l_goff, m2l_gidx;             // per target vector: its partial rows (CSR)
 
     DBuf<int32_t> wleaf, wt0, soff, sbox, poff, prng;
     DBuf<int32_t> pmid;       // per box: its point ranges [poff, pmid) need the r < delta test

@@ -264,6 +264,34 @@ def test_fmm_three_right_hand_sides():
         np.testing.assert_allclose(r["pot"][k], single["pot"][0], rtol=0, atol=1e-6 * np.abs(single["pot"]).max())
 
 
+def test_sparse_v_lists_use_pair_tiles():
+    """Points on surfaces: boxes have few and varied V partners, so M2L runs
+    (target, source) pair tiles of one direction whose partials are gathered
+    per target in direction order; potentials against the float64 direct sum
+    in both forms, bit-identical run to run."""
+    import workloads as Wk
+
+    say("test_sparse_v_lists_use_pair_tiles: 4 spheres of 3920 points, p=8, leaf=40")
+    centres = ((0, 0, 0), (2.5, 0, 0), (0, 2.5, 0), (2.5, 2.5, 0.5))
+    parts = [Wk.sphere_quadrature(14, np.array(c, float), 1.0) for c in centres]
+    x = np.concatenate([p[0] for p in parts]).astype(np.float32)
+    nrm = np.concatenate([p[1] for p in parts]).astype(np.float32)
+    rng = np.random.default_rng(13)
+    q = rng.standard_normal(len(x)).astype(np.float32)
+    mu = rng.standard_normal(len(x)).astype(np.float32)
+    ref, _ = D.direct_sum(x, x, q, mu[:, None].astype(np.float64) * nrm)
+    for precision in (0, 1):
+        r = fmm_run(x, q=q, mu=mu, nrm=nrm, order=8, leaf=40, precision=precision)
+        again = fmm_run(x, q=q, mu=mu, nrm=nrm, order=8, leaf=40, precision=precision)
+        e = D.rel_l2(r["pot"][0], ref)
+        info = r["info"]
+        say(f"  precision {precision}: pair tiles {info['m2l_pair_tiles']}, fill "
+            f"{info['m2l_pairs'] / info['m2l_columns']:.2f}, rel L2 {e:.2e}")
+        assert info["m2l_pair_tiles"] > 0
+        assert e < 3e-6
+        assert np.array_equal(again["pot"], r["pot"])
+
+
 def test_close_pairs_across_leaf_boundaries():
     """The tolerance radius (Sec. III.A.1) where pairs straddle leaf
     boundaries: pairs 0.6 delta apart across the planes x, y, z = 1/2 (a leaf
