@@ -36,6 +36,29 @@ __device__ inline void two_sum_into(float &hi, float &lo, float p) {
 }
 
 // ------------------------------------------------------------ P2M / P2L
+
+// q / r + (m . d) / r^3 = (q + (m . d) / r^2) / r for one (surface point,
+// source) pair; v holds the source's offset from the box centre, then its
+// strengths. Check points lie outside every box that feeds them (P2M: radius
+// 2.95 around the sources' own box; P2L: X-list boxes are a box width away),
+// so r > 0; the floor only keeps a degenerate input finite.
+template <int NRHS, bool SL, bool DL>
+__device__ inline void pair_terms(float x, float y, float z, const float *v, float *t) {
+    const float dx = x - v[0], dy = y - v[1], dz = z - v[2];
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float inv = rsq(fmaxf(r2, 1e-30f));
+    const float inv2 = inv * inv;
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) {
+        float u = SL ? v[3 + r] : 0.f;
+        if (DL) {
+            const int o = 3 + (SL ? NRHS : 0) + 3 * r;
+            u += (v[o] * dx + v[o + 1] * dy + v[o + 2] * dz) * inv2;
+        }
+        t[r] = u * inv;
+    }
+}
+
 template <int NRHS, bool SL, bool DL>
 __global__ __launch_bounds__(64) void k_points_to_surface(const int32_t *items, const int32_t *roff,
                                                          const int32_t *rng, double rfac, SurfaceGeom g,
@@ -48,7 +71,8 @@ __global__ __launch_bounds__(64) void k_points_to_surface(const int32_t *items, 
     const double cx = g.centre[3 * b], cy = g.centre[3 * b + 1], cz = g.centre[3 * b + 2];
     const double rr = rfac * g.half[b];
     float xm[TPL], ym[TPL], zm[TPL];
-    double acc[TPL][NRHS];  // float64 sums: check potentials feed every translation
+    // float64 sums (of float32 sums of two pairs): check potentials feed every translation
+    double acc[TPL][NRHS];
     for (int i = 0; i < TPL; ++i) {
         int m = lane + 64 * i;
         bool ok = m < g.ns;
@@ -63,45 +87,44 @@ __global__ __launch_bounds__(64) void k_points_to_surface(const int32_t *items, 
         for (int j0 = s0; j0 < s1; j0 += 64) {
             const int j = j0 + lane;
             const int cnt = min(64, s1 - j0);
-            if (j < s1) {
+            {
+                // lanes past the range stage a zero-strength source at the box centre (r > 0 from
+                // every check point), so the pair loop below can run over an even count
                 float *p = sh + lane * W;
-                p[0] = (float)((double)src.x[j] - cx);
-                p[1] = (float)((double)src.y[j] - cy);
-                p[2] = (float)((double)src.z[j] - cz);
-                int o = 3;
-                if (SL)
-                    for (int r = 0; r < NRHS; ++r) p[o++] = src.q[r * src.n + j];
-                if (DL)
-                    for (int r = 0; r < NRHS; ++r) {
-                        p[o++] = src.mx[r * src.n + j];
-                        p[o++] = src.my[r * src.n + j];
-                        p[o++] = src.mz[r * src.n + j];
-                    }
+#pragma unroll
+                for (int k = 0; k < W; ++k) p[k] = 0.f;
+                if (j < s1) {
+                    p[0] = (float)((double)src.x[j] - cx);
+                    p[1] = (float)((double)src.y[j] - cy);
+                    p[2] = (float)((double)src.z[j] - cz);
+                    int o = 3;
+                    if (SL)
+                        for (int r = 0; r < NRHS; ++r) p[o++] = src.q[r * src.n + j];
+                    if (DL)
+                        for (int r = 0; r < NRHS; ++r) {
+                            p[o++] = src.mx[r * src.n + j];
+                            p[o++] = src.my[r * src.n + j];
+                            p[o++] = src.mz[r * src.n + j];
+                        }
+                }
             }
             __syncthreads();
-            for (int jj = 0; jj < cnt; ++jj) {
-                const float *p = sh + jj * W;
-                const float sx = p[0], sy = p[1], sz = p[2];
+            for (int jj = 0; jj < cnt; jj += 2) {
+                // two sources per step, read into registers once for all surface points
+                float v0[W], v1[W];
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    v0[k] = sh[jj * W + k];
+                    v1[k] = sh[(jj + 1) * W + k];
+                }
 #pragma unroll
                 for (int i = 0; i < TPL; ++i) {
                     if (i >= ntpl) continue;  // static index keeps acc in registers
-                    const float dx = xm[i] - sx, dy = ym[i] - sy, dz = zm[i] - sz;
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    // check points lie outside every box that feeds them (P2M: radius 2.95 around the
-                    // sources' own box; P2L: X-list boxes are a box width away), so r > 0; the floor
-                    // only keeps a degenerate input finite
-                    const float inv = rsq(fmaxf(r2, 1e-30f));
-                    const float inv2 = inv * inv;
+                    float t0[NRHS], t1[NRHS];
+                    pair_terms<NRHS, SL, DL>(xm[i], ym[i], zm[i], v0, t0);
+                    pair_terms<NRHS, SL, DL>(xm[i], ym[i], zm[i], v1, t1);
 #pragma unroll
-                    for (int r = 0; r < NRHS; ++r) {
-                        // q / r + (m . d) / r^3 = (q + (m . d) / r^2) / r, one float64 add per pair
-                        float t = SL ? p[3 + r] : 0.f;
-                        if (DL) {
-                            const int o = 3 + (SL ? NRHS : 0) + 3 * r;
-                            t += (p[o] * dx + p[o + 1] * dy + p[o + 2] * dz) * inv2;
-                        }
-                        acc[i][r] += (double)(t * inv);
-                    }
+                    for (int r = 0; r < NRHS; ++r) acc[i][r] += (double)(t0[r] + t1[r]);
                 }
             }
             __syncthreads();
