@@ -12,6 +12,8 @@ Contents (each function cites the passage of the paper it follows):
   tree         Morton keys, the octree and the U/V/W/X interaction lists,
                written from their plain definitions
   kifmm        the kernel-independent FMM, step by step in float64
+  chebyshev    the paper's own far-field form: Chebyshev interpolation with
+               the method-2 normal derivative at P2M (Sec. III.A.1 Eq. p2m)
   gmres        restarted GMRES(m) with modified Gram-Schmidt and Givens
                rotations (the solver the paper runs matrix-free, Sec. III)
   operators    the boundary operators of the two model problems
