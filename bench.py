@@ -33,10 +33,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_form(F, torch, x, nrm, q, mu, precision, order, leaf, steps, warmup, eps=0.0):
+def run_form(F, torch, x, nrm, q, mu, precision, order, leaf, steps, warmup, eps=0.0, basis=0):
     opts = F.fmm_default_options(order=order, leaf_size=leaf, precision=precision,
                                  src_kernels=F.FMM_SRC_SINGLE | F.FMM_SRC_DOUBLE, outputs=F.FMM_OUT_POT,
-                                 root=(0.0, 0.0, 0.0, 1.0), pinv_eps=eps)
+                                 root=(0.0, 0.0, 0.0, 1.0), pinv_eps=eps, basis=basis)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan = F.fmm_setup(x, nrm, options=opts)

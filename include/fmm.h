@@ -64,9 +64,23 @@ enum { FMM_OUT_POT = 1, FMM_OUT_FIELD = 2 };
  * into three bfloat16 parts and sums six partial products with float32
  * accumulation on the matrix cores. */
 enum { FMM_PREC_FP32 = 0, FMM_PREC_SPLIT_BF16 = 1 };
+/* Far-field representation of a box (Sec. III.A.1 Eq. p2m: the far field is
+ * interpolated at the sources, translated with the plain 1/r kernel, and
+ * interpolated at the targets).
+ * SURFACE: equivalent densities on a box surface of p points per edge,
+ *   fitted to the potential on a check surface (kernel-independent FMM in the
+ *   equivalent-surface form).
+ * CHEBYSHEV: the paper's own form. Weights at the n^3 tensor-product Chebyshev
+ *   nodes of the box (n = order, 2..8): P2M interpolates the sources onto the
+ *   nodes, with the double layer's normal derivative applied to the
+ *   interpolating polynomial; M2L is the 1/r kernel between node sets, kept as
+ *   r x r matrices in a basis shared by all 316 directions (truncated at
+ *   pinv_eps, the SVD threshold); L2P interpolates back to the targets. */
+enum { FMM_BASIS_SURFACE = 0, FMM_BASIS_CHEBYSHEV = 1 };
 
 typedef struct {
-    int order;          /* p: points per edge of the equivalent/check surfaces, 2..10 */
+    int order;          /* SURFACE: p, points per edge of the equivalent/check surfaces, 2..10;
+                           CHEBYSHEV: n, interpolation nodes per axis, 2..8 */
     int leaf_size;      /* s: adaptive tree splits boxes holding more than s points (targets + sources) */
     int uniform_depth;  /* > 0: uniform tree, every box above this level is split (0 = adaptive) */
     int max_depth;      /* deepest level, <= 21 */
@@ -76,13 +90,16 @@ typedef struct {
     int nrhs;           /* number of density vectors per apply, 1..4 */
     float cutoff;       /* tolerance radius (Sec. III.A.1), e.g. 1e-5; r < cutoff excluded, r == 0 always */
     double root[4];     /* root cube x0, y0, z0, width; width <= 0: derived from the points */
-    double pinv_eps;    /* relative SVD truncation of the check-to-equivalent maps; <= 0: default */
+    double pinv_eps;    /* relative SVD truncation (SURFACE: of the check-to-equivalent maps;
+                           CHEBYSHEV: of the shared M2L basis); <= 0: default */
     int m2l_pieces;     /* M2L work items per tile of target boxes, 1..8; 0: chosen at setup by
                            simulating the dispatch on the GPU's compute units (the default) */
+    int basis;          /* FMM_BASIS_*: far-field representation (default SURFACE) */
 } fmm_options;
 
 /* Fill `opt` with defaults: order 6, leaf_size 64, adaptive, max_depth 21, FP32,
- * single layer, potential, nrhs 1, cutoff 1e-5, root derived, default pinv_eps. */
+ * single layer, potential, nrhs 1, cutoff 1e-5, root derived, default pinv_eps,
+ * surface basis. */
 void fmm_default_options(fmm_options *opt);
 
 /*
@@ -220,19 +237,22 @@ typedef struct {
     int64_t n_src, n_trg, n_points;      /* points inserted in the tree = n_points */
     int64_t n_boxes, n_leaves, n_levels;
     int64_t n_u, n_v, n_w, n_x;          /* list entries (U counts leaf pairs, self included) */
-    int64_t n_surface;                   /* n_s = 6 (p-1)^2 + 2 */
+    int64_t n_surface;                   /* points of a box's far-field representation: n_s =
+                                            6 (p-1)^2 + 2 surface points, or n^3 Chebyshev nodes */
     int64_t p2p_pairs;                   /* near-field point pairs evaluated per apply */
     int64_t m2l_pairs;                   /* M2L box pairs (V-list entries with sources) per rhs */
     int64_t surf_evals;                  /* target x surface-point evaluations (L2P + M2P) per rhs */
     int64_t p2m_evals;                   /* surface-point x source evaluations (P2M + P2L) per rhs */
     int64_t m2l_columns;                 /* matrix-vector products the M2L kernel computes, padding
                                             included (m2l_pairs / m2l_columns is its fill) */
-    int64_t rank;                        /* r: singular values of the check-from-equivalent map kept;
-                                            the far-field state of a box is r values per rhs */
+    int64_t rank;                        /* r: singular values kept (SURFACE: of the check-from-
+                                            equivalent map; CHEBYSHEV: of the shared M2L basis);
+                                            M2L acts on r values per box and rhs */
     int64_t m2l_pieces;                  /* M2L work items per tile of 128 target boxes (load
                                             balance across CUs; pieces add up in a fixed order) */
     int64_t m2l_pair_tiles;              /* M2L work items of one direction whose columns are
                                             (target, source) pairs (sparse V lists) */
+    int64_t basis;                       /* FMM_BASIS_* of the plan */
     double root[4];                      /* root cube actually used */
     double setup_ms;                     /* wall time of fmm_setup */
 } fmm_info;
@@ -290,6 +310,9 @@ int fmm_set_graph(fmm_plan plan, int enable);
  *            left singular vectors, [n_boxes][n_s];
  * which = 1: V_r V_r^T d, the same for the downward check potential after the
  *            parent's contribution, [n_boxes][n_s].
+ * For a CHEBYSHEV plan the node values themselves are written: which = 0 the
+ * multipole weights W, which = 1 the local expansion L at the nodes (after
+ * M2L, P2L and L2L), [n_boxes][n^3].
  * Boxes that were not computed hold zeros.
  */
 int fmm_export_stage(fmm_plan plan, int which, float *host_out);

@@ -124,7 +124,9 @@ def interp_3d_grad(n, t):
 class ChebOperators:
     """Unit-box nodes, M2M/L2L interpolation matrices and M2L translations."""
 
-    def __init__(self, n, eps=0.0):
+    def __init__(self, n, eps=0.0, rank=None):
+        """eps > 0: compressed translations truncated at eps * sigma_max;
+        rank: compressed, keeping exactly that many singular vectors."""
         self.n = n
         self.eps = eps
         self.X = nodes_3d(n)
@@ -135,11 +137,12 @@ class ChebOperators:
         self._dense = {}
         self.rank = self.nn
         self.U = self.V = None
-        if eps > 0:
+        if eps > 0 or rank is not None:
             ks = [self.dense(k) for k in range(len(self.dirs))]
             uf, sf, _ = np.linalg.svd(np.hstack(ks), full_matrices=False)
             _, st, vt = np.linalg.svd(np.vstack(ks), full_matrices=False)
-            r = max(int(np.sum(sf > eps * sf[0])), int(np.sum(st > eps * st[0])))
+            self.sigma = sf
+            r = max(int(np.sum(sf > eps * sf[0])), int(np.sum(st > eps * st[0]))) if rank is None else rank
             self.rank = r
             self.U = uf[:, :r]
             self.V = vt[:r].T

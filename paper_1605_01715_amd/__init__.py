@@ -14,9 +14,9 @@ import ctypes
 import numpy as np
 
 from . import _lib as L
-from ._lib import (FMM_ERR_ARG, FMM_ERR_DEVICE, FMM_ERR_NOMEM, FMM_ERR_NOT_CONVERGED, FMM_ERR_STATE, FMM_OK,
-                   FMM_OP_DIELECTRIC, FMM_OP_FK, FMM_OUT_FIELD, FMM_OUT_POT, FMM_PREC_FP32, FMM_PREC_SPLIT_BF16,
-                   FMM_SRC_DOUBLE, FMM_SRC_SINGLE, STAGES)
+from ._lib import (FMM_BASIS_CHEBYSHEV, FMM_BASIS_SURFACE, FMM_ERR_ARG, FMM_ERR_DEVICE, FMM_ERR_NOMEM,
+                   FMM_ERR_NOT_CONVERGED, FMM_ERR_STATE, FMM_OK, FMM_OP_DIELECTRIC, FMM_OP_FK, FMM_OUT_FIELD,
+                   FMM_OUT_POT, FMM_PREC_FP32, FMM_PREC_SPLIT_BF16, FMM_SRC_DOUBLE, FMM_SRC_SINGLE, STAGES)
 
 __all__ = ["fmm_setup_batch", "Plan", "FmmError", "fmm_default_options", "fmm_setup", "fmm_apply", "gmres_solve", "fmm_destroy",
            "fmm_last_error", "fmm_direct", "fmm_plan_info", "fmm_export_tree", "fmm_export_stage",

@@ -16,6 +16,7 @@ FMM_OK, FMM_ERR_ARG, FMM_ERR_NOMEM, FMM_ERR_DEVICE, FMM_ERR_NOT_CONVERGED, FMM_E
 FMM_SRC_SINGLE, FMM_SRC_DOUBLE = 1, 2
 FMM_OUT_POT, FMM_OUT_FIELD = 1, 2
 FMM_PREC_FP32, FMM_PREC_SPLIT_BF16 = 0, 1
+FMM_BASIS_SURFACE, FMM_BASIS_CHEBYSHEV = 0, 1
 FMM_OP_FK, FMM_OP_DIELECTRIC = 1, 2
 STAGES = ("P2M", "M2M", "P2L", "M2L", "L2L", "C2E", "EVAL")
 
@@ -23,7 +24,8 @@ STAGES = ("P2M", "M2M", "P2L", "M2L", "L2L", "C2E", "EVAL")
 class FmmOptions(ctypes.Structure):
     _fields_ = [("order", c_int), ("leaf_size", c_int), ("uniform_depth", c_int), ("max_depth", c_int),
                 ("precision", c_int), ("src_kernels", c_int), ("outputs", c_int), ("nrhs", c_int),
-                ("cutoff", c_float), ("root", c_double * 4), ("pinv_eps", c_double), ("m2l_pieces", c_int)]
+                ("cutoff", c_float), ("root", c_double * 4), ("pinv_eps", c_double), ("m2l_pieces", c_int),
+                ("basis", c_int)]
 
 
 class FmmOperator(ctypes.Structure):
@@ -33,7 +35,7 @@ class FmmOperator(ctypes.Structure):
 class FmmInfo(ctypes.Structure):
     _fields_ = [(n, c_int64) for n in ("n_src", "n_trg", "n_points", "n_boxes", "n_leaves", "n_levels", "n_u", "n_v",
                                        "n_w", "n_x", "n_surface", "p2p_pairs", "m2l_pairs", "surf_evals",
-                                       "p2m_evals", "m2l_columns", "rank", "m2l_pieces", "m2l_pair_tiles")] + [("root", c_double * 4),
+                                       "p2m_evals", "m2l_columns", "rank", "m2l_pieces", "m2l_pair_tiles", "basis")] + [("root", c_double * 4),
                                                                                  ("setup_ms", c_double)]
 
 

@@ -59,6 +59,7 @@ void fmm_default_options(fmm_options *opt) {
     opt->root[0] = opt->root[1] = opt->root[2] = opt->root[3] = 0.0;
     opt->pinv_eps = 0.0;
     opt->m2l_pieces = 0;
+    opt->basis = FMM_BASIS_SURFACE;
 }
 
 const char *fmm_last_error(void) { return g_last_error.c_str(); }
@@ -70,7 +71,11 @@ namespace {
 void check_options(const fmm_options *opt) {
     using namespace fmm;
     FMM_REQUIRE(opt != nullptr, "fmm_setup: options are NULL");
-    FMM_REQUIRE(opt->order >= 2 && opt->order <= 10, "fmm_setup: order must be in 2..10");
+    FMM_REQUIRE(opt->basis == FMM_BASIS_SURFACE || opt->basis == FMM_BASIS_CHEBYSHEV, "fmm_setup: unknown basis");
+    if (opt->basis == FMM_BASIS_CHEBYSHEV)
+        FMM_REQUIRE(opt->order >= 2 && opt->order <= 8, "fmm_setup: Chebyshev order must be in 2..8");
+    else
+        FMM_REQUIRE(opt->order >= 2 && opt->order <= 10, "fmm_setup: order must be in 2..10");
     FMM_REQUIRE(opt->leaf_size >= 1, "fmm_setup: leaf_size must be >= 1");
     FMM_REQUIRE(opt->max_depth >= 1 && opt->max_depth <= kMaxLevel, "fmm_setup: max_depth must be in 1..21");
     FMM_REQUIRE(opt->uniform_depth >= 0 && opt->uniform_depth <= kMaxLevel,
@@ -113,8 +118,9 @@ void init_plan(fmm::Plan &P, const fmm_options *opt) {
 // Everything after the tree: operators, per-box buffers, work lists.
 void finish_plan(fmm::Plan &P, const fmm_options *opt, const float *trg_nrm, hipStream_t s) {
     using namespace fmm;
-    double eps = opt->pinv_eps > 0 ? opt->pinv_eps : default_pinv_eps(opt->order);
-    P.ops = get_operators(opt->order, eps, s);
+    double eps = opt->pinv_eps > 0 ? opt->pinv_eps : default_pinv_eps(opt->basis, opt->order);
+    P.ops = get_operators(opt->basis, opt->order, eps, s);
+    P.cheb = opt->basis == FMM_BASIS_CHEBYSHEV;
     P.ns = P.ops->ns;
     P.n_pad = P.ops->n_pad;
     P.r = P.ops->r;
@@ -126,6 +132,12 @@ void finish_plan(fmm::Plan &P, const fmm_options *opt, const float *trg_nrm, hip
     if (P.m2l_bf16) P.ut_bf.alloc(m2l_split_vecs_elems(P.r_pad, (int64_t)nvec));
     P.phi_u.alloc(nvec * P.n_pad);
     P.phi_d.alloc(nvec * P.n_pad);
+    if (P.cheb) {
+        // expansion of the M2L result: 1 / half-width per vector
+        std::vector<double> sc(nvec);
+        for (size_t v = 0; v < nvec; ++v) sc[v] = 1.0 / P.t.h_half[v / P.nrhs];
+        P.col_iscale = upload(sc, s);
+    }
     // zero once: padding entries are never written, vectors of boxes
     // a stage skips stay zero
     for (DBuf<float> *b : {&P.ut, &P.chk, &P.phi_u, &P.phi_d})
@@ -376,6 +388,7 @@ int fmm_plan_info(fmm_plan plan, fmm_info *info) {
         r.rank = P.r;
         r.m2l_pieces = P.m2l_pieces_per_tile;
         r.m2l_pair_tiles = P.m2l_pair_tiles;
+        r.basis = P.cheb ? FMM_BASIS_CHEBYSHEV : FMM_BASIS_SURFACE;
         for (int c = 0; c < 3; ++c) r.root[c] = P.t.x0[c];
         r.root[3] = P.t.w;
         r.setup_ms = P.setup_ms;
@@ -422,6 +435,16 @@ int fmm_export_stage(fmm_plan plan, int which, float *host_out) {
         Plan &P = live(plan);
         FMM_REQUIRE(host_out != nullptr, "fmm_export_stage: out is NULL");
         FMM_REQUIRE(which == 0 || which == 1, "fmm_export_stage: which must be 0 or 1");
+        if (P.cheb) {
+            // node weights W (upward) or node values L (downward), stored as they are
+            const DBuf<float> &b = which == 0 ? P.phi_u : P.phi_d;
+            std::vector<float> all(b.n);
+            FMM_HIP(hipDeviceSynchronize());
+            d2h(all.data(), b.p, b.n, nullptr);
+            for (int64_t box = 0; box < P.t.nb; ++box)
+                for (int m = 0; m < P.ns; ++m) host_out[box * P.ns + m] = all[((size_t)box * P.nrhs) * P.n_pad + m];
+            return;
+        }
         // reconstruct U_r ut (upward) or V_r dt (downward), [ns][r] host factors
         const DBuf<float> &b = which == 0 ? P.ut : P.dt;
         const std::vector<double> &B = which == 0 ? P.ops->U : P.ops->V;

@@ -1,0 +1,282 @@
+// Interpolation kernels of the Chebyshev far field (Sec. III.A.1 Eq. p2m).
+//
+// Both kernels use the tensor-product structure of the interpolant,
+// S(xbar_m, t) = S_x(i, t_x) S_y(j, t_y) S_z(k, t_z) for node m = (i n + j) n + k,
+// with the 1D Lagrange polynomial of node i written as
+// S(i, t) = sum_k coef[i][k] T_k(t) (T_k by the three-term recurrence, its
+// derivative as k U_{k-1}). One wave handles one box.
+//
+// P2M: lane (j, k) owns the n nodes (0..n-1, j, k) and keeps their n sums in
+// registers; each source is reduced once to the 3n values S_c(i, t_c) (and
+// 3n derivatives for the double layer) when it is staged in LDS, so the
+// inner loop costs 2 LDS reads and about 2n + 8 FMAs per (source, lane).
+// The double layer uses
+//   sum_j m . grad S = dS_x (m_x S_y S_z) + S_x (m_y dS_y S_z + m_z S_y dS_z).
+//
+// L2P: lane = target. The contraction over the n^3 node values (staged in
+// LDS, read by broadcast) runs axis by axis: z inside, then y, then x.
+#include "chebyshev.hpp"
+
+namespace fmm {
+
+namespace {
+
+// T_k(t), k < N, and (if D) T_k'(t) = k U_{k-1}(t), into registers.
+template <int N, bool D>
+__device__ inline void cheb_basis(float t, float *tk, float *dtk) {
+    tk[0] = 1.f;
+    if (N > 1) tk[1] = t;
+#pragma unroll
+    for (int k = 2; k < N; ++k) tk[k] = 2.f * t * tk[k - 1] - tk[k - 2];
+    if (D) {
+        float u0 = 1.f, u1 = 2.f * t;  // U_0, U_1
+        dtk[0] = 0.f;
+        if (N > 1) dtk[1] = 1.f;
+#pragma unroll
+        for (int k = 2; k < N; ++k) {
+            dtk[k] = k * u1;
+            const float u2 = 2.f * t * u1 - u0;
+            u0 = u1;
+            u1 = u2;
+        }
+    }
+}
+
+// S(i, t) and (if D) dS/dt for every node i of one axis.
+template <int N, bool D>
+__device__ inline void cheb_lagrange_1d(const float *cf, float t, float *s, float *ds) {
+    float tk[N], dtk[N];
+    cheb_basis<N, D>(t, tk, dtk);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        float v = 0.f, dv = 0.f;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            v += cf[i * N + k] * tk[k];
+            if (D) dv += cf[i * N + k] * dtk[k];
+        }
+        s[i] = v;
+        if (D) ds[i] = dv;
+    }
+}
+
+template <int N, int NRHS, bool SL, bool DL>
+__global__ __launch_bounds__(64) void k_points_to_nodes(const float *coef, const int32_t *items, const int32_t *roff,
+                                                       const int32_t *rng, SurfaceGeom g, PointSrc src, float *out) {
+    // per staged source: S_c(i) for c = x, y, z; dS_c(i) (DL); then q, m / h
+    constexpr int OS = 0, OD = 3 * N, OQ = DL ? 6 * N : 3 * N, OM = OQ + (SL ? NRHS : 0);
+    constexpr int W = OM + (DL ? 3 * NRHS : 0);
+    __shared__ float sh[64 * W];
+    __shared__ float cf[N * N];
+    const int lane = threadIdx.x;
+    const int b = items[blockIdx.x];
+    if (lane < N * N) cf[lane] = coef[lane];
+    const double cx = g.centre[3 * b], cy = g.centre[3 * b + 1], cz = g.centre[3 * b + 2];
+    const double ih = 1.0 / g.half[b];
+    const bool act = lane < N * N;
+    const int jy = act ? lane / N : 0, kz = act ? lane % N : 0;
+    float acc[N][NRHS];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        for (int r = 0; r < NRHS; ++r) acc[i][r] = 0.f;
+    __syncthreads();
+    for (int e = roff[blockIdx.x]; e < roff[blockIdx.x + 1]; ++e) {
+        const int s0 = rng[2 * e], s1 = rng[2 * e + 1];
+        for (int j0 = s0; j0 < s1; j0 += 64) {
+            const int j = j0 + lane;
+            const int cnt = min(64, s1 - j0);
+            if (j < s1) {
+                float *p = sh + lane * W;
+                const float t[3] = {(float)(((double)src.x[j] - cx) * ih), (float)(((double)src.y[j] - cy) * ih),
+                                    (float)(((double)src.z[j] - cz) * ih)};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) cheb_lagrange_1d<N, DL>(cf, t[c], p + OS + c * N, p + OD + c * N);
+                if (SL)
+                    for (int r = 0; r < NRHS; ++r) p[OQ + r] = src.q[r * src.n + j];
+                if (DL)
+                    for (int r = 0; r < NRHS; ++r) {
+                        p[OM + 3 * r] = (float)(src.mx[r * src.n + j] * ih);
+                        p[OM + 3 * r + 1] = (float)(src.my[r * src.n + j] * ih);
+                        p[OM + 3 * r + 2] = (float)(src.mz[r * src.n + j] * ih);
+                    }
+            }
+            __syncthreads();
+            for (int jj = 0; jj < cnt; ++jj) {
+                const float *p = sh + jj * W;
+                const float sy = p[OS + N + jy], sz = p[OS + 2 * N + kz];
+                float A[NRHS], B[NRHS];
+#pragma unroll
+                for (int r = 0; r < NRHS; ++r) {
+                    A[r] = SL ? p[OQ + r] * (sy * sz) : 0.f;
+                    B[r] = 0.f;
+                }
+                if (DL) {
+                    const float dsy = p[OD + N + jy], dsz = p[OD + 2 * N + kz];
+#pragma unroll
+                    for (int r = 0; r < NRHS; ++r) {
+                        A[r] += p[OM + 3 * r + 1] * (dsy * sz) + p[OM + 3 * r + 2] * (sy * dsz);
+                        B[r] = p[OM + 3 * r] * (sy * sz);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const float sx = p[OS + i];
+                    const float dsx = DL ? p[OD + i] : 0.f;
+#pragma unroll
+                    for (int r = 0; r < NRHS; ++r) {
+                        acc[i][r] += sx * A[r];
+                        if (DL) acc[i][r] += dsx * B[r];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (!act) return;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        for (int r = 0; r < NRHS; ++r)
+            out[((int64_t)b * NRHS + r) * g.n_pad + (i * N + jy) * N + kz] = acc[i][r];
+}
+
+template <int N, int NRHS, bool FIELD>
+__global__ __launch_bounds__(64) void k_nodes_to_points(const float *coef, EvalArgs a, SurfaceGeom g, const float *L) {
+    constexpr int NN = N * N * N;
+    __shared__ float sl[NRHS * NN];
+    __shared__ float cf[N * N];
+    const int lane = threadIdx.x;
+    const int leaf = a.wleaf[blockIdx.x];
+    const int64_t t_first = a.tbeg[leaf] + a.wt0[blockIdx.x];
+    const int nt = (int)min((int64_t)64, a.tend[leaf] - t_first);
+    if (lane < N * N) cf[lane] = coef[lane];
+    for (int m = lane; m < NN; m += 64)
+        for (int r = 0; r < NRHS; ++r) sl[r * NN + m] = L[((int64_t)leaf * NRHS + r) * g.n_pad + m];
+    __syncthreads();
+    if (lane >= nt) return;
+    const int64_t k = t_first + lane;
+    const double ih = 1.0 / g.half[leaf];
+    const float tx = (float)(((double)a.tx[k] - g.centre[3 * leaf]) * ih);
+    const float ty = (float)(((double)a.ty[k] - g.centre[3 * leaf + 1]) * ih);
+    const float tz = (float)(((double)a.tz[k] - g.centre[3 * leaf + 2]) * ih);
+    float sy[N], sz[N], dsy[N], dsz[N], tk[N], dtk[N];
+    cheb_lagrange_1d<N, FIELD>(cf, ty, sy, dsy);
+    cheb_lagrange_1d<N, FIELD>(cf, tz, sz, dsz);
+    cheb_basis<N, FIELD>(tx, tk, dtk);
+    const int64_t dst = a.trg_perm ? a.trg_perm[k] : k;
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) {
+        const float *lr = sl + r * NN;
+        float pot = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        // the x axis stays a loop (n^2 node values live at a time); S_x(i) is
+        // formed from row i of the coefficients
+#pragma unroll 1
+        for (int i = 0; i < N; ++i) {
+            float sxi = 0.f, dsxi = 0.f;
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                sxi += cf[i * N + q] * tk[q];
+                if (FIELD) dsxi += cf[i * N + q] * dtk[q];
+            }
+            float bi = 0.f, biy = 0.f, biz = 0.f;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                float az = 0.f, azd = 0.f;
+#pragma unroll
+                for (int kk = 0; kk < N; ++kk) {
+                    const float l = lr[(i * N + j) * N + kk];
+                    az += sz[kk] * l;
+                    if (FIELD) azd += dsz[kk] * l;
+                }
+                bi += sy[j] * az;
+                if (FIELD) {
+                    biy += dsy[j] * az;
+                    biz += sy[j] * azd;
+                }
+            }
+            pot += sxi * bi;
+            if (FIELD) {
+                gx += dsxi * bi;
+                gy += sxi * biy;
+                gz += sxi * biz;
+            }
+        }
+        if (a.pot) a.pot[r * a.n_trg + dst] += pot;
+        if (FIELD && a.field) {
+            // field = -grad_x f = -(1/h) grad_t f
+            float *f = a.field + ((int64_t)r * a.n_trg + dst) * 3;
+            const float s = (float)-ih;
+            f[0] += s * gx;
+            f[1] += s * gy;
+            f[2] += s * gz;
+        }
+    }
+}
+
+#define FMM_CHEB_SWITCH(N_VAR, NRHS_VAR, CALL)                                      \
+    switch ((N_VAR) * 8 + (NRHS_VAR)) {                                             \
+    case 2 * 8 + 1: { constexpr int N = 2, R = 1; CALL; } break;                    \
+    case 2 * 8 + 2: { constexpr int N = 2, R = 2; CALL; } break;                    \
+    case 2 * 8 + 3: { constexpr int N = 2, R = 3; CALL; } break;                    \
+    case 2 * 8 + 4: { constexpr int N = 2, R = 4; CALL; } break;                    \
+    case 3 * 8 + 1: { constexpr int N = 3, R = 1; CALL; } break;                    \
+    case 3 * 8 + 2: { constexpr int N = 3, R = 2; CALL; } break;                    \
+    case 3 * 8 + 3: { constexpr int N = 3, R = 3; CALL; } break;                    \
+    case 3 * 8 + 4: { constexpr int N = 3, R = 4; CALL; } break;                    \
+    case 4 * 8 + 1: { constexpr int N = 4, R = 1; CALL; } break;                    \
+    case 4 * 8 + 2: { constexpr int N = 4, R = 2; CALL; } break;                    \
+    case 4 * 8 + 3: { constexpr int N = 4, R = 3; CALL; } break;                    \
+    case 4 * 8 + 4: { constexpr int N = 4, R = 4; CALL; } break;                    \
+    case 5 * 8 + 1: { constexpr int N = 5, R = 1; CALL; } break;                    \
+    case 5 * 8 + 2: { constexpr int N = 5, R = 2; CALL; } break;                    \
+    case 5 * 8 + 3: { constexpr int N = 5, R = 3; CALL; } break;                    \
+    case 5 * 8 + 4: { constexpr int N = 5, R = 4; CALL; } break;                    \
+    case 6 * 8 + 1: { constexpr int N = 6, R = 1; CALL; } break;                    \
+    case 6 * 8 + 2: { constexpr int N = 6, R = 2; CALL; } break;                    \
+    case 6 * 8 + 3: { constexpr int N = 6, R = 3; CALL; } break;                    \
+    case 6 * 8 + 4: { constexpr int N = 6, R = 4; CALL; } break;                    \
+    case 7 * 8 + 1: { constexpr int N = 7, R = 1; CALL; } break;                    \
+    case 7 * 8 + 2: { constexpr int N = 7, R = 2; CALL; } break;                    \
+    case 7 * 8 + 3: { constexpr int N = 7, R = 3; CALL; } break;                    \
+    case 7 * 8 + 4: { constexpr int N = 7, R = 4; CALL; } break;                    \
+    case 8 * 8 + 1: { constexpr int N = 8, R = 1; CALL; } break;                    \
+    case 8 * 8 + 2: { constexpr int N = 8, R = 2; CALL; } break;                    \
+    case 8 * 8 + 3: { constexpr int N = 8, R = 3; CALL; } break;                    \
+    case 8 * 8 + 4: { constexpr int N = 8, R = 4; CALL; } break;                    \
+    default: throw Error(FMM_ERR_ARG, "Chebyshev order must be 2..8 and nrhs 1..4"); \
+    }
+
+}  // namespace
+
+void points_to_nodes(int nrhs, bool sl, bool dl, int n, const float *coef, const int32_t *items, int nitems,
+                     const int32_t *roff, const int32_t *rng, const SurfaceGeom &g, const PointSrc &src, float *out,
+                     hipStream_t s) {
+    if (nitems <= 0) return;
+    FMM_REQUIRE(g.ns == n * n * n && g.n_pad >= g.ns, "points_to_nodes: node count does not match the order");
+    dim3 gr(nitems), bl(64);
+    if (sl && dl) {
+        FMM_CHEB_SWITCH(n, nrhs, hipLaunchKernelGGL((k_points_to_nodes<N, R, true, true>), gr, bl, 0, s, coef, items,
+                                                    roff, rng, g, src, out));
+    } else if (dl) {
+        FMM_CHEB_SWITCH(n, nrhs, hipLaunchKernelGGL((k_points_to_nodes<N, R, false, true>), gr, bl, 0, s, coef, items,
+                                                    roff, rng, g, src, out));
+    } else {
+        FMM_CHEB_SWITCH(n, nrhs, hipLaunchKernelGGL((k_points_to_nodes<N, R, true, false>), gr, bl, 0, s, coef, items,
+                                                    roff, rng, g, src, out));
+    }
+    FMM_HIP(hipGetLastError());
+}
+
+void nodes_to_points(int nrhs, int n, const float *coef, const EvalArgs &a, const SurfaceGeom &g, const float *L,
+                     hipStream_t s) {
+    if (a.nwork <= 0) return;
+    FMM_REQUIRE(g.ns == n * n * n && g.n_pad >= g.ns, "nodes_to_points: node count does not match the order");
+    dim3 gr(a.nwork), bl(64);
+    if (a.field) {
+        FMM_CHEB_SWITCH(n, nrhs, hipLaunchKernelGGL((k_nodes_to_points<N, R, true>), gr, bl, 0, s, coef, a, g, L));
+    } else {
+        FMM_CHEB_SWITCH(n, nrhs, hipLaunchKernelGGL((k_nodes_to_points<N, R, false>), gr, bl, 0, s, coef, a, g, L));
+    }
+    FMM_HIP(hipGetLastError());
+}
+
+}  // namespace fmm

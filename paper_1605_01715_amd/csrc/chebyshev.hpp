@@ -1,0 +1,33 @@
+// Interpolation kernels of the Chebyshev far field (Sec. III.A.1 Eq. p2m):
+// sources onto the nodes of their leaf (P2M) and node values back to the
+// targets of a leaf (L2P). Everything between the two is shared with the
+// surface form (GEMMs on node vectors, M2L in a compressed basis, P2L and M2P
+// as kernel sums at the nodes).
+#pragma once
+
+#include "nbody.hpp"
+
+namespace fmm {
+
+constexpr int kChebMaxOrder = 8;
+
+// P2M: for work item i (box b = items[i], centre c, half-width h) write
+//   out[(b * nrhs + r) * n_pad + m] = sum_j q_j S(xbar_m, t_j) + (m_j / h) . grad_t S(xbar_m, t_j)
+// over the sources j in ranges rng[roff[i] .. roff[i+1]) (pairs s0, s1), with
+// t_j = (y_j - c) / h, S the tensor product of the order-n Lagrange
+// polynomials (coefficients coef [n][n] in the Chebyshev basis) and nodes
+// m = (i n + j) n + k. The double layer enters through the gradient of S
+// (the paper's second method). g supplies centres, half-widths and n_pad.
+void points_to_nodes(int nrhs, bool sl, bool dl, int n, const float *coef, const int32_t *items, int nitems,
+                     const int32_t *roff, const int32_t *rng, const SurfaceGeom &g, const PointSrc &src, float *out,
+                     hipStream_t s);
+
+// L2P: for every work item of the leaf evaluation (a.wleaf / a.wt0: up to 64
+// targets of one leaf) add sum_m S(xbar_m, t) L_m to a.pot and
+// -(1/h) grad_t of it to a.field (user order through a.trg_perm; either may be
+// NULL), where L = node values [(leaf * nrhs + r) * g.n_pad + m]. Runs after
+// eval_leaves, which overwrites the outputs.
+void nodes_to_points(int nrhs, int n, const float *coef, const EvalArgs &a, const SurfaceGeom &g, const float *L,
+                     hipStream_t s);
+
+}  // namespace fmm

@@ -18,6 +18,7 @@ constexpr int kNumDirs = 316;   // M2L offsets d in {-3..3}^3 with max|d| >= 2
 constexpr int kMaxOrder = 12;
 constexpr double kRadIn = 1.05;   // upward-equivalent / downward-check surface radius (box half-widths)
 constexpr double kRadOut = 2.95;  // upward-check / downward-equivalent surface radius
+constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kFourPi = 12.566370614359172953850573533118;
 
 struct Error : std::runtime_error {

@@ -208,7 +208,7 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
     for (int e = a.soff[leaf]; e < a.soff[leaf + 1]; ++e) {
         const int box = a.sbox[e];
         const bool down = a.skind[e] == 0;
-        const double rr = (down ? kRadOut : kRadIn) * g.half[box];
+        const double rr = (down ? a.rad_down : a.rad_up) * g.half[box];
         const double ox = g.centre[3 * box] - cx, oy = g.centre[3 * box + 1] - cy, oz = g.centre[3 * box + 2] - cz;
         const float *phi = (down ? a.phi_d : a.phi_u) + (int64_t)box * NRHS * g.n_pad;
         for (int m0 = 0; m0 < g.ns; m0 += 64) {

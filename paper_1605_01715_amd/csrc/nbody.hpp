@@ -31,8 +31,10 @@ void points_to_surface(int nrhs, bool sl, bool dl, const int32_t *items, int nit
 // Leaf evaluation (L2P + M2P + P2P). Work item i is leaf wleaf[i] with targets
 // [tbeg + wt0[i], min(tbeg + wt0[i] + 64, tend)). Surface sources of a leaf are
 // the entries sbox/skind[soff[leaf] .. soff[leaf+1]) (kind 0: the downward
-// equivalent density phi_d of that box at radius 2.95, kind 1: the upward
-// equivalent density phi_u at radius 1.05); point sources are the ranges
+// equivalent density phi_d of that box at radius rad_down, kind 1: the upward
+// density phi_u at radius rad_up, both times the box half-width and around
+// its centre; for the surface form 2.95 and 1.05, for the Chebyshev form
+// the node weights at the nodes, radius 1); point sources are the ranges
 // prng[poff[leaf] .. poff[leaf+1]). Results go to pot[r * n_trg + perm[k]] and
 // field[(r * n_trg + perm[k]) * 3 + c] (user order), overwriting.
 struct EvalArgs {
@@ -47,6 +49,7 @@ struct EvalArgs {
     const int64_t *trg_perm = nullptr;  // NULL: identity
     int64_t n_trg = 0;
     const float *phi_d = nullptr, *phi_u = nullptr;
+    double rad_down = 0.0, rad_up = 0.0;
     float delta2 = 0.f;
     float *pot = nullptr, *field = nullptr;
 };

@@ -42,8 +42,11 @@ std::vector<double> unit_surface(int p) {
 // Threshold tuned for float32 application: 1e-8 keeps the pre-multiplied
 // translations well enough conditioned that float32 products lose little,
 // while the float64 approximation error stays far below the float32 floor.
-double default_pinv_eps(int p) {
-    (void)p;
+double default_pinv_eps(int basis, int p) {
+    // Chebyshev basis: interpolation error falls about 7x per order (~3e-5 at
+    // n = 5, ~1e-6 at n = 7 on clustered clouds); keep the M2L truncation an
+    // order below it
+    if (basis == kBasisChebyshev) return std::max(1e-7, std::pow(10.0, -(p + 1)));
     return 1e-8;
 }
 
@@ -141,6 +144,47 @@ std::vector<double> pinv_jacobi(const std::vector<double> &K, int n, double eps)
 
 namespace {
 
+// Translations C_b = left (r x n) * G_b * right (n x r), one per 9-double entry
+// of prm (G_b as in build_laplace_mats, over the n points of dY), written as
+// float64 fragments r_pad x r_pad (f64) and/or row-major float32 padded to
+// r_pad x r_pad (rm). G is built on the device in chunks of 32.
+void build_translations(const double *dY, int n, int r, int rp, const std::vector<double> &prm, const double *left,
+                        const double *right, DBuf<double> *f64, DBuf<float> *rm, hipStream_t s) {
+    const int nb = (int)prm.size() / 9;
+    const size_t rr = (size_t)rp * rp;
+    if (f64) f64->alloc((size_t)nb * rr);
+    if (rm) rm->alloc((size_t)nb * rr);
+    const int chunk = 32;
+    DBuf<double> G((size_t)chunk * n * n), X((size_t)chunk * n * r), C((size_t)chunk * r * r);
+    for (int b0 = 0; b0 < nb; b0 += chunk) {
+        int cnt = std::min(chunk, nb - b0);
+        std::vector<double> sub(prm.begin() + 9 * b0, prm.begin() + 9 * (b0 + cnt));
+        DBuf<double> dprm = upload(sub, s);
+        build_laplace_mats(dY, n, cnt, dprm.p, G.p, s);
+        dgemm_batched(G.p, (size_t)n * n, right, 0, X.p, (size_t)n * r, n, r, n, cnt, s);
+        dgemm_batched(left, 0, X.p, (size_t)n * r, C.p, (size_t)r * r, r, r, n, cnt, s);
+        for (int b = 0; b < cnt; ++b) {
+            const double *Cb = C.p + (size_t)b * r * r;
+            if (f64) to_frag_f64(Cb, r, r, rp, rp, f64->p + (size_t)(b0 + b) * rr, s);
+            if (rm) to_padded_f32(Cb, r, r, rp, rp, rm->p + (size_t)(b0 + b) * rr, s);
+        }
+        FMM_HIP(hipStreamSynchronize(s));
+    }
+}
+
+// The 316 M2L directions d in {-3..3}^3 with max |d_c| >= 2, in (i, j, k)
+// lexicographic order, as 9-double entries for build_laplace_mats: targets
+// at ro * Y around the origin, sources at rs * Y around 2 d.
+std::vector<double> m2l_params(double ro, double rs) {
+    std::vector<double> prm;
+    for (int i = -3; i <= 3; ++i)
+        for (int j = -3; j <= 3; ++j)
+            for (int k = -3; k <= 3; ++k)
+                if (std::max(std::abs(i), std::max(std::abs(j), std::abs(k))) >= 2)
+                    prm.insert(prm.end(), {0.0, 0.0, 0.0, ro, 2.0 * i, 2.0 * j, 2.0 * k, rs, 1.0});
+    return prm;
+}
+
 std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
     auto op = std::make_shared<Operators>();
     op->p = p;
@@ -193,28 +237,9 @@ std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
     to_frag_f64(dVrSi.p, n, r, np, rp, op->cu_f64.p, s);
     to_frag_f64(dUrSi.p, n, r, np, rp, op->cd_f64.p, s);
 
-    // translations: G (n x n) built on the device, then left(r x n) * G * right(n x r)
     auto build = [&](const std::vector<double> &prm, const DBuf<double> &left, const DBuf<double> &right,
                      DBuf<double> *f64, DBuf<float> *rm) {
-        const int nb = (int)prm.size() / 9;
-        if (f64) f64->alloc((size_t)nb * rr);
-        if (rm) rm->alloc((size_t)nb * rr);
-        const int chunk = 32;
-        DBuf<double> G((size_t)chunk * n * n), X((size_t)chunk * n * r), C((size_t)chunk * r * r);
-        for (int b0 = 0; b0 < nb; b0 += chunk) {
-            int cnt = std::min(chunk, nb - b0);
-            std::vector<double> sub(prm.begin() + 9 * b0, prm.begin() + 9 * (b0 + cnt));
-            DBuf<double> dprm = upload(sub, s);
-            build_laplace_mats(op->dY.p, n, cnt, dprm.p, G.p, s);
-            dgemm_batched(G.p, (size_t)n * n, right.p, 0, X.p, (size_t)n * r, n, r, n, cnt, s);
-            dgemm_batched(left.p, 0, X.p, (size_t)n * r, C.p, (size_t)r * r, r, r, n, cnt, s);
-            for (int b = 0; b < cnt; ++b) {
-                const double *Cb = C.p + (size_t)b * r * r;
-                if (f64) to_frag_f64(Cb, r, r, rp, rp, f64->p + (size_t)(b0 + b) * rr, s);
-                if (rm) to_padded_f32(Cb, r, r, rp, rp, rm->p + (size_t)(b0 + b) * rr, s);
-            }
-            FMM_HIP(hipStreamSynchronize(s));
-        }
+        build_translations(op->dY.p, n, r, rp, prm, left.p, right.p, f64, rm, s);
     };
     auto sgn = [](int o, int c) { return ((o >> (2 - c)) & 1) ? 1.0 : -1.0; };
     std::vector<double> pm2m, pl2l, pm2l;
@@ -226,11 +251,7 @@ std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
         pl2l.insert(pl2l.end(), {0.5 * sgn(o, 0), 0.5 * sgn(o, 1), 0.5 * sgn(o, 2), 0.5 * kRadIn, 0.0, 0.0, 0.0,
                                  kRadOut, 1.0});
     }
-    for (int i = -3; i <= 3; ++i)
-        for (int j = -3; j <= 3; ++j)
-            for (int k = -3; k <= 3; ++k)
-                if (std::max(std::abs(i), std::max(std::abs(j), std::abs(k))) >= 2)
-                    pm2l.insert(pm2l.end(), {0.0, 0.0, 0.0, kRadIn, 2.0 * i, 2.0 * j, 2.0 * k, kRadIn, 1.0});
+    pm2l = m2l_params(kRadIn, kRadIn);
     build(pm2m, dPU, dVrSi, &op->m2m_f64, nullptr);
     build(pl2l, dPV, dUrSi, &op->l2l_f64, nullptr);
     {
@@ -245,20 +266,156 @@ std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
     return op;
 }
 
+// Lagrange polynomial of node i of the order-n Chebyshev nodes x, written in
+// the Chebyshev basis: 1/n + (2/n) sum_{k=1}^{n-1} T_k(x_i) T_k(t).
+double cheb_lagrange(const std::vector<double> &x, int i, double t) {
+    const int n = (int)x.size();
+    double s = 1.0 / n, a0 = 1.0, a1 = x[i], b0 = 1.0, b1 = t;
+    for (int k = 1; k < n; ++k) {
+        s += 2.0 / n * a1 * b1;
+        const double a2 = 2.0 * x[i] * a1 - a0, b2 = 2.0 * t * b1 - b0;
+        a0 = a1;
+        a1 = a2;
+        b0 = b1;
+        b1 = b2;
+    }
+    return s;
+}
+
+// The paper's interpolation form (Sec. III.A.1 Eq. p2m) on Chebyshev nodes.
+std::shared_ptr<Operators> build_chebyshev(int n, double eps, hipStream_t s) {
+    auto op = std::make_shared<Operators>();
+    op->basis = kBasisChebyshev;
+    op->p = n;
+    op->eps = eps;
+    const std::vector<double> x = chebyshev_nodes(n);
+    const int nn = op->ns = n * n * n;
+    const int np = op->n_pad = ((nn + 31) / 32) * 32;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) op->Y.insert(op->Y.end(), {x[i], x[j], x[k]});
+    op->dY = upload(op->Y, s);
+    {
+        std::vector<float> coef((size_t)n * n);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k)
+                coef[(size_t)i * n + k] = (float)(k == 0 ? 1.0 / n : 2.0 / n * std::cos(k * (2 * i + 1) * kPi / (2 * n)));
+        op->cheb_coef = upload(coef, s);
+    }
+
+    // M2M: S_o[m][m'] = prod_c S(x_{m_c}, s_{o,c} / 2 + x_{m'_c} / 2), child o's node
+    // weights to the parent's (exact: the parent's polynomials have degree
+    // n - 1 per axis); L2L uses the transposes.
+    {
+        std::vector<double> s1[2];
+        for (int side = 0; side < 2; ++side) {
+            s1[side].resize((size_t)n * n);
+            for (int i = 0; i < n; ++i)
+                for (int i2 = 0; i2 < n; ++i2)
+                    s1[side][(size_t)i * n + i2] = cheb_lagrange(x, i, (side ? 0.5 : -0.5) + 0.5 * x[i2]);
+        }
+        const size_t mm = (size_t)np * np;
+        op->m2m_f64.alloc(8 * mm);
+        op->l2l_f64.alloc(8 * mm);
+        std::vector<double> M((size_t)nn * nn), MT((size_t)nn * nn);
+        for (int o = 0; o < 8; ++o) {
+            const double *ax = s1[(o >> 2) & 1].data(), *ay = s1[(o >> 1) & 1].data(), *az = s1[o & 1].data();
+            for (int m = 0; m < nn; ++m)
+                for (int m2 = 0; m2 < nn; ++m2) {
+                    const double v = ax[(m / (n * n)) * n + m2 / (n * n)] * ay[((m / n) % n) * n + (m2 / n) % n] *
+                                     az[(m % n) * n + m2 % n];
+                    M[(size_t)m * nn + m2] = v;
+                    MT[(size_t)m2 * nn + m] = v;
+                }
+            DBuf<double> dM = upload(M, s), dMT = upload(MT, s);
+            to_frag_f64(dM.p, nn, nn, np, np, op->m2m_f64.p + o * mm, s);
+            to_frag_f64(dMT.p, nn, nn, np, np, op->l2l_f64.p + o * mm, s);
+            FMM_HIP(hipStreamSynchronize(s));
+        }
+    }
+
+    // M2L: K_d = G(x, 2 d + x) between unit boxes. One basis Q for every
+    // direction: the leading eigenvectors of sum_d K_d K_d^T (the left
+    // singular vectors of [K_1 ... K_316]). The direction set is symmetric and
+    // K_-d = K_d^T, so the same Q spans the right singular vectors of the
+    // stacked [K_1; ...; K_316], and K_d ~ Q (Q^T K_d Q) Q^T.
+    const std::vector<double> prm = m2l_params(1.0, 1.0), prmT = [&] {
+        std::vector<double> t = prm;  // sources at the origin, targets at 2 d: G^T
+        for (size_t b = 0; b < t.size(); b += 9)
+            for (int c = 0; c < 3; ++c) std::swap(t[b + c], t[b + 4 + c]);
+        return t;
+    }();
+    std::vector<double> gram((size_t)nn * nn, 0.0);
+    {
+        const int chunk = 16, nb = (int)prm.size() / 9;
+        const size_t n2 = (size_t)nn * nn;
+        DBuf<double> G(chunk * n2), GT(chunk * n2), C(chunk * n2);
+        std::vector<double> h(chunk * n2);
+        for (int b0 = 0; b0 < nb; b0 += chunk) {
+            const int cnt = std::min(chunk, nb - b0);
+            std::vector<double> sub(prm.begin() + 9 * b0, prm.begin() + 9 * (b0 + cnt));
+            std::vector<double> subT(prmT.begin() + 9 * b0, prmT.begin() + 9 * (b0 + cnt));
+            DBuf<double> dp = upload(sub, s), dpT = upload(subT, s);
+            build_laplace_mats(op->dY.p, nn, cnt, dp.p, G.p, s);
+            build_laplace_mats(op->dY.p, nn, cnt, dpT.p, GT.p, s);
+            dgemm_batched(G.p, n2, GT.p, n2, C.p, n2, nn, nn, nn, cnt, s);
+            d2h(h.data(), C.p, cnt * n2, s);
+            for (int b = 0; b < cnt; ++b)
+                for (size_t e = 0; e < n2; ++e) gram[e] += h[b * n2 + e];
+        }
+    }
+    std::vector<double> Qf, lam, Vf;
+    svd_jacobi(gram, nn, Qf, lam, Vf);
+    // sigma_k = sqrt(lambda_k); float64 resolves lambda to ~1e-16 lambda_max
+    const double thr = std::max(eps * eps, 1e-15) * lam[0];
+    int r = 0;
+    while (r < nn && lam[r] > thr) ++r;
+    r = std::max(r, 1);
+    const int rp = ((r + 31) / 32) * 32;
+    op->r = r;
+    op->r_pad = rp;
+    std::vector<double> Q((size_t)nn * r), QT((size_t)r * nn);
+    for (int m = 0; m < nn; ++m)
+        for (int k = 0; k < r; ++k) Q[(size_t)m * r + k] = QT[(size_t)k * nn + m] = Qf[(size_t)m * nn + k];
+    op->U = Q;
+    op->V = Q;
+    DBuf<double> dQ = upload(Q, s), dQT = upload(QT, s);
+    op->pv_f64.alloc((size_t)rp * np);  // node weights -> M2L basis
+    op->cd_f64.alloc((size_t)np * rp);  // M2L basis -> node values
+    to_frag_f64(dQT.p, r, nn, rp, np, op->pv_f64.p, s);
+    to_frag_f64(dQ.p, nn, r, np, rp, op->cd_f64.p, s);
+    {
+        DBuf<float> rm;
+        build_translations(op->dY.p, nn, r, rp, prm, dQT.p, dQ.p, nullptr, &rm, s);
+        op->m2l_f32.alloc((size_t)rp * rp * kNumDirs);
+        m2l_image_mats(rm.p, rp, kNumDirs, op->m2l_f32.p, s);
+        op->m2l_bf.alloc(m2l_split_mats_elems(rp, kNumDirs));
+        m2l_split_mats(rm.p, rp, kNumDirs, op->m2l_bf.p, s);
+        FMM_HIP(hipStreamSynchronize(s));
+    }
+    return op;
+}
+
 }  // namespace
 
-std::shared_ptr<const Operators> get_operators(int p, double eps, hipStream_t s) {
+std::vector<double> chebyshev_nodes(int n) {
+    std::vector<double> x(n);
+    for (int i = 0; i < n; ++i) x[i] = std::cos((2 * i + 1) * kPi / (2 * n));
+    return x;
+}
+
+std::shared_ptr<const Operators> get_operators(int basis, int p, double eps, hipStream_t s) {
     // Held until the process ends (never destroyed, so no device memory is
     // freed after the HIP runtime has shut down).
     static std::mutex mu;
-    static auto *cache = new std::map<std::tuple<int, int, double>, std::shared_ptr<Operators>>();
+    static auto *cache = new std::map<std::tuple<int, int, int, double>, std::shared_ptr<Operators>>();
     int dev = 0;
     FMM_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(mu);
-    auto key = std::make_tuple(dev, p, eps);
+    auto key = std::make_tuple(dev, basis, p, eps);
     auto it = cache->find(key);
     if (it != cache->end()) return it->second;
-    auto op = build_operators(p, eps, s);
+    auto op = basis == kBasisChebyshev ? build_chebyshev(p, eps, s) : build_operators(p, eps, s);
     (*cache)[key] = op;
     return op;
 }

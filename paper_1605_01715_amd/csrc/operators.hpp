@@ -22,19 +22,36 @@ namespace fmm {
 // with the projections pu = U^T, pv = V^T (r x n_s) for check potentials
 // computed from points (P2M, P2L) and the expansions cu = V S^-1 and
 // cd = U S^-1 (n_s x r) giving equivalent densities (times the box half-width).
+//
+// Chebyshev basis (the paper's form, Sec. III.A.1 Eq. p2m), order n: Y holds
+// the n^3 tensor-product Chebyshev nodes on [-1,1]^3 (ns = n^3) and the state
+// of a box is its node weights W (upward) and node values L (downward), ns
+// per box. m2m[o] (ns x ns) = S_o maps child o's weights to the parent's,
+// l2l[o] = S_o^T, both exact. M2L: K_d = G(x, 2 d + x) between unit boxes,
+// Q (ns x r) the leading eigenvectors of sum_d K_d K_d^T, m2l[d] = Q^T K_d Q
+// (r x r), pv = Q^T compresses W, cd = Q expands (times 1 / half-width).
+// cheb_coef[i][k] (n x n, float32) are the Chebyshev coefficients of node
+// i's Lagrange polynomial: 1/n for k = 0, (2/n) T_k(x_i) after.
+enum Basis { kBasisSurface = 0, kBasisChebyshev = 1 };
+
 struct Operators {
-    int p = 0, ns = 0, n_pad = 0;  // surface points, padded to 32
+    int basis = kBasisSurface;
+    int p = 0, ns = 0, n_pad = 0;  // surface points (or Chebyshev nodes), padded to 32
     int r = 0, r_pad = 0;          // kept singular values, padded to 32
     double eps = 0;
     std::vector<double> Y;         // [ns][3]
     DBuf<double> dY;
     DBuf<float> m2l_f32;           // [316] r_pad x r_pad float32, M2L kernel chunk order (FP32 form)
     DBuf<uint16_t> m2l_bf;         // the same, split into bfloat16 parts (M2L kernel, split-BF16 form)
-    DBuf<double> m2m_f64, l2l_f64; // [8] r_pad x r_pad, float64 fragment layout
+    DBuf<double> m2m_f64, l2l_f64; // [8] r_pad x r_pad (Chebyshev: n_pad x n_pad), float64 fragments
     DBuf<double> pu_f64, pv_f64;   // r_pad x n_pad fragment layout
     DBuf<double> cu_f64, cd_f64;   // n_pad x r_pad fragment layout
     std::vector<double> U, V;      // host [ns][r] row-major (reconstruction for inspection)
+    DBuf<float> cheb_coef;         // Chebyshev basis: [n][n]
 };
+
+// Chebyshev nodes of the first kind, cos((2i + 1) pi / (2n)), i = 0..n-1.
+std::vector<double> chebyshev_nodes(int n);
 
 // Unit surface Y(p): boundary nodes of the p^3 grid on [-1,1]^3, lexicographic.
 std::vector<double> unit_surface(int p);
@@ -48,9 +65,9 @@ void svd_jacobi(const std::vector<double> &K, int n, std::vector<double> &U, std
 // below eps * sigma_max are dropped.
 std::vector<double> pinv_jacobi(const std::vector<double> &K, int n, double eps);
 
-// Cached per (device, p, eps); built on first use.
-std::shared_ptr<const Operators> get_operators(int p, double eps, hipStream_t s);
+// Cached per (device, basis, order, eps); built on first use.
+std::shared_ptr<const Operators> get_operators(int basis, int p, double eps, hipStream_t s);
 
-double default_pinv_eps(int p);
+double default_pinv_eps(int basis, int p);
 
 }  // namespace fmm

@@ -19,6 +19,8 @@
 
 #include "plan.hpp"
 
+#include "chebyshev.hpp"
+
 namespace fmm {
 
 namespace {
@@ -617,8 +619,10 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         };
         if (lvl(b) >= 2) {
             down_boxes.push_back((int32_t)b);
-            sbox.push_back((int32_t)b);
-            skind.push_back(0);
+            if (!P.cheb) {  // the Chebyshev L2P is an interpolation (nodes_to_points), not a kernel sum
+                sbox.push_back((int32_t)b);
+                skind.push_back(0);
+            }
             P.surf_evals += ntrg(b) * ns;
         }
         size_t from = prng.size();
@@ -702,6 +706,21 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         j.cols = upload(cols, s);
         j.src = upload(cols, s);
     }
+    if (P.cheb) {
+        std::vector<int32_t> with_src, with_trg;
+        for (int64_t b = 0; b < nb; ++b) {
+            if (lvl(b) < 2) continue;
+            if (nsrc(b) > 0) with_src.push_back((int32_t)b);
+            if (ntrg(b) > 0) with_trg.push_back((int32_t)b);
+        }
+        for (auto *jb : {&P.cheb_compress, &P.cheb_expand}) {
+            GemmJob &j = *jb;
+            std::vector<int32_t> cols = tile_columns(jb == &P.cheb_compress ? with_src : with_trg, nrhs, ncol64, j.ntile);
+            j.nterm = 1;
+            j.cols = upload(cols, s);
+            j.src = upload(cols, s);
+        }
+    }
     FMM_HIP(hipStreamSynchronize(s));
 }
 
@@ -758,18 +777,7 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     g.centre = t.centre.p;
     g.half = t.half.p;
 
-    mark(ST_P2M);
-    points_to_surface(nrhs, sl, dl, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, kRadOut, g, src, P.chk.p,
-                      false, s);
-    run_gemm(P.p2m_proj, op.pu_f64.p, rp, np, P.chk.p, P.ut.p, nullptr, false, s);
-    mark(ST_M2M);
-    for (auto &j : P.m2m_jobs) run_gemm(j, op.m2m_f64.p, rp, rp, P.ut.p, P.ut.p, nullptr, false, s);
-    mark(ST_P2L);
-    points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, kRadIn, g, src, P.chk.p,
-                      false, s);
-    run_gemm(P.p2l_proj, op.pv_f64.p, rp, np, P.chk.p, P.dt.p, nullptr, true, s);
-    mark(ST_M2L);
-    {
+    auto run_m2l = [&] {
         if (P.m2l_bf16) m2l_split_vecs(P.ut.p, rp, t.nb * nrhs, P.ut_bf.p, s);
         M2LLaunch m;
         m.r_pad = rp;
@@ -793,12 +801,48 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
                        P.dt.p, s);
         if (P.m2l_ngather > 0)
             m2l_gather(rp, P.m2l_ngather, P.m2l_gt.p, P.m2l_goff.p, P.m2l_gidx.p, P.m2l_partial.p, P.dt.p, s);
-    }
+    };
+
+    if (P.cheb) {
+        // Chebyshev form (Sec. III.A.1 Eq. p2m): node weights W (phi_u) up the
+        // tree, node values L (phi_d) down; M2L in the shared compressed basis
+        hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)P.phi_d.n, kBlock)), dim3(kBlock), 0, s, P.phi_d.p,
+                           (int64_t)P.phi_d.n);
+        FMM_HIP(hipGetLastError());
+        mark(ST_P2M);
+        points_to_nodes(nrhs, sl, dl, op.p, op.cheb_coef.p, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, g, src,
+                        P.phi_u.p, s);
+        mark(ST_M2M);
+        for (auto &j : P.m2m_jobs) run_gemm(j, op.m2m_f64.p, np, np, P.phi_u.p, P.phi_u.p, nullptr, false, s);
+        mark(ST_P2L);
+        points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, 1.0, g, src, P.phi_d.p,
+                          false, s);
+        mark(ST_M2L);
+        run_gemm(P.cheb_compress, op.pv_f64.p, rp, np, P.phi_u.p, P.ut.p, nullptr, false, s);
+        run_m2l();
+        run_gemm(P.cheb_expand, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_iscale.p, true, s);
+        mark(ST_L2L);
+        for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, np, np, P.phi_d.p, P.phi_d.p, nullptr, true, s);
+        mark(ST_C2E);
+    } else {
+    mark(ST_P2M);
+    points_to_surface(nrhs, sl, dl, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, kRadOut, g, src, P.chk.p,
+                      false, s);
+    run_gemm(P.p2m_proj, op.pu_f64.p, rp, np, P.chk.p, P.ut.p, nullptr, false, s);
+    mark(ST_M2M);
+    for (auto &j : P.m2m_jobs) run_gemm(j, op.m2m_f64.p, rp, rp, P.ut.p, P.ut.p, nullptr, false, s);
+    mark(ST_P2L);
+    points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, kRadIn, g, src, P.chk.p,
+                      false, s);
+    run_gemm(P.p2l_proj, op.pv_f64.p, rp, np, P.chk.p, P.dt.p, nullptr, true, s);
+    mark(ST_M2L);
+    run_m2l();
     mark(ST_L2L);
     for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, rp, rp, P.dt.p, P.dt.p, nullptr, true, s);
     mark(ST_C2E);
     run_gemm(P.c2e_down, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_scale.p, false, s);
     run_gemm(P.c2e_up, op.cu_f64.p, np, rp, P.ut.p, P.phi_u.p, P.col_scale.p, false, s);
+    }
     mark(ST_EVAL);
     EvalArgs e;
     e.wleaf = P.wleaf.p;
@@ -826,11 +870,14 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     e.n_trg = t.n_trg;
     e.phi_d = P.phi_d.p;
     e.phi_u = P.phi_u.p;
+    e.rad_down = kRadOut;
+    e.rad_up = P.cheb ? 1.0 : kRadIn;
     // r < cutoff is excluded; a positive floor also excludes r = 0 when cutoff = 0
     e.delta2 = std::max(P.opt.cutoff * P.opt.cutoff, std::numeric_limits<float>::min());
     e.pot = pot;
     e.field = field;
     eval_leaves(nrhs, sl, dl, e, g, src, s);
+    if (P.cheb) nodes_to_points(nrhs, op.p, op.cheb_coef.p, e, g, P.phi_d.p, s);
     mark(ST_COUNT);
     if (P.timing && !capturing) plan_collect_times(P);
 }

@@ -30,6 +30,7 @@ struct Plan {
     std::shared_ptr<const Operators> ops;
     int ns = 0, n_pad = 0, r = 0, r_pad = 0;
     bool m2l_bf16 = false;
+    bool cheb = false;  // Chebyshev basis: node weights W in phi_u, node values L in phi_d
 
     DBuf<float> ut, dt;                     // [nb * nrhs][r_pad] compressed upward / downward state
     DBuf<uint16_t> ut_bf;                   // ut split into bfloat16 parts (split-BF16 M2L)
@@ -37,6 +38,7 @@ struct Plan {
     DBuf<float> phi_u, phi_d;               // [nb * nrhs][n_pad] equivalent densities
     DBuf<float> q_sorted, mx, my, mz;       // [nrhs][n_src]
     DBuf<double> col_scale;                 // half-width per vector index
+    DBuf<double> col_iscale;                // 1 / half-width per vector index (Chebyshev M2L expansion)
     DBuf<float> trg_nrm_user;               // [n_trg][3] target normals, caller's order
 
     DBuf<int32_t> p2m_items, p2m_roff, p2m_rng;
@@ -47,6 +49,7 @@ struct Plan {
     std::vector<GemmJob> m2m_jobs;  // bottom-up
     std::vector<GemmJob> l2l_jobs;  // top-down
     GemmJob c2e_down, c2e_up;
+    GemmJob cheb_compress, cheb_expand;  // Chebyshev: W -> M2L basis (boxes with sources), back (with targets)
     // M2L: tiles with their active directions
     int m2l_ntile = 0, m2l_ncol = 0;
     int64_t m2l_steps = 0;  // (tile, direction) products the dedicated kernel runs

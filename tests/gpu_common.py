@@ -21,7 +21,7 @@ def dev(a, dtype=None):
 
 
 def fmm_run(xyz, q=None, mu=None, nrm=None, trg=None, trg_nrm=None, field=False, order=6, leaf=64, depth=0,
-            root=None, precision=0, nrhs=1, cutoff=1e-5, pinv_eps=0.0, keep_plan=False, m2l_pieces=0):
+            root=None, precision=0, nrhs=1, cutoff=1e-5, pinv_eps=0.0, keep_plan=False, m2l_pieces=0, basis=0):
     """One setup + apply; q/mu are [nrhs, n_src] (or [n_src]). Returns dict."""
     import torch
 
@@ -30,7 +30,7 @@ def fmm_run(xyz, q=None, mu=None, nrm=None, trg=None, trg_nrm=None, field=False,
     kern = (F.FMM_SRC_SINGLE if q is not None else 0) | (F.FMM_SRC_DOUBLE if mu is not None else 0)
     outs = F.FMM_OUT_FIELD if field else F.FMM_OUT_POT
     kw = dict(order=order, leaf_size=leaf, uniform_depth=depth, precision=precision, src_kernels=kern,
-              outputs=outs, nrhs=nrhs, cutoff=cutoff, pinv_eps=pinv_eps, m2l_pieces=m2l_pieces)
+              outputs=outs, nrhs=nrhs, cutoff=cutoff, pinv_eps=pinv_eps, m2l_pieces=m2l_pieces, basis=basis)
     if root is not None:
         kw["root"] = root
     opts = F.fmm_default_options(**kw)

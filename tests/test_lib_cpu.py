@@ -49,15 +49,47 @@ def test_default_options():
     assert (o.order, o.leaf_size, o.uniform_depth, o.max_depth, o.nrhs) == (6, 64, 0, 21, 1)
     assert o.cutoff == pytest.approx(1e-5)
     assert o.src_kernels == F.FMM_SRC_SINGLE and o.outputs == F.FMM_OUT_POT
+    assert o.basis == F.FMM_BASIS_SURFACE
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Offsets and sizes of the option and info structs as the C compiler
+    lays them out, against the ctypes mirrors."""
+    import shutil
+    import subprocess
+
+    F = _lib()
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    L = F._lib
+    fields = {"fmm_options": [n for n, _ in L.FmmOptions._fields_], "fmm_info": [n for n, _ in L.FmmInfo._fields_]}
+    body = "".join(f'printf("{st} {f} %zu\\n", offsetof({st}, {f}));' for st, fs in fields.items() for f in fs)
+    body += 'printf("fmm_options sizeof %zu\\n", sizeof(fmm_options));printf("fmm_info sizeof %zu\\n", sizeof(fmm_info));'
+    src = tmp_path / "probe.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "fmm.h"\nint main(void){' + body + "return 0;}\n")
+    exe = tmp_path / "probe"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call([cc, "-I", inc, str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    mirror = {"fmm_options": L.FmmOptions, "fmm_info": L.FmmInfo}
+    for line in filter(None, out):
+        st, f, v = line.split()
+        want = ctypes.sizeof(mirror[st]) if f == "sizeof" else getattr(mirror[st], f).offset
+        assert int(v) == want, (st, f)
 
 
 @pytest.mark.parametrize("field,value", [("order", 1), ("order", 11), ("leaf_size", 0), ("max_depth", 22),
                                          ("nrhs", 0), ("nrhs", 5), ("precision", 7), ("src_kernels", 0),
-                                         ("outputs", 4)])
+                                         ("outputs", 4), ("basis", 2), ("basis", -1), ("cheb_order", 9),
+                                         ("cheb_order", 1)])
 def test_setup_rejects_bad_options_before_device_work(field, value):
     F = _lib()
     lib = F._lib.load()
-    o = F.fmm_default_options(**{field: value})
+    if field == "cheb_order":
+        o = F.fmm_default_options(basis=F.FMM_BASIS_CHEBYSHEV, order=value)
+    else:
+        o = F.fmm_default_options(**{field: value})
     h = ctypes.c_void_p()
     rc = lib.fmm_setup(None, None, 0, None, None, 0, ctypes.byref(o), None, ctypes.byref(h))
     assert rc == F.FMM_ERR_ARG
