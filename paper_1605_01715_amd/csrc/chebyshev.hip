@@ -212,6 +212,83 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const float *coef, EvalA
     }
 }
 
+// out (+)= (A_x (x) A_y (x) A_z) in with A_c = S[side_c] (M2M) or its
+// transpose (L2L). Lane (q, s) = (lane / N, lane % N): the z pass gives
+// T1[p'][q][s] (to LDS), the y pass T2[p'] for the lane's (q, s) in
+// registers, the x pass accumulates out[p][q][s] for every p.
+template <int N, int NRHS, bool L2L>
+__global__ __launch_bounds__(64) void k_cheb_tensor(const float *s1, const int32_t *dst, const int32_t *src,
+                                                   const int8_t *oct, const float *in, float *out, int n_pad) {
+    constexpr int NN = N * N * N, NT = L2L ? 1 : 8;
+    __shared__ float sm[2 * N * N];
+    __shared__ float X[NN], T1[NN];
+    const int lane = threadIdx.x, item = blockIdx.x;
+    for (int e = lane; e < 2 * N * N; e += 64) sm[e] = s1[e];
+    const bool act = lane < N * N;
+    const int q = act ? lane / N : 0, sz = act ? lane % N : 0;
+    // A_c[p][p'] from table side: S[side][p][p'] (M2M) or S[side][p'][p] (L2L)
+    auto A = [&](int side, int p, int p2) { return L2L ? sm[(side * N + p2) * N + p] : sm[(side * N + p) * N + p2]; };
+    const int64_t d = dst[item];
+#pragma unroll 1
+    for (int r = 0; r < NRHS; ++r) {
+        float acc[N];
+#pragma unroll
+        for (int p = 0; p < N; ++p) acc[p] = 0.f;
+#pragma unroll 1
+        for (int t = 0; t < NT; ++t) {
+            const int64_t sb = src[(int64_t)item * NT + t];
+            if (sb < 0) continue;  // uniform across the wave
+            const int o = L2L ? oct[item] : t;
+            const int sx = (o >> 2) & 1, sy = (o >> 1) & 1, szd = o & 1;
+            __syncthreads();  // sm loaded; the previous term is done with X and T1
+            for (int m = lane; m < NN; m += 64) X[m] = in[(sb * NRHS + r) * n_pad + m];
+            __syncthreads();
+            if (act) {
+                // z pass: T1[p'][q][s] = sum_s' A_z[s][s'] X[p'][q][s']
+                float az[N];
+#pragma unroll
+                for (int s2 = 0; s2 < N; ++s2) az[s2] = A(szd, sz, s2);
+#pragma unroll
+                for (int p2 = 0; p2 < N; ++p2) {
+                    float v = 0.f;
+#pragma unroll
+                    for (int s2 = 0; s2 < N; ++s2) v += az[s2] * X[(p2 * N + q) * N + s2];
+                    T1[(p2 * N + q) * N + sz] = v;
+                }
+            }
+            __syncthreads();
+            if (act) {
+                // y pass: T2[p'] = sum_q' A_y[q][q'] T1[p'][q'][s]
+                float ay[N], t2[N];
+#pragma unroll
+                for (int q2 = 0; q2 < N; ++q2) ay[q2] = A(sy, q, q2);
+#pragma unroll
+                for (int p2 = 0; p2 < N; ++p2) {
+                    float v = 0.f;
+#pragma unroll
+                    for (int q2 = 0; q2 < N; ++q2) v += ay[q2] * T1[(p2 * N + q2) * N + sz];
+                    t2[p2] = v;
+                }
+                // x pass: acc[p] += sum_p' A_x[p][p'] T2[p']
+#pragma unroll
+                for (int p = 0; p < N; ++p) {
+                    float v = acc[p];
+#pragma unroll
+                    for (int p2 = 0; p2 < N; ++p2) v += A(sx, p, p2) * t2[p2];
+                    acc[p] = v;
+                }
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int p = 0; p < N; ++p) {
+                float *o = out + (d * NRHS + r) * n_pad + (p * N + q) * N + sz;
+                *o = L2L ? *o + acc[p] : acc[p];
+            }
+        }
+    }
+}
+
 #define FMM_CHEB_SWITCH(N_VAR, NRHS_VAR, CALL)                                      \
     switch ((N_VAR) * 8 + (NRHS_VAR)) {                                             \
     case 2 * 8 + 1: { constexpr int N = 2, R = 1; CALL; } break;                    \
@@ -262,6 +339,21 @@ void points_to_nodes(int nrhs, bool sl, bool dl, int n, const float *coef, const
     } else {
         FMM_CHEB_SWITCH(n, nrhs, hipLaunchKernelGGL((k_points_to_nodes<N, R, true, false>), gr, bl, 0, s, coef, items,
                                                     roff, rng, g, src, out));
+    }
+    FMM_HIP(hipGetLastError());
+}
+
+void cheb_tensor(int nrhs, int n, bool l2l, const float *s1, int nitems, const int32_t *dst, const int32_t *src,
+                 const int8_t *oct, const float *in, float *out, int n_pad, hipStream_t s) {
+    if (nitems <= 0) return;
+    FMM_REQUIRE(n_pad >= n * n * n, "cheb_tensor: rows shorter than n^3");
+    dim3 gr(nitems), bl(64);
+    if (l2l) {
+        FMM_CHEB_SWITCH(n, nrhs, hipLaunchKernelGGL((k_cheb_tensor<N, R, true>), gr, bl, 0, s, s1, dst, src, oct, in,
+                                                    out, n_pad));
+    } else {
+        FMM_CHEB_SWITCH(n, nrhs, hipLaunchKernelGGL((k_cheb_tensor<N, R, false>), gr, bl, 0, s, s1, dst, src, oct, in,
+                                                    out, n_pad));
     }
     FMM_HIP(hipGetLastError());
 }

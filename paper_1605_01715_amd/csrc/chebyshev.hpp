@@ -30,4 +30,15 @@ void points_to_nodes(int nrhs, bool sl, bool dl, int n, const float *coef, const
 void nodes_to_points(int nrhs, int n, const float *coef, const EvalArgs &a, const SurfaceGeom &g, const float *L,
                      hipStream_t s);
 
+// M2M / L2L by the tensor-product structure of the octant maps: with
+// S[side][i][i'] = S(xbar_i, side / 2 + xbar_i' / 2) (side 0: -, 1: +) the map
+// from child o's node weights to the parent's is S[o_x] (x) S[o_y] (x) S[o_z]
+// (o_x = bit 2 of o, o_y bit 1, o_z bit 0), applied axis by axis (3 n^4
+// FMAs instead of n^6). One wave per item:
+//   M2M (l2l = false): out[dst[i]] = sum_{o < 8, src[8 i + o] >= 0} M_o in[src[8 i + o]]
+//   L2L (l2l = true):  out[dst[i]] += M_{oct[i]}^T in[src[i]]
+// Vectors are rows [(box * nrhs + r) * n_pad + m], s1 is [2][n][n] float32.
+void cheb_tensor(int nrhs, int n, bool l2l, const float *s1, int nitems, const int32_t *dst, const int32_t *src,
+                 const int8_t *oct, const float *in, float *out, int n_pad, hipStream_t s);
+
 }  // namespace fmm

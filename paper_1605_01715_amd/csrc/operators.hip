@@ -303,35 +303,17 @@ std::shared_ptr<Operators> build_chebyshev(int n, double eps, hipStream_t s) {
         op->cheb_coef = upload(coef, s);
     }
 
-    // M2M: S_o[m][m'] = prod_c S(x_{m_c}, s_{o,c} / 2 + x_{m'_c} / 2), child o's node
-    // weights to the parent's (exact: the parent's polynomials have degree
-    // n - 1 per axis); L2L uses the transposes.
+    // M2M / L2L: the map from child o's node weights to the parent's is
+    // S[o_x] (x) S[o_y] (x) S[o_z] with S[side][i][i'] = S(x_i, -+1/2 + x_i' / 2)
+    // (exact: the parent's polynomials have degree n - 1 per axis); L2L uses
+    // the transposes.
     {
-        std::vector<double> s1[2];
-        for (int side = 0; side < 2; ++side) {
-            s1[side].resize((size_t)n * n);
+        std::vector<float> s1(2 * (size_t)n * n);
+        for (int side = 0; side < 2; ++side)
             for (int i = 0; i < n; ++i)
                 for (int i2 = 0; i2 < n; ++i2)
-                    s1[side][(size_t)i * n + i2] = cheb_lagrange(x, i, (side ? 0.5 : -0.5) + 0.5 * x[i2]);
-        }
-        const size_t mm = (size_t)np * np;
-        op->m2m_f64.alloc(8 * mm);
-        op->l2l_f64.alloc(8 * mm);
-        std::vector<double> M((size_t)nn * nn), MT((size_t)nn * nn);
-        for (int o = 0; o < 8; ++o) {
-            const double *ax = s1[(o >> 2) & 1].data(), *ay = s1[(o >> 1) & 1].data(), *az = s1[o & 1].data();
-            for (int m = 0; m < nn; ++m)
-                for (int m2 = 0; m2 < nn; ++m2) {
-                    const double v = ax[(m / (n * n)) * n + m2 / (n * n)] * ay[((m / n) % n) * n + (m2 / n) % n] *
-                                     az[(m % n) * n + m2 % n];
-                    M[(size_t)m * nn + m2] = v;
-                    MT[(size_t)m2 * nn + m] = v;
-                }
-            DBuf<double> dM = upload(M, s), dMT = upload(MT, s);
-            to_frag_f64(dM.p, nn, nn, np, np, op->m2m_f64.p + o * mm, s);
-            to_frag_f64(dMT.p, nn, nn, np, np, op->l2l_f64.p + o * mm, s);
-            FMM_HIP(hipStreamSynchronize(s));
-        }
+                    s1[((size_t)side * n + i) * n + i2] = (float)cheb_lagrange(x, i, (side ? 0.5 : -0.5) + 0.5 * x[i2]);
+        op->cheb_s1 = upload(s1, s);
     }
 
     // M2L: K_d = G(x, 2 d + x) between unit boxes. One basis Q for every

@@ -26,8 +26,9 @@ namespace fmm {
 // Chebyshev basis (the paper's form, Sec. III.A.1 Eq. p2m), order n: Y holds
 // the n^3 tensor-product Chebyshev nodes on [-1,1]^3 (ns = n^3) and the state
 // of a box is its node weights W (upward) and node values L (downward), ns
-// per box. m2m[o] (ns x ns) = S_o maps child o's weights to the parent's,
-// l2l[o] = S_o^T, both exact. M2L: K_d = G(x, 2 d + x) between unit boxes,
+// per box. Child o's weights map to the parent's by S[o_x] (x) S[o_y] (x)
+// S[o_z] with the 1D tables cheb_s1[side][i][i'] = S(x_i, -+1/2 + x_i' / 2),
+// L2L by the transposes, both exact. M2L: K_d = G(x, 2 d + x) between unit boxes,
 // Q (ns x r) the leading eigenvectors of sum_d K_d K_d^T, m2l[d] = Q^T K_d Q
 // (r x r), pv = Q^T compresses W, cd = Q expands (times 1 / half-width).
 // cheb_coef[i][k] (n x n, float32) are the Chebyshev coefficients of node
@@ -43,11 +44,12 @@ struct Operators {
     DBuf<double> dY;
     DBuf<float> m2l_f32;           // [316] r_pad x r_pad float32, M2L kernel chunk order (FP32 form)
     DBuf<uint16_t> m2l_bf;         // the same, split into bfloat16 parts (M2L kernel, split-BF16 form)
-    DBuf<double> m2m_f64, l2l_f64; // [8] r_pad x r_pad (Chebyshev: n_pad x n_pad), float64 fragments
+    DBuf<double> m2m_f64, l2l_f64; // [8] r_pad x r_pad, float64 fragment layout
     DBuf<double> pu_f64, pv_f64;   // r_pad x n_pad fragment layout
     DBuf<double> cu_f64, cd_f64;   // n_pad x r_pad fragment layout
     std::vector<double> U, V;      // host [ns][r] row-major (reconstruction for inspection)
     DBuf<float> cheb_coef;         // Chebyshev basis: [n][n]
+    DBuf<float> cheb_s1;           // Chebyshev basis: [2][n][n]
 };
 
 // Chebyshev nodes of the first kind, cos((2i + 1) pi / (2n)), i = 0..n-1.

@@ -707,6 +707,41 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         j.src = upload(cols, s);
     }
     if (P.cheb) {
+        for (int l = t.nlev - 2; l >= 2; --l) {
+            std::vector<int32_t> dst, src;
+            for (int64_t b = t.lvl_off[l]; b < t.lvl_off[l + 1]; ++b) {
+                if (leaf(b) || nsrc(b) == 0) continue;
+                dst.push_back((int32_t)b);
+                for (int o = 0; o < 8; ++o) {
+                    const int32_t ch = t.h_child[8 * (size_t)b + o];
+                    src.push_back(ch >= 0 && nsrc(ch) > 0 ? ch : -1);
+                }
+            }
+            if (dst.empty()) continue;
+            ChebJob j;
+            j.n = (int)dst.size();
+            j.dst = upload(dst, s);
+            j.src = upload(src, s);
+            P.cheb_m2m.push_back(std::move(j));
+        }
+        for (int l = 3; l < t.nlev; ++l) {
+            std::vector<int32_t> dst, src;
+            std::vector<int8_t> oct;
+            for (int64_t b = t.lvl_off[l]; b < t.lvl_off[l + 1]; ++b) {
+                if (ntrg(b) == 0) continue;
+                const int32_t *a = &t.h_anchor[3 * b];
+                dst.push_back((int32_t)b);
+                src.push_back(t.h_parent[b]);
+                oct.push_back((int8_t)(((a[0] & 1) << 2) | ((a[1] & 1) << 1) | (a[2] & 1)));
+            }
+            if (dst.empty()) continue;
+            ChebJob j;
+            j.n = (int)dst.size();
+            j.dst = upload(dst, s);
+            j.src = upload(src, s);
+            j.oct = upload(oct, s);
+            P.cheb_l2l.push_back(std::move(j));
+        }
         std::vector<int32_t> with_src, with_trg;
         for (int64_t b = 0; b < nb; ++b) {
             if (lvl(b) < 2) continue;
@@ -813,7 +848,8 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         points_to_nodes(nrhs, sl, dl, op.p, op.cheb_coef.p, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, g, src,
                         P.phi_u.p, s);
         mark(ST_M2M);
-        for (auto &j : P.m2m_jobs) run_gemm(j, op.m2m_f64.p, np, np, P.phi_u.p, P.phi_u.p, nullptr, false, s);
+        for (auto &j : P.cheb_m2m)
+            cheb_tensor(nrhs, op.p, false, op.cheb_s1.p, j.n, j.dst.p, j.src.p, nullptr, P.phi_u.p, P.phi_u.p, np, s);
         mark(ST_P2L);
         points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, 1.0, g, src, P.phi_d.p,
                           false, s);
@@ -822,7 +858,8 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         run_m2l();
         run_gemm(P.cheb_expand, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_iscale.p, true, s);
         mark(ST_L2L);
-        for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, np, np, P.phi_d.p, P.phi_d.p, nullptr, true, s);
+        for (auto &j : P.cheb_l2l)
+            cheb_tensor(nrhs, op.p, true, op.cheb_s1.p, j.n, j.dst.p, j.src.p, j.oct.p, P.phi_d.p, P.phi_d.p, np, s);
         mark(ST_C2E);
     } else {
     mark(ST_P2M);

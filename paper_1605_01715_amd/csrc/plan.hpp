@@ -12,6 +12,14 @@
 
 namespace fmm {
 
+// Chebyshev M2M / L2L at one level (cheb_tensor): dst boxes, their sources
+// (8 children per parent, or the parent of a child) and the child's octant.
+struct ChebJob {
+    DBuf<int32_t> dst, src;
+    DBuf<int8_t> oct;
+    int n = 0;
+};
+
 struct GemmJob {
     DBuf<int32_t> cols, src, mat;
     int ntile = 0, nterm = 0;
@@ -50,6 +58,7 @@ struct Plan {
     std::vector<GemmJob> l2l_jobs;  // top-down
     GemmJob c2e_down, c2e_up;
     GemmJob cheb_compress, cheb_expand;  // Chebyshev: W -> M2L basis (boxes with sources), back (with targets)
+    std::vector<ChebJob> cheb_m2m, cheb_l2l;  // bottom-up / top-down, one per level
     // M2L: tiles with their active directions
     int m2l_ntile = 0, m2l_ncol = 0;
     int64_t m2l_steps = 0;  // (tile, direction) products the dedicated kernel runs
