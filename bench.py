@@ -5,9 +5,11 @@ layer Laplace potential) on the clustered 4M-point workload.
 A step is one full fmm_apply (P2M, M2M, P2L, M2L, L2L, check-to-equivalent
 maps, leaf evaluation) with the tree, lists and operators already built and
 all inputs resident in HBM. The headline value is the split-BF16 M2L form;
-the plain float32 form is measured beside it on the same tree. Errors are
-relative L2 against the float64 direct sum at sampled targets, which is also
-what the CPU baseline times.
+the plain float32 form is measured beside it. Both the surface form and the
+paper's Chebyshev-interpolation form are tuning candidates; the fastest one
+that meets the accuracy target is timed. Errors are relative L2 against the
+float64 direct sum at sampled targets, which is also what the CPU baseline
+times.
 
 Prints one JSON line (rank 0, one GPU).
 """
@@ -27,6 +29,7 @@ METRIC = "FMM matvec Mpoints/s at 1e-6 rel err: split-BF16 MFMA M2L vs plain FP3
 # builds, one FMA per lane per cycle gives 256 CU x 64 lanes x 2 x 2.4 GHz.
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32_mfma": 157.3, "fp32_valu": 157.3, "fp32_valu_unpacked": 78.6, "fp64": 78.6}
 FLOPS_PER_PAIR = {"sl": 11, "dl": 13, "sl+dl": 16, "sl+field": 20}
+BASES = ("surface", "chebyshev")
 
 
 def log(msg):
@@ -64,9 +67,14 @@ def run_form(F, torch, x, nrm, q, mu, precision, order, leaf, steps, warmup, eps
     return {"ms": ms, "setup_s": setup_s, "info": info, "stages": stages, "pot": pot}
 
 
+def form_tag(cfg):
+    """p8_s192_eps1e-07 (surface basis, order 8) or cheb8_s192_eps1e-07 (Chebyshev, 8 nodes per axis)."""
+    basis, order, leaf, eps = cfg
+    return f"{'cheb' if basis == 1 else 'p'}{order}_s{leaf}_eps{eps:g}"
+
+
 def traffic_profile(n, cfg):
-    order, leaf, eps = cfg
-    return os.path.join(ROOT, "profiles", f"hbm_traffic_clustered{n // 1_000_000}m_p{order}_s{leaf}_eps{eps:g}.md")
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_clustered{n // 1_000_000}m_{form_tag(cfg)}.md")
 
 
 def measured_traffic(kernel, precision, n, cfg):
@@ -76,7 +84,8 @@ def measured_traffic(kernel, precision, n, cfg):
         txt = open(traffic_profile(n, cfg)).read()
         data = json.loads(txt[txt.index("```json") + 7:txt.rindex("```")])
         run = data.get("config", {})
-        if (n, precision, list(cfg)) != (run.get("n"), run.get("precision"), run.get("order_leaf_eps")):
+        if (n, precision, cfg[0], list(cfg[1:])) != (run.get("n"), run.get("precision"), run.get("basis", 0),
+                                                      run.get("order_leaf_eps")):
             return None
         ent = data[kernel]
         import hashlib
@@ -135,13 +144,16 @@ def main():
     ap.add_argument("--n", type=int, default=4_000_000)
     ap.add_argument("--order", type=int, default=8)
     ap.add_argument("--leaf", type=int, default=192)
-    ap.add_argument("--eps", type=float, default=1e-7, help="pseudo-inverse threshold (relative)")
+    ap.add_argument("--eps", type=float, default=1e-7,
+                    help="relative SVD threshold (surface: pseudo-inverse; Chebyshev: M2L basis)")
     ap.add_argument("--no-tune", action="store_true",
                     help="time --order/--leaf/--eps as given instead of tuning leaf size and threshold")
     ap.add_argument("--target", type=float, default=1e-6, help="relative L2 error the tuned form must meet")
     ap.add_argument("--sample", type=int, default=10000, help="targets checked against the float64 direct sum")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain float32 form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle (error and baseline)")
+    ap.add_argument("--basis", choices=("surface", "chebyshev"), default="surface",
+                    help="far-field form for --no-tune runs (tuning tries both)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -197,29 +209,33 @@ def main():
         got = r["pot"].cpu().numpy()[sample].astype(np.float64)
         return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
-    # Leaf size and pseudo-inverse threshold are tuned per form (the paper
-    # tunes the octree height, Sec. III.A.1): each candidate is set up and
-    # timed briefly, and the fastest one whose error against the float64
-    # direct sum meets the target is timed in full.
-    candidates = [(args.order, args.leaf, args.eps)]
+    # Far-field form, leaf size and SVD threshold are tuned per M2L
+    # arithmetic (the paper tunes the octree height, Sec. III.A.1): each
+    # candidate is set up and timed briefly, and the fastest one whose error
+    # against the float64 direct sum meets the target is timed in full. The
+    # candidates are the surface form at order 8 and the paper's Chebyshev
+    # form at 8 nodes per axis, the orders at which each meets 1e-6.
+    candidates = [(1 if args.basis == "chebyshev" else 0, args.order, args.leaf, args.eps)]
     if not args.no_tune and ref is not None:
-        candidates = [(8, 128, 1e-8), (8, 128, 1e-7), (8, 192, 1e-8), (8, 192, 1e-7), (8, 256, 1e-7)]
+        candidates = [(0, 8, 128, 1e-8), (0, 8, 128, 1e-7), (0, 8, 192, 1e-8), (0, 8, 192, 1e-7), (0, 8, 256, 1e-7),
+                      (1, 8, 192, 1e-7), (1, 8, 256, 1e-7)]
     results = {}
     forms = [("split_bf16", F.FMM_PREC_SPLIT_BF16)] + ([] if args.no_fp32 else [("fp32", F.FMM_PREC_FP32)])
     for name, prec in forms:
         tune = []
         if len(candidates) > 1:
-            for order, leaf, eps in candidates:
-                r = run_form(F, torch, x, nrm, q, mu, prec, order, leaf, 3, 1, eps)
-                tune.append({"order": order, "leaf": leaf, "eps": eps, "ms": round(r["ms"], 3), "err": error_of(r)})
+            for basis, order, leaf, eps in candidates:
+                r = run_form(F, torch, x, nrm, q, mu, prec, order, leaf, 3, 1, eps, basis)
+                tune.append({"basis": BASES[basis], "order": order, "leaf": leaf, "eps": eps, "ms": round(r["ms"], 3),
+                             "err": error_of(r)})
                 log(f"bench: tune {name}: {tune[-1]}")
             ok = [c for c in tune if c["err"] <= args.target] or [min(tune, key=lambda c: c["err"])]
             best = min(ok, key=lambda c: c["ms"])
-            cfg = (best["order"], best["leaf"], best["eps"])
+            cfg = (BASES.index(best["basis"]), best["order"], best["leaf"], best["eps"])
         else:
             cfg = candidates[0]
         log(f"bench: form {name} {cfg}: setup + {args.warmup} warmup + {args.steps} timed steps")
-        r = run_form(F, torch, x, nrm, q, mu, prec, cfg[0], cfg[1], args.steps, args.warmup, cfg[2])
+        r = run_form(F, torch, x, nrm, q, mu, prec, cfg[1], cfg[2], args.steps, args.warmup, cfg[3], cfg[0])
         if ref is not None:
             r["err"] = error_of(r)
         r["cfg"], r["tune"] = cfg, tune
@@ -230,7 +246,9 @@ def main():
 
     main_r = results["split_bf16"]
     info = main_r["info"]
-    order, leaf, eps = main_r["cfg"]
+    basis, order, leaf, eps = main_r["cfg"]
+    form_txt = (f"Chebyshev interpolation with {order} nodes per axis ({order ** 3} per box), M2L basis threshold "
+                f"{eps:g}" if basis == 1 else f"surface basis order {order}, pseudo-inverse threshold {eps:g}")
     value = info["n_points"] / (main_r["ms"] * 1e-3) / 1e6
     line = {
         "metric": METRIC,
@@ -246,10 +264,10 @@ def main():
         "dtype": "f32+bf16x6",
         "data": "synthetic",
         "config": {"workload": f"clustered cloud, {args.n} points (70% in 64 Gaussian blobs sigma 0.02, 30% "
-                               f"uniform in the unit cube), single + double layer potential, order {order}, "
-                               f"leaf size {leaf}, pseudo-inverse threshold {eps:g}, adaptive octree, split-BF16 M2L",
-                   "n_points": info["n_points"], "order": order, "leaf_size": leaf, "pinv_eps": eps,
-                   "rank": info["rank"], "boxes": info["n_boxes"], "levels": info["n_levels"],
+                               f"uniform in the unit cube), single + double layer potential, {form_txt}, "
+                               f"leaf size {leaf}, adaptive octree, split-BF16 M2L",
+                   "n_points": info["n_points"], "basis": BASES[basis], "order": order, "leaf_size": leaf,
+                   "svd_eps": eps, "rank": info["rank"], "boxes": info["n_boxes"], "levels": info["n_levels"],
                    "m2l_pieces_per_tile": info["m2l_pieces"]},
         "autotune": {"target_rel_l2": args.target, "split_bf16": main_r["tune"],
                      "fp32": results["fp32"]["tune"] if "fp32" in results else None},
@@ -263,7 +281,7 @@ def main():
     if "fp32" in results:
         f = results["fp32"]
         line["fp32_form"] = {"value": round(info["n_points"] / (f["ms"] * 1e-3) / 1e6, 3),
-                             "order_leaf_eps": list(f["cfg"]),
+                             "basis": BASES[f["cfg"][0]], "order_leaf_eps": list(f["cfg"][1:]),
                              "ms_per_step": round(f["ms"], 4), "rel_l2_error": f.get("err"),
                              "stages_ms": {k: round(v, 4) for k, v in f["stages"].items()},
                              "roofline": f["roofline"]}

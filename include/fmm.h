@@ -241,7 +241,8 @@ typedef struct {
                                             6 (p-1)^2 + 2 surface points, or n^3 Chebyshev nodes */
     int64_t p2p_pairs;                   /* near-field point pairs evaluated per apply */
     int64_t m2l_pairs;                   /* M2L box pairs (V-list entries with sources) per rhs */
-    int64_t surf_evals;                  /* target x surface-point evaluations (L2P + M2P) per rhs */
+    int64_t surf_evals;                  /* target x surface-point kernel evaluations (L2P + M2P; for
+                                            CHEBYSHEV M2P only, its L2P interpolates) per rhs */
     int64_t p2m_evals;                   /* surface-point x source evaluations (P2M + P2L) per rhs */
     int64_t m2l_columns;                 /* matrix-vector products the M2L kernel computes, padding
                                             included (m2l_pairs / m2l_columns is its fill) */

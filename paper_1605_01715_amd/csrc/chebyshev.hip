@@ -21,53 +21,56 @@ namespace fmm {
 
 namespace {
 
-// T_k(t), k < N, and (if D) T_k'(t) = k U_{k-1}(t), into registers.
+// T_k(t), k < N, and (if D) T_k'(t) = k U_{k-1}(t), into registers. The
+// interpolation weights are formed in float64: a float32 weight is off by
+// about 1e-7 absolute, and n^3 such errors against a smooth kernel do not
+// cancel (they would cap the far field near 1e-6).
 template <int N, bool D>
-__device__ inline void cheb_basis(float t, float *tk, float *dtk) {
-    tk[0] = 1.f;
+__device__ inline void cheb_basis(double t, double *tk, double *dtk) {
+    tk[0] = 1.0;
     if (N > 1) tk[1] = t;
 #pragma unroll
-    for (int k = 2; k < N; ++k) tk[k] = 2.f * t * tk[k - 1] - tk[k - 2];
+    for (int k = 2; k < N; ++k) tk[k] = 2.0 * t * tk[k - 1] - tk[k - 2];
     if (D) {
-        float u0 = 1.f, u1 = 2.f * t;  // U_0, U_1
-        dtk[0] = 0.f;
-        if (N > 1) dtk[1] = 1.f;
+        double u0 = 1.0, u1 = 2.0 * t;  // U_0, U_1
+        dtk[0] = 0.0;
+        if (N > 1) dtk[1] = 1.0;
 #pragma unroll
         for (int k = 2; k < N; ++k) {
             dtk[k] = k * u1;
-            const float u2 = 2.f * t * u1 - u0;
+            const double u2 = 2.0 * t * u1 - u0;
             u0 = u1;
             u1 = u2;
         }
     }
 }
 
-// S(i, t) and (if D) dS/dt for every node i of one axis.
-template <int N, bool D>
-__device__ inline void cheb_lagrange_1d(const float *cf, float t, float *s, float *ds) {
-    float tk[N], dtk[N];
+// S(i, t) and (if D) dS/dt for every node i of one axis; cf [N][N] float64.
+template <int N, bool D, typename T>
+__device__ inline void cheb_lagrange_1d(const double *cf, double t, T *s, T *ds) {
+    double tk[N], dtk[N];
     cheb_basis<N, D>(t, tk, dtk);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        float v = 0.f, dv = 0.f;
+        double v = 0.0, dv = 0.0;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             v += cf[i * N + k] * tk[k];
             if (D) dv += cf[i * N + k] * dtk[k];
         }
-        s[i] = v;
-        if (D) ds[i] = dv;
+        s[i] = (T)v;
+        if (D) ds[i] = (T)dv;
     }
 }
 
 template <int N, int NRHS, bool SL, bool DL>
-__global__ __launch_bounds__(64) void k_points_to_nodes(const float *coef, const int32_t *items, const int32_t *roff,
+__global__ __launch_bounds__(64) void k_points_to_nodes(const double *coef, const int32_t *items, const int32_t *roff,
                                                        const int32_t *rng, SurfaceGeom g, PointSrc src, float *out) {
     // per staged source: S_c(i) for c = x, y, z; dS_c(i) (DL); then q, m / h
     constexpr int OS = 0, OD = 3 * N, OQ = DL ? 6 * N : 3 * N, OM = OQ + (SL ? NRHS : 0);
     constexpr int W = OM + (DL ? 3 * NRHS : 0);
     __shared__ float sh[64 * W];
-    __shared__ float cf[N * N];
+    __shared__ double cf[N * N];
     const int lane = threadIdx.x;
     const int b = items[blockIdx.x];
     if (lane < N * N) cf[lane] = coef[lane];
@@ -75,10 +78,11 @@ __global__ __launch_bounds__(64) void k_points_to_nodes(const float *coef, const
     const double ih = 1.0 / g.half[b];
     const bool act = lane < N * N;
     const int jy = act ? lane / N : 0, kz = act ? lane % N : 0;
-    float acc[N][NRHS];
+    // float64 sums: the Lagrange weights take both signs and cancel
+    double acc[N][NRHS];
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        for (int r = 0; r < NRHS; ++r) acc[i][r] = 0.f;
+        for (int r = 0; r < NRHS; ++r) acc[i][r] = 0.0;
     __syncthreads();
     for (int e = roff[blockIdx.x]; e < roff[blockIdx.x + 1]; ++e) {
         const int s0 = rng[2 * e], s1 = rng[2 * e + 1];
@@ -87,8 +91,8 @@ __global__ __launch_bounds__(64) void k_points_to_nodes(const float *coef, const
             const int cnt = min(64, s1 - j0);
             if (j < s1) {
                 float *p = sh + lane * W;
-                const float t[3] = {(float)(((double)src.x[j] - cx) * ih), (float)(((double)src.y[j] - cy) * ih),
-                                    (float)(((double)src.z[j] - cz) * ih)};
+                const double t[3] = {((double)src.x[j] - cx) * ih, ((double)src.y[j] - cy) * ih,
+                                     ((double)src.z[j] - cz) * ih};
 #pragma unroll
                 for (int c = 0; c < 3; ++c) cheb_lagrange_1d<N, DL>(cf, t[c], p + OS + c * N, p + OD + c * N);
                 if (SL)
@@ -123,10 +127,7 @@ __global__ __launch_bounds__(64) void k_points_to_nodes(const float *coef, const
                     const float sx = p[OS + i];
                     const float dsx = DL ? p[OD + i] : 0.f;
 #pragma unroll
-                    for (int r = 0; r < NRHS; ++r) {
-                        acc[i][r] += sx * A[r];
-                        if (DL) acc[i][r] += dsx * B[r];
-                    }
+                    for (int r = 0; r < NRHS; ++r) acc[i][r] += (double)(DL ? sx * A[r] + dsx * B[r] : sx * A[r]);
                 }
             }
             __syncthreads();
@@ -136,14 +137,14 @@ __global__ __launch_bounds__(64) void k_points_to_nodes(const float *coef, const
 #pragma unroll
     for (int i = 0; i < N; ++i)
         for (int r = 0; r < NRHS; ++r)
-            out[((int64_t)b * NRHS + r) * g.n_pad + (i * N + jy) * N + kz] = acc[i][r];
+            out[((int64_t)b * NRHS + r) * g.n_pad + (i * N + jy) * N + kz] = (float)acc[i][r];
 }
 
 template <int N, int NRHS, bool FIELD>
-__global__ __launch_bounds__(64) void k_nodes_to_points(const float *coef, EvalArgs a, SurfaceGeom g, const float *L) {
+__global__ __launch_bounds__(64) void k_nodes_to_points(const double *coef, EvalArgs a, SurfaceGeom g, const float *L) {
     constexpr int NN = N * N * N;
     __shared__ float sl[NRHS * NN];
-    __shared__ float cf[N * N];
+    __shared__ double cf[N * N];
     const int lane = threadIdx.x;
     const int leaf = a.wleaf[blockIdx.x];
     const int64_t t_first = a.tbeg[leaf] + a.wt0[blockIdx.x];
@@ -155,10 +156,10 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const float *coef, EvalA
     if (lane >= nt) return;
     const int64_t k = t_first + lane;
     const double ih = 1.0 / g.half[leaf];
-    const float tx = (float)(((double)a.tx[k] - g.centre[3 * leaf]) * ih);
-    const float ty = (float)(((double)a.ty[k] - g.centre[3 * leaf + 1]) * ih);
-    const float tz = (float)(((double)a.tz[k] - g.centre[3 * leaf + 2]) * ih);
-    float sy[N], sz[N], dsy[N], dsz[N], tk[N], dtk[N];
+    const double tx = ((double)a.tx[k] - g.centre[3 * leaf]) * ih;
+    const double ty = ((double)a.ty[k] - g.centre[3 * leaf + 1]) * ih;
+    const double tz = ((double)a.tz[k] - g.centre[3 * leaf + 2]) * ih;
+    double sy[N], sz[N], dsy[N], dsz[N], tk[N], dtk[N];
     cheb_lagrange_1d<N, FIELD>(cf, ty, sy, dsy);
     cheb_lagrange_1d<N, FIELD>(cf, tz, sz, dsz);
     cheb_basis<N, FIELD>(tx, tk, dtk);
@@ -166,24 +167,24 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const float *coef, EvalA
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) {
         const float *lr = sl + r * NN;
-        float pot = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        double pot = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
         // the x axis stays a loop (n^2 node values live at a time); S_x(i) is
         // formed from row i of the coefficients
 #pragma unroll 1
         for (int i = 0; i < N; ++i) {
-            float sxi = 0.f, dsxi = 0.f;
+            double sxi = 0.0, dsxi = 0.0;
 #pragma unroll
             for (int q = 0; q < N; ++q) {
                 sxi += cf[i * N + q] * tk[q];
                 if (FIELD) dsxi += cf[i * N + q] * dtk[q];
             }
-            float bi = 0.f, biy = 0.f, biz = 0.f;
+            double bi = 0.0, biy = 0.0, biz = 0.0;
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                float az = 0.f, azd = 0.f;
+                double az = 0.0, azd = 0.0;
 #pragma unroll
                 for (int kk = 0; kk < N; ++kk) {
-                    const float l = lr[(i * N + j) * N + kk];
+                    const double l = lr[(i * N + j) * N + kk];
                     az += sz[kk] * l;
                     if (FIELD) azd += dsz[kk] * l;
                 }
@@ -200,14 +201,13 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const float *coef, EvalA
                 gz += sxi * biz;
             }
         }
-        if (a.pot) a.pot[r * a.n_trg + dst] += pot;
+        if (a.pot) a.pot[r * a.n_trg + dst] = (float)pot;
         if (FIELD && a.field) {
             // field = -grad_x f = -(1/h) grad_t f
             float *f = a.field + ((int64_t)r * a.n_trg + dst) * 3;
-            const float s = (float)-ih;
-            f[0] += s * gx;
-            f[1] += s * gy;
-            f[2] += s * gz;
+            f[0] = (float)(-ih * gx);
+            f[1] = (float)(-ih * gy);
+            f[2] = (float)(-ih * gz);
         }
     }
 }
@@ -217,11 +217,11 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const float *coef, EvalA
 // T1[p'][q][s] (to LDS), the y pass T2[p'] for the lane's (q, s) in
 // registers, the x pass accumulates out[p][q][s] for every p.
 template <int N, int NRHS, bool L2L>
-__global__ __launch_bounds__(64) void k_cheb_tensor(const float *s1, const int32_t *dst, const int32_t *src,
+__global__ __launch_bounds__(64) void k_cheb_tensor(const double *s1, const int32_t *dst, const int32_t *src,
                                                    const int8_t *oct, const float *in, float *out, int n_pad) {
     constexpr int NN = N * N * N, NT = L2L ? 1 : 8;
-    __shared__ float sm[2 * N * N];
-    __shared__ float X[NN], T1[NN];
+    __shared__ double sm[2 * N * N];
+    __shared__ double X[NN], T1[NN];
     const int lane = threadIdx.x, item = blockIdx.x;
     for (int e = lane; e < 2 * N * N; e += 64) sm[e] = s1[e];
     const bool act = lane < N * N;
@@ -231,9 +231,9 @@ __global__ __launch_bounds__(64) void k_cheb_tensor(const float *s1, const int32
     const int64_t d = dst[item];
 #pragma unroll 1
     for (int r = 0; r < NRHS; ++r) {
-        float acc[N];
+        double acc[N];
 #pragma unroll
-        for (int p = 0; p < N; ++p) acc[p] = 0.f;
+        for (int p = 0; p < N; ++p) acc[p] = 0.0;
 #pragma unroll 1
         for (int t = 0; t < NT; ++t) {
             const int64_t sb = src[(int64_t)item * NT + t];
@@ -245,12 +245,12 @@ __global__ __launch_bounds__(64) void k_cheb_tensor(const float *s1, const int32
             __syncthreads();
             if (act) {
                 // z pass: T1[p'][q][s] = sum_s' A_z[s][s'] X[p'][q][s']
-                float az[N];
+                double az[N];
 #pragma unroll
                 for (int s2 = 0; s2 < N; ++s2) az[s2] = A(szd, sz, s2);
 #pragma unroll
                 for (int p2 = 0; p2 < N; ++p2) {
-                    float v = 0.f;
+                    double v = 0.0;
 #pragma unroll
                     for (int s2 = 0; s2 < N; ++s2) v += az[s2] * X[(p2 * N + q) * N + s2];
                     T1[(p2 * N + q) * N + sz] = v;
@@ -259,12 +259,12 @@ __global__ __launch_bounds__(64) void k_cheb_tensor(const float *s1, const int32
             __syncthreads();
             if (act) {
                 // y pass: T2[p'] = sum_q' A_y[q][q'] T1[p'][q'][s]
-                float ay[N], t2[N];
+                double ay[N], t2[N];
 #pragma unroll
                 for (int q2 = 0; q2 < N; ++q2) ay[q2] = A(sy, q, q2);
 #pragma unroll
                 for (int p2 = 0; p2 < N; ++p2) {
-                    float v = 0.f;
+                    double v = 0.0;
 #pragma unroll
                     for (int q2 = 0; q2 < N; ++q2) v += ay[q2] * T1[(p2 * N + q2) * N + sz];
                     t2[p2] = v;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(64) void k_cheb_tensor(const float *s1, const int32
                 // x pass: acc[p] += sum_p' A_x[p][p'] T2[p']
 #pragma unroll
                 for (int p = 0; p < N; ++p) {
-                    float v = acc[p];
+                    double v = acc[p];
 #pragma unroll
                     for (int p2 = 0; p2 < N; ++p2) v += A(sx, p, p2) * t2[p2];
                     acc[p] = v;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(64) void k_cheb_tensor(const float *s1, const int32
 #pragma unroll
             for (int p = 0; p < N; ++p) {
                 float *o = out + (d * NRHS + r) * n_pad + (p * N + q) * N + sz;
-                *o = L2L ? *o + acc[p] : acc[p];
+                *o = L2L ? (float)((double)*o + acc[p]) : (float)acc[p];
             }
         }
     }
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(64) void k_cheb_tensor(const float *s1, const int32
 
 }  // namespace
 
-void points_to_nodes(int nrhs, bool sl, bool dl, int n, const float *coef, const int32_t *items, int nitems,
+void points_to_nodes(int nrhs, bool sl, bool dl, int n, const double *coef, const int32_t *items, int nitems,
                      const int32_t *roff, const int32_t *rng, const SurfaceGeom &g, const PointSrc &src, float *out,
                      hipStream_t s) {
     if (nitems <= 0) return;
@@ -343,7 +343,7 @@ void points_to_nodes(int nrhs, bool sl, bool dl, int n, const float *coef, const
     FMM_HIP(hipGetLastError());
 }
 
-void cheb_tensor(int nrhs, int n, bool l2l, const float *s1, int nitems, const int32_t *dst, const int32_t *src,
+void cheb_tensor(int nrhs, int n, bool l2l, const double *s1, int nitems, const int32_t *dst, const int32_t *src,
                  const int8_t *oct, const float *in, float *out, int n_pad, hipStream_t s) {
     if (nitems <= 0) return;
     FMM_REQUIRE(n_pad >= n * n * n, "cheb_tensor: rows shorter than n^3");
@@ -358,7 +358,7 @@ void cheb_tensor(int nrhs, int n, bool l2l, const float *s1, int nitems, const i
     FMM_HIP(hipGetLastError());
 }
 
-void nodes_to_points(int nrhs, int n, const float *coef, const EvalArgs &a, const SurfaceGeom &g, const float *L,
+void nodes_to_points(int nrhs, int n, const double *coef, const EvalArgs &a, const SurfaceGeom &g, const float *L,
                      hipStream_t s) {
     if (a.nwork <= 0) return;
     FMM_REQUIRE(g.ns == n * n * n && g.n_pad >= g.ns, "nodes_to_points: node count does not match the order");

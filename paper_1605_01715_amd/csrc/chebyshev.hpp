@@ -15,19 +15,19 @@ constexpr int kChebMaxOrder = 8;
 //   out[(b * nrhs + r) * n_pad + m] = sum_j q_j S(xbar_m, t_j) + (m_j / h) . grad_t S(xbar_m, t_j)
 // over the sources j in ranges rng[roff[i] .. roff[i+1]) (pairs s0, s1), with
 // t_j = (y_j - c) / h, S the tensor product of the order-n Lagrange
-// polynomials (coefficients coef [n][n] in the Chebyshev basis) and nodes
+// polynomials (float64 coefficients coef [n][n] in the Chebyshev basis) and nodes
 // m = (i n + j) n + k. The double layer enters through the gradient of S
 // (the paper's second method). g supplies centres, half-widths and n_pad.
-void points_to_nodes(int nrhs, bool sl, bool dl, int n, const float *coef, const int32_t *items, int nitems,
+void points_to_nodes(int nrhs, bool sl, bool dl, int n, const double *coef, const int32_t *items, int nitems,
                      const int32_t *roff, const int32_t *rng, const SurfaceGeom &g, const PointSrc &src, float *out,
                      hipStream_t s);
 
 // L2P: for every work item of the leaf evaluation (a.wleaf / a.wt0: up to 64
-// targets of one leaf) add sum_m S(xbar_m, t) L_m to a.pot and
+// targets of one leaf) write sum_m S(xbar_m, t) L_m to a.pot and
 // -(1/h) grad_t of it to a.field (user order through a.trg_perm; either may be
-// NULL), where L = node values [(leaf * nrhs + r) * g.n_pad + m]. Runs after
-// eval_leaves, which overwrites the outputs.
-void nodes_to_points(int nrhs, int n, const float *coef, const EvalArgs &a, const SurfaceGeom &g, const float *L,
+// NULL), where L = node values [(leaf * nrhs + r) * g.n_pad + m]. Overwrites:
+// it runs before eval_leaves, which then adds (a.accumulate = 1).
+void nodes_to_points(int nrhs, int n, const double *coef, const EvalArgs &a, const SurfaceGeom &g, const float *L,
                      hipStream_t s);
 
 // M2M / L2L by the tensor-product structure of the octant maps: with
@@ -37,8 +37,9 @@ void nodes_to_points(int nrhs, int n, const float *coef, const EvalArgs &a, cons
 // FMAs instead of n^6). One wave per item:
 //   M2M (l2l = false): out[dst[i]] = sum_{o < 8, src[8 i + o] >= 0} M_o in[src[8 i + o]]
 //   L2L (l2l = true):  out[dst[i]] += M_{oct[i]}^T in[src[i]]
-// Vectors are rows [(box * nrhs + r) * n_pad + m], s1 is [2][n][n] float32.
-void cheb_tensor(int nrhs, int n, bool l2l, const float *s1, int nitems, const int32_t *dst, const int32_t *src,
+// Vectors are rows [(box * nrhs + r) * n_pad + m], s1 is [2][n][n] float64;
+// arithmetic is float64.
+void cheb_tensor(int nrhs, int n, bool l2l, const double *s1, int nitems, const int32_t *dst, const int32_t *src,
                  const int8_t *oct, const float *in, float *out, int n_pad, hipStream_t s);
 
 }  // namespace fmm

@@ -386,12 +386,17 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
             const int64_t k = t_first + t;
             const int64_t dst = a.trg_perm ? a.trg_perm[k] : k;
             for (int r = 0; r < NRHS; ++r) {
-                if (a.pot) a.pot[r * a.n_trg + dst] = (hi[u][r][0] + lo[u][r][0]) * kInv4Pi;
+                if (a.pot) {
+                    float *pp = a.pot + r * a.n_trg + dst;
+                    const float v = (hi[u][r][0] + lo[u][r][0]) * kInv4Pi;
+                    *pp = a.accumulate ? *pp + v : v;
+                }
                 if (FIELD && a.field) {
                     float *f = a.field + ((int64_t)r * a.n_trg + dst) * 3;
-                    f[0] = (hi[u][r][1] + lo[u][r][1]) * kInv4Pi;
-                    f[1] = (hi[u][r][2] + lo[u][r][2]) * kInv4Pi;
-                    f[2] = (hi[u][r][3] + lo[u][r][3]) * kInv4Pi;
+                    for (int c = 0; c < 3; ++c) {
+                        const float v = (hi[u][r][1 + c] + lo[u][r][1 + c]) * kInv4Pi;
+                        f[c] = a.accumulate ? f[c] + v : v;
+                    }
                 }
             }
         }

@@ -36,7 +36,8 @@ void points_to_surface(int nrhs, bool sl, bool dl, const int32_t *items, int nit
 // its centre; for the surface form 2.95 and 1.05, for the Chebyshev form
 // the node weights at the nodes, radius 1); point sources are the ranges
 // prng[poff[leaf] .. poff[leaf+1]). Results go to pot[r * n_trg + perm[k]] and
-// field[(r * n_trg + perm[k]) * 3 + c] (user order), overwriting.
+// field[(r * n_trg + perm[k]) * 3 + c] (user order), overwriting (accumulate =
+// 0) or added to what is there (accumulate = 1).
 struct EvalArgs {
     const int32_t *wleaf = nullptr, *wt0 = nullptr;
     int nwork = 0;
@@ -52,6 +53,7 @@ struct EvalArgs {
     double rad_down = 0.0, rad_up = 0.0;
     float delta2 = 0.f;
     float *pot = nullptr, *field = nullptr;
+    int accumulate = 0;
 };
 void eval_leaves(int nrhs, bool sl, bool dl, const EvalArgs &a, const SurfaceGeom &g, const PointSrc &src,
                  hipStream_t s);

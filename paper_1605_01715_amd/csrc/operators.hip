@@ -296,10 +296,10 @@ std::shared_ptr<Operators> build_chebyshev(int n, double eps, hipStream_t s) {
             for (int k = 0; k < n; ++k) op->Y.insert(op->Y.end(), {x[i], x[j], x[k]});
     op->dY = upload(op->Y, s);
     {
-        std::vector<float> coef((size_t)n * n);
+        std::vector<double> coef((size_t)n * n);
         for (int i = 0; i < n; ++i)
             for (int k = 0; k < n; ++k)
-                coef[(size_t)i * n + k] = (float)(k == 0 ? 1.0 / n : 2.0 / n * std::cos(k * (2 * i + 1) * kPi / (2 * n)));
+                coef[(size_t)i * n + k] = k == 0 ? 1.0 / n : 2.0 / n * std::cos(k * (2 * i + 1) * kPi / (2 * n));
         op->cheb_coef = upload(coef, s);
     }
 
@@ -308,11 +308,11 @@ std::shared_ptr<Operators> build_chebyshev(int n, double eps, hipStream_t s) {
     // (exact: the parent's polynomials have degree n - 1 per axis); L2L uses
     // the transposes.
     {
-        std::vector<float> s1(2 * (size_t)n * n);
+        std::vector<double> s1(2 * (size_t)n * n);
         for (int side = 0; side < 2; ++side)
             for (int i = 0; i < n; ++i)
                 for (int i2 = 0; i2 < n; ++i2)
-                    s1[((size_t)side * n + i) * n + i2] = (float)cheb_lagrange(x, i, (side ? 0.5 : -0.5) + 0.5 * x[i2]);
+                    s1[((size_t)side * n + i) * n + i2] = cheb_lagrange(x, i, (side ? 0.5 : -0.5) + 0.5 * x[i2]);
         op->cheb_s1 = upload(s1, s);
     }
 

@@ -31,7 +31,7 @@ namespace fmm {
 // L2L by the transposes, both exact. M2L: K_d = G(x, 2 d + x) between unit boxes,
 // Q (ns x r) the leading eigenvectors of sum_d K_d K_d^T, m2l[d] = Q^T K_d Q
 // (r x r), pv = Q^T compresses W, cd = Q expands (times 1 / half-width).
-// cheb_coef[i][k] (n x n, float32) are the Chebyshev coefficients of node
+// cheb_coef[i][k] (n x n, float64) are the Chebyshev coefficients of node
 // i's Lagrange polynomial: 1/n for k = 0, (2/n) T_k(x_i) after.
 enum Basis { kBasisSurface = 0, kBasisChebyshev = 1 };
 
@@ -48,8 +48,8 @@ struct Operators {
     DBuf<double> pu_f64, pv_f64;   // r_pad x n_pad fragment layout
     DBuf<double> cu_f64, cd_f64;   // n_pad x r_pad fragment layout
     std::vector<double> U, V;      // host [ns][r] row-major (reconstruction for inspection)
-    DBuf<float> cheb_coef;         // Chebyshev basis: [n][n]
-    DBuf<float> cheb_s1;           // Chebyshev basis: [2][n][n]
+    DBuf<double> cheb_coef;        // Chebyshev basis: [n][n]
+    DBuf<double> cheb_s1;          // Chebyshev basis: [2][n][n]
 };
 
 // Chebyshev nodes of the first kind, cos((2i + 1) pi / (2n)), i = 0..n-1.

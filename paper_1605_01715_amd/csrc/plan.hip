@@ -622,8 +622,8 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             if (!P.cheb) {  // the Chebyshev L2P is an interpolation (nodes_to_points), not a kernel sum
                 sbox.push_back((int32_t)b);
                 skind.push_back(0);
+                P.surf_evals += ntrg(b) * ns;
             }
-            P.surf_evals += ntrg(b) * ns;
         }
         size_t from = prng.size();
         for (int32_t k = U.h_off[b]; k < U.h_off[b + 1]; ++k) add_src(U.h_idx[k]);
@@ -860,27 +860,26 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         mark(ST_L2L);
         for (auto &j : P.cheb_l2l)
             cheb_tensor(nrhs, op.p, true, op.cheb_s1.p, j.n, j.dst.p, j.src.p, j.oct.p, P.phi_d.p, P.phi_d.p, np, s);
-        mark(ST_C2E);
+        mark(ST_C2E);  // the Chebyshev L2P takes the slot of the surface form's check-to-equivalent maps
     } else {
-    mark(ST_P2M);
-    points_to_surface(nrhs, sl, dl, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, kRadOut, g, src, P.chk.p,
-                      false, s);
-    run_gemm(P.p2m_proj, op.pu_f64.p, rp, np, P.chk.p, P.ut.p, nullptr, false, s);
-    mark(ST_M2M);
-    for (auto &j : P.m2m_jobs) run_gemm(j, op.m2m_f64.p, rp, rp, P.ut.p, P.ut.p, nullptr, false, s);
-    mark(ST_P2L);
-    points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, kRadIn, g, src, P.chk.p,
-                      false, s);
-    run_gemm(P.p2l_proj, op.pv_f64.p, rp, np, P.chk.p, P.dt.p, nullptr, true, s);
-    mark(ST_M2L);
-    run_m2l();
-    mark(ST_L2L);
-    for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, rp, rp, P.dt.p, P.dt.p, nullptr, true, s);
-    mark(ST_C2E);
-    run_gemm(P.c2e_down, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_scale.p, false, s);
-    run_gemm(P.c2e_up, op.cu_f64.p, np, rp, P.ut.p, P.phi_u.p, P.col_scale.p, false, s);
+        mark(ST_P2M);
+        points_to_surface(nrhs, sl, dl, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, kRadOut, g, src, P.chk.p,
+                          false, s);
+        run_gemm(P.p2m_proj, op.pu_f64.p, rp, np, P.chk.p, P.ut.p, nullptr, false, s);
+        mark(ST_M2M);
+        for (auto &j : P.m2m_jobs) run_gemm(j, op.m2m_f64.p, rp, rp, P.ut.p, P.ut.p, nullptr, false, s);
+        mark(ST_P2L);
+        points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, kRadIn, g, src, P.chk.p,
+                          false, s);
+        run_gemm(P.p2l_proj, op.pv_f64.p, rp, np, P.chk.p, P.dt.p, nullptr, true, s);
+        mark(ST_M2L);
+        run_m2l();
+        mark(ST_L2L);
+        for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, rp, rp, P.dt.p, P.dt.p, nullptr, true, s);
+        mark(ST_C2E);
+        run_gemm(P.c2e_down, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_scale.p, false, s);
+        run_gemm(P.c2e_up, op.cu_f64.p, np, rp, P.ut.p, P.phi_u.p, P.col_scale.p, false, s);
     }
-    mark(ST_EVAL);
     EvalArgs e;
     e.wleaf = P.wleaf.p;
     e.wt0 = P.wt0.p;
@@ -913,8 +912,13 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     e.delta2 = std::max(P.opt.cutoff * P.opt.cutoff, std::numeric_limits<float>::min());
     e.pot = pot;
     e.field = field;
+    if (P.cheb) {
+        // L2P writes every target's output first; the leaf evaluation adds to it
+        nodes_to_points(nrhs, op.p, op.cheb_coef.p, e, g, P.phi_d.p, s);
+        e.accumulate = 1;
+    }
+    mark(ST_EVAL);
     eval_leaves(nrhs, sl, dl, e, g, src, s);
-    if (P.cheb) nodes_to_points(nrhs, op.p, op.cheb_coef.p, e, g, P.phi_d.p, s);
     mark(ST_COUNT);
     if (P.timing && !capturing) plan_collect_times(P);
 }
