@@ -89,6 +89,11 @@ __global__ __launch_bounds__(64) void k_points_to_nodes(const double *coef, cons
         for (int j0 = s0; j0 < s1; j0 += 64) {
             const int j = j0 + lane;
             const int cnt = min(64, s1 - j0);
+            if (j >= s1 && lane < ((cnt + 1) & ~1)) {
+                // the odd tail slot: a zero-strength record, so the loop below takes sources in pairs
+                float *p = sh + lane * W;
+                for (int k = 0; k < W; ++k) p[k] = 0.f;
+            }
             if (j < s1) {
                 float *p = sh + lane * W;
                 const double t[3] = {((double)src.x[j] - cx) * ih, ((double)src.y[j] - cy) * ih,
@@ -105,10 +110,9 @@ __global__ __launch_bounds__(64) void k_points_to_nodes(const double *coef, cons
                     }
             }
             __syncthreads();
-            for (int jj = 0; jj < cnt; ++jj) {
-                const float *p = sh + jj * W;
+            // the weights of x-node i for one source: S_x(i) A + dS_x(i) B
+            auto weights = [&](const float *p, float (&A)[NRHS], float (&B)[NRHS]) {
                 const float sy = p[OS + N + jy], sz = p[OS + 2 * N + kz];
-                float A[NRHS], B[NRHS];
 #pragma unroll
                 for (int r = 0; r < NRHS; ++r) {
                     A[r] = SL ? p[OQ + r] * (sy * sz) : 0.f;
@@ -122,12 +126,23 @@ __global__ __launch_bounds__(64) void k_points_to_nodes(const double *coef, cons
                         B[r] = p[OM + 3 * r] * (sy * sz);
                     }
                 }
+            };
+            for (int jj = 0; jj < cnt; jj += 2) {
+                // two sources per step: their float32 terms are added, then one float64 add
+                const float *p0 = sh + jj * W, *p1 = p0 + W;
+                float A0[NRHS], B0[NRHS], A1[NRHS], B1[NRHS];
+                weights(p0, A0, B0);
+                weights(p1, A1, B1);
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
-                    const float sx = p[OS + i];
-                    const float dsx = DL ? p[OD + i] : 0.f;
+                    const float sx0 = p0[OS + i], sx1 = p1[OS + i];
+                    const float dsx0 = DL ? p0[OD + i] : 0.f, dsx1 = DL ? p1[OD + i] : 0.f;
 #pragma unroll
-                    for (int r = 0; r < NRHS; ++r) acc[i][r] += (double)(DL ? sx * A[r] + dsx * B[r] : sx * A[r]);
+                    for (int r = 0; r < NRHS; ++r) {
+                        const float t0 = DL ? sx0 * A0[r] + dsx0 * B0[r] : sx0 * A0[r];
+                        const float t1 = DL ? sx1 * A1[r] + dsx1 * B1[r] : sx1 * A1[r];
+                        acc[i][r] += (double)(t0 + t1);
+                    }
                 }
             }
             __syncthreads();
@@ -143,7 +158,7 @@ __global__ __launch_bounds__(64) void k_points_to_nodes(const double *coef, cons
 template <int N, int NRHS, bool FIELD>
 __global__ __launch_bounds__(64) void k_nodes_to_points(const double *coef, EvalArgs a, SurfaceGeom g, const float *L) {
     constexpr int NN = N * N * N;
-    __shared__ float sl[NRHS * NN];
+    __shared__ double sl[NRHS * NN];  // node values, converted once per work item
     __shared__ double cf[N * N];
     const int lane = threadIdx.x;
     const int leaf = a.wleaf[blockIdx.x];
@@ -166,7 +181,7 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const double *coef, Eval
     const int64_t dst = a.trg_perm ? a.trg_perm[k] : k;
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) {
-        const float *lr = sl + r * NN;
+        const double *lr = sl + r * NN;
         double pot = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
         // the x axis stays a loop (n^2 node values live at a time); S_x(i) is
         // formed from row i of the coefficients

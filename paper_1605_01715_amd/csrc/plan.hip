@@ -850,14 +850,16 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         mark(ST_M2M);
         for (auto &j : P.cheb_m2m)
             cheb_tensor(nrhs, op.p, false, op.cheb_s1.p, j.n, j.dst.p, j.src.p, nullptr, P.phi_u.p, P.phi_u.p, np, s);
+        // the upward pass ends with the weights in the M2L basis
+        run_gemm(P.cheb_compress, op.pv_f64.p, rp, np, P.phi_u.p, P.ut.p, nullptr, false, s);
         mark(ST_P2L);
         points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, 1.0, g, src, P.phi_d.p,
                           false, s);
         mark(ST_M2L);
-        run_gemm(P.cheb_compress, op.pv_f64.p, rp, np, P.phi_u.p, P.ut.p, nullptr, false, s);
         run_m2l();
-        run_gemm(P.cheb_expand, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_iscale.p, true, s);
         mark(ST_L2L);
+        // the downward pass starts by expanding the M2L result onto the nodes
+        run_gemm(P.cheb_expand, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_iscale.p, true, s);
         for (auto &j : P.cheb_l2l)
             cheb_tensor(nrhs, op.p, true, op.cheb_s1.p, j.n, j.dst.p, j.src.p, j.oct.p, P.phi_d.p, P.phi_d.p, np, s);
         mark(ST_C2E);  // the Chebyshev L2P takes the slot of the surface form's check-to-equivalent maps

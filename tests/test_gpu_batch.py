@@ -28,7 +28,8 @@ def _densities(insts):
     return mus
 
 
-def test_batch_matches_independent_instances():
+@pytest.mark.parametrize("basis,order", [(0, 6), (1, 7)])
+def test_batch_matches_independent_instances(basis, order):
     import torch
 
     import paper_1605_01715_amd as F
@@ -42,8 +43,8 @@ def test_batch_matches_independent_instances():
     nrm = np.concatenate([d["normals"] for d in insts])
     trg = np.concatenate([d["trg"] for d in insts])
     mu = np.concatenate(mus, axis=1)  # [3][total sources]
-    opts = F.fmm_default_options(order=6, leaf_size=48, src_kernels=F.FMM_SRC_DOUBLE, outputs=F.FMM_OUT_POT,
-                                 nrhs=3)
+    opts = F.fmm_default_options(order=order, leaf_size=48, src_kernels=F.FMM_SRC_DOUBLE, outputs=F.FMM_OUT_POT,
+                                 nrhs=3, basis=basis)
     plan = F.fmm_setup_batch(so, dev(src), dev(nrm), to, dev(trg), options=opts)
     pot = torch.empty(3 * int(to[-1]), device="cuda:0")
     F.fmm_apply(plan, mu=dev(np.ascontiguousarray(mu)), pot=pot)
@@ -54,7 +55,8 @@ def test_batch_matches_independent_instances():
     say(f"  batch plan: {info['n_boxes']} boxes, {info['n_levels']} levels")
     for i, d in enumerate(insts):
         g = got[:, to[i]:to[i + 1]]
-        one = fmm_run(d["src"], mu=mus[i], nrm=d["normals"], trg=d["trg"], order=6, leaf=48, nrhs=3)["pot"]
+        one = fmm_run(d["src"], mu=mus[i], nrm=d["normals"], trg=d["trg"], order=order, leaf=48, nrhs=3,
+                      basis=basis)["pot"]
         dip = [mus[i][c].astype(np.float64)[:, None] * d["normals"].astype(np.float64) for c in range(3)]
         ref = np.stack([D.direct_sum(d["trg"], d["src"], None, dip[c])[0] for c in range(3)])
         e_one = D.rel_l2(g, one)

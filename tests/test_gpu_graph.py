@@ -13,23 +13,23 @@ from gpu_common import dev, say
 pytestmark = pytest.mark.gpu
 
 
-def _plan(x, nrm, F, prec=0):
-    opts = F.fmm_default_options(order=6, leaf_size=48, precision=prec,
+def _plan(x, nrm, F, prec=0, basis=0):
+    opts = F.fmm_default_options(order=6, leaf_size=48, precision=prec, basis=basis,
                                  src_kernels=F.FMM_SRC_SINGLE | F.FMM_SRC_DOUBLE, outputs=F.FMM_OUT_POT)
     return F.fmm_setup(x, nrm, options=opts)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_graph_replays_equal_eager(prec):
+@pytest.mark.parametrize("prec,basis", [(0, 0), (1, 0), (1, 1)])
+def test_graph_replays_equal_eager(prec, basis):
     import torch
 
     import paper_1605_01715_amd as F
 
     d = W.clustered(30000, seed=7)
-    say(f"test_graph_replays_equal_eager: n=30000 precision={prec}")
+    say(f"test_graph_replays_equal_eager: n=30000 precision={prec} basis={basis}")
     x, nrm = dev(d["xyz"]), dev(d["normals"])
     q, mu = dev(d["q"]), dev(d["mu"])
-    plan = _plan(x, nrm, F, prec)
+    plan = _plan(x, nrm, F, prec, basis)
     ref = torch.empty(len(d["q"]), device="cuda:0")
     F.fmm_apply(plan, q=q, mu=mu, pot=ref)
     torch.cuda.synchronize()
