@@ -367,18 +367,44 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(int r_pad, int ncol, const i
 }
 
 // Pair tiles: out[targets[t]] += the partial rows rows[off[t]] .. rows[off[t+1] - 1]
-// (row i at partial + i * r_pad), in the given (direction) order. One wave per
-// target, four values per lane.
+// (row i at partial + i * r_pad), added in the given (direction) order. One
+// wave per target, four values per lane. The row indices are loaded 64 at a
+// time (one per lane) and broadcast with readlane, so four row loads are in
+// flight at once instead of one dependent index-then-row chain per row.
 __global__ __launch_bounds__(256) void k_m2l_gather(int r_pad, int n, const int32_t *targets, const int32_t *off,
                                                     const int32_t *rows, const float *partial, float *out) {
     const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (t >= n) return;
-    const int v = targets[t], e0 = off[t], e1 = off[t + 1];
-    for (int r4 = 4 * lane; r4 < r_pad; r4 += 256) {
-        f32x4 sum = *(const f32x4 *)(partial + (size_t)rows[e0] * r_pad + r4);
-        for (int e = e0 + 1; e < e1; ++e) sum += *(const f32x4 *)(partial + (size_t)rows[e] * r_pad + r4);
-        f32x4 *o = (f32x4 *)(out + (size_t)v * r_pad + r4);
-        *o = *o + sum;
+    const int v = targets[t], e0 = off[t], m = off[t + 1] - e0;
+    auto row = [&](int i, int c) { return *(const f32x4 *)(partial + (size_t)i * r_pad + c); };
+    for (int c0 = 0; c0 < r_pad; c0 += 256) {
+        const int c = c0 + 4 * lane;
+        const bool act = c < r_pad;
+        f32x4 sum = {0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < m; b += 64) {
+            const int idx = b + lane < m ? rows[e0 + b + lane] : 0;
+            const int cnt = min(64, m - b);
+            int k = 0;
+            for (; k + 4 <= cnt; k += 4) {
+                const int i0 = __builtin_amdgcn_readlane(idx, k), i1 = __builtin_amdgcn_readlane(idx, k + 1);
+                const int i2 = __builtin_amdgcn_readlane(idx, k + 2), i3 = __builtin_amdgcn_readlane(idx, k + 3);
+                if (act) {
+                    const f32x4 a0 = row(i0, c), a1 = row(i1, c), a2 = row(i2, c), a3 = row(i3, c);
+                    sum += a0;
+                    sum += a1;
+                    sum += a2;
+                    sum += a3;
+                }
+            }
+            for (; k < cnt; ++k) {
+                const int i = __builtin_amdgcn_readlane(idx, k);
+                if (act) sum += row(i, c);
+            }
+        }
+        if (act) {
+            f32x4 *o = (f32x4 *)(out + (size_t)v * r_pad + c);
+            *o = *o + sum;
+        }
     }
 }
 
