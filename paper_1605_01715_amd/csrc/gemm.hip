@@ -20,6 +20,8 @@
 // shared by the four waves.
 #include "gemm.hpp"
 
+#include <algorithm>
+
 namespace fmm {
 
 namespace {
@@ -28,16 +30,18 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 
-// The tile's source vectors of one term are staged in LDS whole (float32,
-// [k][column], one barrier pair per term), and the matrix fragments of the
+// The tile's source vectors of one term are staged in LDS 128 k at a time
+// (float32, [k][column], 18 KB, so up to eight workgroups share a CU and
+// cover each other's staging and barriers), and the matrix fragments of the
 // next 16-k chunk are loaded while the current chunk's MFMAs run.
 constexpr int kMaxK = 512;
+constexpr int kKChunk = 128;          // k rows staged at a time
 constexpr int kBStr = kGemmCols + 4;  // floats per k row in LDS
 
 template <int MAXRB>
 __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmLaunch a) {
     constexpr int NCOL = kGemmCols;
-    extern __shared__ float Bs[];  // [k_pad][kBStr]
+    extern __shared__ float Bs[];  // [kKChunk][kBStr]
     __shared__ int32_t cols[NCOL], srcs[NCOL];
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6) + 4 * MAXRB * (int)blockIdx.y;  // first row block
@@ -58,19 +62,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmLaunch a) {
         if (!__syncthreads_or(mysrc >= 0)) continue;
         const int mat = a.term_mat ? a.term_mat[tile * a.nterm + term] : term;
         const double *M = a.mats + (size_t)mat * a.mat_elems;
-        // stage all K values of the 32 source vectors, transposed
-        const int kq = K / 4;
-        for (int idx = t; idx < NCOL * kq; idx += kThreads) {
-            const int col = idx / kq, k4 = (idx % kq) * 4;
-            const int sidx = srcs[col];
-            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (sidx >= 0) x = *(const float4 *)(a.in + (size_t)sidx * K + k4);
-            Bs[(k4 + 0) * kBStr + col] = x.x;
-            Bs[(k4 + 1) * kBStr + col] = x.y;
-            Bs[(k4 + 2) * kBStr + col] = x.z;
-            Bs[(k4 + 3) * kBStr + col] = x.w;
-        }
-        __syncthreads();
         // matrix fragments: av[i][s] for row block w + 4 i, chunk kc
         double av0[MAXRB][4], av1[MAXRB][4];
         auto load_av = [&](double (&av)[MAXRB][4], int kc) {
@@ -81,11 +72,12 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmLaunch a) {
                 for (int s = 0; s < 4; ++s) av[i][s] = ap[s];
             }
         };
-        auto mma = [&](const double (&av)[MAXRB][4], int kc) {
+        // chunk kc against the staged rows lk * 16 .. lk * 16 + 15 of the LDS slice
+        auto mma = [&](const double (&av)[MAXRB][4], int lk) {
             double bf[4][2];
             for (int s = 0; s < 4; ++s)
                 for (int cb = 0; cb < 2; ++cb)
-                    bf[s][cb] = (double)Bs[(kc * 16 + 4 * s + (lane >> 4)) * kBStr + cb * 16 + (lane & 15)];
+                    bf[s][cb] = (double)Bs[(lk * 16 + 4 * s + (lane >> 4)) * kBStr + cb * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < MAXRB; ++i) {
                 if (w + 4 * i >= nrb) continue;
@@ -94,13 +86,31 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmLaunch a) {
                         acc[i][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s], bf[s][cb], acc[i][cb], 0, 0, 0);
             }
         };
-        load_av(av0, 0);
-        for (int kc = 0; kc < nkc; kc += 2) {
-            if (kc + 1 < nkc) load_av(av1, kc + 1);
-            mma(av0, kc);
-            if (kc + 1 < nkc) {
-                if (kc + 2 < nkc) load_av(av0, kc + 2);
-                mma(av1, kc + 1);
+        for (int k0 = 0; k0 < K; k0 += kKChunk) {
+            const int kn = min(kKChunk, K - k0);  // a multiple of 16
+            if (k0 > 0) __syncthreads();         // every wave is done with the previous slice
+            // stage k0 .. k0 + kn of the 32 source vectors, transposed
+            const int kq = kn / 4;
+            for (int idx = t; idx < NCOL * kq; idx += kThreads) {
+                const int col = idx / kq, k4 = (idx % kq) * 4;
+                const int sidx = srcs[col];
+                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (sidx >= 0) x = *(const float4 *)(a.in + (size_t)sidx * K + k0 + k4);
+                Bs[(k4 + 0) * kBStr + col] = x.x;
+                Bs[(k4 + 1) * kBStr + col] = x.y;
+                Bs[(k4 + 2) * kBStr + col] = x.z;
+                Bs[(k4 + 3) * kBStr + col] = x.w;
+            }
+            __syncthreads();
+            const int c0 = k0 / 16, c1 = (k0 + kn) / 16;
+            load_av(av0, c0);
+            for (int kc = c0; kc < c1; kc += 2) {
+                if (kc + 1 < c1) load_av(av1, kc + 1);
+                mma(av0, kc - c0);
+                if (kc + 1 < c1) {
+                    if (kc + 2 < c1) load_av(av0, kc + 2);
+                    mma(av1, kc + 1 - c0);
+                }
             }
         }
     }
@@ -185,12 +195,8 @@ void box_gemm_f64(const GemmLaunch &a, hipStream_t s) {
     FMM_REQUIRE(a.m_pad % 16 == 0 && a.k_pad % 16 == 0 && a.m_pad <= 512 && a.k_pad <= kMaxK,
                 "box_gemm: unsupported size");
     dim3 g((unsigned)a.ntile, (unsigned)((a.m_pad / 16 + 3) / 4)), b(kThreads);  // one row block per wave
-    const size_t sh = (size_t)a.k_pad * kBStr * sizeof(float);
-    auto go = [&](auto kern) {
-        FMM_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(kMaxK * kBStr * sizeof(float))));
-        hipLaunchKernelGGL(kern, g, b, sh, s, a);
-    };
+    const size_t sh = (size_t)std::min(a.k_pad, kKChunk) * kBStr * sizeof(float);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, b, sh, s, a); };
     go(k_gemm_f64<1>);
     FMM_HIP(hipGetLastError());
 }
