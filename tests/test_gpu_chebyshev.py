@@ -156,3 +156,21 @@ def test_chebyshev_edge_cases():
         err = D.rel_l2(r["pot"][0], pot)
         say(f"  order {n}: vs oracle Chebyshev {err:.3e}")
         assert err < 3e-6
+
+
+def test_chebyshev_field_with_two_right_hand_sides():
+    """Field output with two right-hand sides in one plan: each equals its
+    single-rhs run, and the second matches the oracle's Chebyshev field."""
+    say("test_chebyshev_field_with_two_right_hand_sides: n=8000 order 6, split-BF16")
+    x, _, q, _ = _cloud(8000, 31)
+    q2 = np.stack([q, np.random.default_rng(32).standard_normal(len(q)).astype(np.float32)])
+    r2 = fmm_run(x, q=q2, nrhs=2, field=True, order=6, leaf=40, basis=CHEB, precision=1, pinv_eps=1e-7)
+    for k in range(2):
+        r1 = fmm_run(x, q=q2[k], field=True, order=6, leaf=40, basis=CHEB, precision=1, pinv_eps=1e-7)
+        assert D.rel_l2(r2["field"][k], r1["field"][0]) < 1e-6
+    t = T.build_tree(x, leaf_size=40)
+    ops = C.ChebOperators(6, rank=r2["info"]["rank"])
+    _, fld = C.cheb_apply(t, T.all_lists(t), ops, x, q=q2[1], field=True)
+    err = D.rel_l2(r2["field"][1], fld)
+    say(f"  rhs 1 field vs oracle Chebyshev {err:.3e}")
+    assert err < 5e-6
