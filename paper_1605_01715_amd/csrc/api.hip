@@ -154,6 +154,7 @@ void finish_plan(fmm::Plan &P, const fmm_options *opt, const float *trg_nrm, hip
         FMM_HIP(hipMemcpyAsync(P.trg_nrm_user.p, trg_nrm, 3 * P.t.n_src * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
     if (P.t.nb) plan_build_worklists(P, s);
+    if (P.cheb) plan_create_side(P);
     FMM_HIP(hipStreamSynchronize(s));
 }
 
@@ -263,6 +264,8 @@ int fmm_apply(fmm_plan plan, const float *q, const float *mu, float *pot, float 
         }
         if (P.timing && !P.ev[0]) {
             for (auto &e : P.ev) FMM_HIP(hipEventCreate(&e));
+            for (auto &e : P.ev_side) FMM_HIP(hipEventCreate(&e));
+            FMM_HIP(hipEventCreate(&P.ev_l2l_end));
         }
         if (P.graph.enabled && !P.timing)  // stage timing needs the ordinary apply
             plan_apply_graph(P, q, mu, pot, field, s);
@@ -340,8 +343,7 @@ int fmm_destroy(fmm_plan plan) {
     if (!plan) return FMM_OK;
     return guarded([&] {
         fmm::plan_release_graph(plan->p);
-        for (auto &e : plan->p.ev)
-            if (e) (void)hipEventDestroy(e);
+        fmm::plan_release_events(plan->p);
         plan->p.alive = false;
         delete plan;
     });

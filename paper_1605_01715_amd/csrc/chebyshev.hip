@@ -216,13 +216,15 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const double *coef, Eval
                 gz += sxi * biz;
             }
         }
-        if (a.pot) a.pot[r * a.n_trg + dst] = (float)pot;
+        if (a.pot) {
+            float *pp = a.pot + r * a.n_trg + dst;
+            *pp = a.accumulate ? (float)((double)*pp + pot) : (float)pot;
+        }
         if (FIELD && a.field) {
             // field = -grad_x f = -(1/h) grad_t f
             float *f = a.field + ((int64_t)r * a.n_trg + dst) * 3;
-            f[0] = (float)(-ih * gx);
-            f[1] = (float)(-ih * gy);
-            f[2] = (float)(-ih * gz);
+            const double gr[3] = {-ih * gx, -ih * gy, -ih * gz};
+            for (int c = 0; c < 3; ++c) f[c] = a.accumulate ? (float)((double)f[c] + gr[c]) : (float)gr[c];
         }
     }
 }

@@ -25,8 +25,9 @@ void points_to_nodes(int nrhs, bool sl, bool dl, int n, const double *coef, cons
 // L2P: for every work item of the leaf evaluation (a.wleaf / a.wt0: up to 64
 // targets of one leaf) write sum_m S(xbar_m, t) L_m to a.pot and
 // -(1/h) grad_t of it to a.field (user order through a.trg_perm; either may be
-// NULL), where L = node values [(leaf * nrhs + r) * g.n_pad + m]. Overwrites:
-// it runs before eval_leaves, which then adds (a.accumulate = 1).
+// NULL), where L = node values [(leaf * nrhs + r) * g.n_pad + m]. With
+// a.accumulate = 1 the values are added to what is there (the plan runs the
+// leaf evaluation first, on a side stream, and L2P after the join).
 void nodes_to_points(int nrhs, int n, const double *coef, const EvalArgs &a, const SurfaceGeom &g, const float *L,
                      hipStream_t s);
 

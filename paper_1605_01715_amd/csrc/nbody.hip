@@ -243,7 +243,7 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
                     const float dx = xl[u] - r0.x, dy = yl[u] - r0.y, dz = zl[u] - r0.z;
                     const float r2 = dx * dx + dy * dy + dz * dz;
                     const float inv = rsq(r2);
-                    if (FIELD) {
+                    if constexpr (FIELD) {
                         const float inv3 = inv * inv * inv;
                         for (int r = 0; r < NRHS; ++r) {
                             part[u][r][0] += ph[r] * inv;
@@ -320,7 +320,7 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
                     float sl[NRHS];
                     for (int r = 0; r < NRHS; ++r) sl[r] = SL ? rec[o + r] : 0.f;
                     if (SL) o += NRHS;
-                    if (FIELD) {
+                    if constexpr (FIELD) {
                         const float inv3 = inv2 * inv;
                         for (int r = 0; r < NRHS; ++r) {
                             part[u][r][0] += sl[r] * inv;

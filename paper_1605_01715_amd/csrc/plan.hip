@@ -838,50 +838,6 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
             m2l_gather(rp, P.m2l_ngather, P.m2l_gt.p, P.m2l_goff.p, P.m2l_gidx.p, P.m2l_partial.p, P.dt.p, s);
     };
 
-    if (P.cheb) {
-        // Chebyshev form (Sec. III.A.1 Eq. p2m): node weights W (phi_u) up the
-        // tree, node values L (phi_d) down; M2L in the shared compressed basis
-        hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)P.phi_d.n, kBlock)), dim3(kBlock), 0, s, P.phi_d.p,
-                           (int64_t)P.phi_d.n);
-        FMM_HIP(hipGetLastError());
-        mark(ST_P2M);
-        points_to_nodes(nrhs, sl, dl, op.p, op.cheb_coef.p, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, g, src,
-                        P.phi_u.p, s);
-        mark(ST_M2M);
-        for (auto &j : P.cheb_m2m)
-            cheb_tensor(nrhs, op.p, false, op.cheb_s1.p, j.n, j.dst.p, j.src.p, nullptr, P.phi_u.p, P.phi_u.p, np, s);
-        // the upward pass ends with the weights in the M2L basis
-        run_gemm(P.cheb_compress, op.pv_f64.p, rp, np, P.phi_u.p, P.ut.p, nullptr, false, s);
-        mark(ST_P2L);
-        points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, 1.0, g, src, P.phi_d.p,
-                          false, s);
-        mark(ST_M2L);
-        run_m2l();
-        mark(ST_L2L);
-        // the downward pass starts by expanding the M2L result onto the nodes
-        run_gemm(P.cheb_expand, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_iscale.p, true, s);
-        for (auto &j : P.cheb_l2l)
-            cheb_tensor(nrhs, op.p, true, op.cheb_s1.p, j.n, j.dst.p, j.src.p, j.oct.p, P.phi_d.p, P.phi_d.p, np, s);
-        mark(ST_C2E);  // the Chebyshev L2P takes the slot of the surface form's check-to-equivalent maps
-    } else {
-        mark(ST_P2M);
-        points_to_surface(nrhs, sl, dl, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, kRadOut, g, src, P.chk.p,
-                          false, s);
-        run_gemm(P.p2m_proj, op.pu_f64.p, rp, np, P.chk.p, P.ut.p, nullptr, false, s);
-        mark(ST_M2M);
-        for (auto &j : P.m2m_jobs) run_gemm(j, op.m2m_f64.p, rp, rp, P.ut.p, P.ut.p, nullptr, false, s);
-        mark(ST_P2L);
-        points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, kRadIn, g, src, P.chk.p,
-                          false, s);
-        run_gemm(P.p2l_proj, op.pv_f64.p, rp, np, P.chk.p, P.dt.p, nullptr, true, s);
-        mark(ST_M2L);
-        run_m2l();
-        mark(ST_L2L);
-        for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, rp, rp, P.dt.p, P.dt.p, nullptr, true, s);
-        mark(ST_C2E);
-        run_gemm(P.c2e_down, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_scale.p, false, s);
-        run_gemm(P.c2e_up, op.cu_f64.p, np, rp, P.ut.p, P.phi_u.p, P.col_scale.p, false, s);
-    }
     EvalArgs e;
     e.wleaf = P.wleaf.p;
     e.wt0 = P.wt0.p;
@@ -915,12 +871,66 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     e.pot = pot;
     e.field = field;
     if (P.cheb) {
-        // L2P writes every target's output first; the leaf evaluation adds to it
-        nodes_to_points(nrhs, op.p, op.cheb_coef.p, e, g, P.phi_d.p, s);
-        e.accumulate = 1;
+        // Chebyshev form (Sec. III.A.1 Eq. p2m): node weights W (phi_u) up the
+        // tree, node values L (phi_d) down; M2L in the shared compressed basis.
+        // The leaf evaluation needs W only (M2P), so it runs on the side stream
+        // from the end of the upward pass, beside P2L, M2L and L2L, and writes
+        // the outputs; L2P adds to them after the join.
+        hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)P.phi_d.n, kBlock)), dim3(kBlock), 0, s, P.phi_d.p,
+                           (int64_t)P.phi_d.n);
+        FMM_HIP(hipGetLastError());
+        mark(ST_P2M);
+        points_to_nodes(nrhs, sl, dl, op.p, op.cheb_coef.p, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, g, src,
+                        P.phi_u.p, s);
+        mark(ST_M2M);
+        for (auto &j : P.cheb_m2m)
+            cheb_tensor(nrhs, op.p, false, op.cheb_s1.p, j.n, j.dst.p, j.src.p, nullptr, P.phi_u.p, P.phi_u.p, np, s);
+        // the upward pass ends with the weights in the M2L basis
+        run_gemm(P.cheb_compress, op.pv_f64.p, rp, np, P.phi_u.p, P.ut.p, nullptr, false, s);
+        FMM_HIP(hipEventRecord(P.fork, s));
+        FMM_HIP(hipStreamWaitEvent(P.side, P.fork, 0));
+        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[0], P.side));
+        eval_leaves(nrhs, sl, dl, e, g, src, P.side);
+        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[1], P.side));
+        FMM_HIP(hipEventRecord(P.join, P.side));
+        mark(ST_P2L);
+        points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, 1.0, g, src, P.phi_d.p,
+                          false, s);
+        mark(ST_M2L);
+        run_m2l();
+        mark(ST_L2L);
+        // the downward pass starts by expanding the M2L result onto the nodes
+        run_gemm(P.cheb_expand, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_iscale.p, true, s);
+        for (auto &j : P.cheb_l2l)
+            cheb_tensor(nrhs, op.p, true, op.cheb_s1.p, j.n, j.dst.p, j.src.p, j.oct.p, P.phi_d.p, P.phi_d.p, np, s);
+        if (P.timing) FMM_HIP(hipEventRecord(P.ev_l2l_end, s));
+        FMM_HIP(hipStreamWaitEvent(s, P.join, 0));
+        mark(ST_C2E);  // the Chebyshev L2P takes the slot of the surface form's check-to-equivalent maps
+        EvalArgs el = e;
+        el.accumulate = 1;
+        nodes_to_points(nrhs, op.p, op.cheb_coef.p, el, g, P.phi_d.p, s);
+        mark(ST_EVAL);  // the evaluation itself is timed on the side stream
+    } else {
+        mark(ST_P2M);
+        points_to_surface(nrhs, sl, dl, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, kRadOut, g, src, P.chk.p,
+                          false, s);
+        run_gemm(P.p2m_proj, op.pu_f64.p, rp, np, P.chk.p, P.ut.p, nullptr, false, s);
+        mark(ST_M2M);
+        for (auto &j : P.m2m_jobs) run_gemm(j, op.m2m_f64.p, rp, rp, P.ut.p, P.ut.p, nullptr, false, s);
+        mark(ST_P2L);
+        points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, kRadIn, g, src, P.chk.p,
+                          false, s);
+        run_gemm(P.p2l_proj, op.pv_f64.p, rp, np, P.chk.p, P.dt.p, nullptr, true, s);
+        mark(ST_M2L);
+        run_m2l();
+        mark(ST_L2L);
+        for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, rp, rp, P.dt.p, P.dt.p, nullptr, true, s);
+        mark(ST_C2E);
+        run_gemm(P.c2e_down, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_scale.p, false, s);
+        run_gemm(P.c2e_up, op.cu_f64.p, np, rp, P.ut.p, P.phi_u.p, P.col_scale.p, false, s);
+        mark(ST_EVAL);
+        eval_leaves(nrhs, sl, dl, e, g, src, s);
     }
-    mark(ST_EVAL);
-    eval_leaves(nrhs, sl, dl, e, g, src, s);
     mark(ST_COUNT);
     if (P.timing && !capturing) plan_collect_times(P);
 }
@@ -932,7 +942,40 @@ void plan_collect_times(Plan &P) {
         FMM_HIP(hipEventElapsedTime(&ms, P.ev[k], P.ev[k + 1]));
         P.stage_ms[k] = ms;
     }
+    if (P.cheb) {
+        // L2L ends before the join; the evaluation ran on the side stream
+        float ms = 0.f;
+        FMM_HIP(hipEventElapsedTime(&ms, P.ev[ST_L2L], P.ev_l2l_end));
+        P.stage_ms[ST_L2L] = ms;
+        FMM_HIP(hipEventElapsedTime(&ms, P.ev_side[0], P.ev_side[1]));
+        P.stage_ms[ST_EVAL] = ms;
+    }
     P.have_times = true;
+}
+
+void plan_create_side(Plan &P) {
+    if (P.side) return;
+    FMM_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));  // default priority
+    FMM_HIP(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
+    FMM_HIP(hipEventCreateWithFlags(&P.join, hipEventDisableTiming));
+}
+
+void plan_release_events(Plan &P) {
+    if (P.side) {
+        (void)hipStreamSynchronize(P.side);
+        (void)hipStreamDestroy(P.side);
+        P.side = nullptr;
+    }
+    for (hipEvent_t *e : {&P.fork, &P.join, &P.ev_side[0], &P.ev_side[1], &P.ev_l2l_end})
+        if (*e) {
+            (void)hipEventDestroy(*e);
+            *e = nullptr;
+        }
+    for (auto &e : P.ev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
 }
 
 void plan_apply_graph(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s) {

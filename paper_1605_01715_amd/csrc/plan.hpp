@@ -93,8 +93,16 @@ struct Plan {
         std::array<const void *, 4> key{};
     } graph;
 
+    // Chebyshev form: the leaf evaluation (near field and M2P) needs only the
+    // node weights, so it runs on a plan-owned side stream forked after M2M
+    // and joined before L2P, beside P2L, M2L and L2L on the caller's stream
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+
     bool timing = false;
     hipEvent_t ev[ST_COUNT + 1] = {};
+    hipEvent_t ev_side[2] = {};      // evaluation start / end on the side stream (timing)
+    hipEvent_t ev_l2l_end = nullptr;  // end of L2L before the join (timing)
     double stage_ms[ST_COUNT] = {-1, -1, -1, -1, -1, -1, -1};
     bool have_times = false;
 };
@@ -108,6 +116,9 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
 void plan_apply_graph(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s);
 void plan_collect_times(Plan &P);
 void plan_release_graph(Plan &P);
+// Streams and events the plan owns (side stream, fork/join, timing events).
+void plan_create_side(Plan &P);
+void plan_release_events(Plan &P);
 // Dielectric problem (Sec. II.C): right-hand side with free charges (Eq. rhs)
 // into device b, and per-body forces eps_m sigma E a (sigma = sigma + sigma2,
 // sigma2 may be NULL) summed over the bodies' index ranges into host forces.
