@@ -879,6 +879,14 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)P.phi_d.n, kBlock)), dim3(kBlock), 0, s, P.phi_d.p,
                            (int64_t)P.phi_d.n);
         FMM_HIP(hipGetLastError());
+        // side stream, first: P2L at the nodes, beside P2M and M2M
+        FMM_HIP(hipEventRecord(P.fork0, s));
+        FMM_HIP(hipStreamWaitEvent(P.side, P.fork0, 0));
+        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[0], P.side));
+        points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, 1.0, g, src, P.phi_d.p,
+                          false, P.side);
+        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[1], P.side));
+        FMM_HIP(hipEventRecord(P.p2l_done, P.side));
         mark(ST_P2M);
         points_to_nodes(nrhs, sl, dl, op.p, op.cheb_coef.p, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, g, src,
                         P.phi_u.p, s);
@@ -887,19 +895,20 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
             cheb_tensor(nrhs, op.p, false, op.cheb_s1.p, j.n, j.dst.p, j.src.p, nullptr, P.phi_u.p, P.phi_u.p, np, s);
         // the upward pass ends with the weights in the M2L basis
         run_gemm(P.cheb_compress, op.pv_f64.p, rp, np, P.phi_u.p, P.ut.p, nullptr, false, s);
+        // side stream, second: the leaf evaluation, beside M2L and L2L
         FMM_HIP(hipEventRecord(P.fork, s));
         FMM_HIP(hipStreamWaitEvent(P.side, P.fork, 0));
-        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[0], P.side));
+        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[2], P.side));
         eval_leaves(nrhs, sl, dl, e, g, src, P.side);
-        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[1], P.side));
+        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[3], P.side));
         FMM_HIP(hipEventRecord(P.join, P.side));
-        mark(ST_P2L);
-        points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, 1.0, g, src, P.phi_d.p,
-                          false, s);
+        mark(ST_P2L);  // (P2L runs on the side stream; timed there)
         mark(ST_M2L);
         run_m2l();
         mark(ST_L2L);
-        // the downward pass starts by expanding the M2L result onto the nodes
+        // the downward pass starts by expanding the M2L result onto the nodes,
+        // adding to the P2L values
+        FMM_HIP(hipStreamWaitEvent(s, P.p2l_done, 0));
         run_gemm(P.cheb_expand, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_iscale.p, true, s);
         for (auto &j : P.cheb_l2l)
             cheb_tensor(nrhs, op.p, true, op.cheb_s1.p, j.n, j.dst.p, j.src.p, j.oct.p, P.phi_d.p, P.phi_d.p, np, s);
@@ -943,11 +952,13 @@ void plan_collect_times(Plan &P) {
         P.stage_ms[k] = ms;
     }
     if (P.cheb) {
-        // L2L ends before the join; the evaluation ran on the side stream
+        // L2L ends before the join; P2L and the evaluation ran on the side stream
         float ms = 0.f;
         FMM_HIP(hipEventElapsedTime(&ms, P.ev[ST_L2L], P.ev_l2l_end));
         P.stage_ms[ST_L2L] = ms;
         FMM_HIP(hipEventElapsedTime(&ms, P.ev_side[0], P.ev_side[1]));
+        P.stage_ms[ST_P2L] = ms;
+        FMM_HIP(hipEventElapsedTime(&ms, P.ev_side[2], P.ev_side[3]));
         P.stage_ms[ST_EVAL] = ms;
     }
     P.have_times = true;
@@ -956,8 +967,8 @@ void plan_collect_times(Plan &P) {
 void plan_create_side(Plan &P) {
     if (P.side) return;
     FMM_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));  // default priority
-    FMM_HIP(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
-    FMM_HIP(hipEventCreateWithFlags(&P.join, hipEventDisableTiming));
+    for (hipEvent_t *e : {&P.fork0, &P.p2l_done, &P.fork, &P.join})
+        FMM_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
 }
 
 void plan_release_events(Plan &P) {
@@ -966,7 +977,8 @@ void plan_release_events(Plan &P) {
         (void)hipStreamDestroy(P.side);
         P.side = nullptr;
     }
-    for (hipEvent_t *e : {&P.fork, &P.join, &P.ev_side[0], &P.ev_side[1], &P.ev_l2l_end})
+    for (hipEvent_t *e : {&P.fork0, &P.p2l_done, &P.fork, &P.join, &P.ev_side[0], &P.ev_side[1], &P.ev_side[2],
+                          &P.ev_side[3], &P.ev_l2l_end})
         if (*e) {
             (void)hipEventDestroy(*e);
             *e = nullptr;

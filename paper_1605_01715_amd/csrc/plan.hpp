@@ -93,15 +93,15 @@ struct Plan {
         std::array<const void *, 4> key{};
     } graph;
 
-    // Chebyshev form: the leaf evaluation (near field and M2P) needs only the
-    // node weights, so it runs on a plan-owned side stream forked after M2M
-    // and joined before L2P, beside P2L, M2L and L2L on the caller's stream
+    // Chebyshev form: P2L (needs only the points) and the leaf evaluation
+    // (near field and M2P, needs only the node weights) run on a plan-owned
+    // side stream, beside P2M/M2M and M2L/L2L on the caller's stream
     hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t fork0 = nullptr, p2l_done = nullptr, fork = nullptr, join = nullptr;
 
     bool timing = false;
     hipEvent_t ev[ST_COUNT + 1] = {};
-    hipEvent_t ev_side[2] = {};      // evaluation start / end on the side stream (timing)
+    hipEvent_t ev_side[4] = {};      // P2L start / end, evaluation start / end on the side stream (timing)
     hipEvent_t ev_l2l_end = nullptr;  // end of L2L before the join (timing)
     double stage_ms[ST_COUNT] = {-1, -1, -1, -1, -1, -1, -1};
     bool have_times = false;
