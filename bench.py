@@ -166,8 +166,8 @@ def main():
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design note only).", file=sys.stderr)
+        print(f"bench.py: the FMM runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
