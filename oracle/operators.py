@@ -31,9 +31,16 @@ form the GPU library's GMRES operator takes:
   eps_m sigma_j E_j a_j with sigma = sigma_f + sigma_b and E the field of
   sigma (with its self term) plus E0.
 
+  Quadrature variant of FK (Sec. IV.A): sources at the points of a
+  fifth-order rule on every flat triangle, targets at the mesh nodes
+  (fk_phi2_at_nodes), and the stray-field energy of the nodal potential
+  (stray_energy_on_mesh).
+
 Pins: tests/test_oracle_operators.py (sphere closed forms in closed_forms,
 Gauss's law for a charged sphere, Coulomb's law for distant spheres, the
-paper's force sign change between two charged dielectric spheres).
+paper's force sign change between two charged dielectric spheres) and
+tests/test_oracle_fk_quadrature.py (the rule's exactness, second-order
+convergence of phi_2 and the energy to the sphere's closed forms).
 """
 
 from __future__ import annotations
@@ -114,3 +121,36 @@ def body_forces(xyz, normals, areas, curvature, sigma, eps_m, body_off, e0=None,
         e = e + np.asarray(e0, dtype=np.float64)
     f = eps_m * (np.asarray(sigma, dtype=np.float64) * np.asarray(areas, dtype=np.float64))[:, None] * e
     return np.array([f[body_off[i]:body_off[i + 1]].sum(axis=0) for i in range(len(body_off) - 1)])
+
+
+def fk_phi2_at_nodes(phi1, verts, tris, bary, weights, delta=1e-5):
+    """phi_2 at the mesh nodes with the double layer integrated by a quadrature
+    rule on every flat triangle (Sec. II.B Eq. fk_integral; Sec. IV.A: a
+    fifth-order rule, quadrature points as sources and nodes as targets).
+
+    phi_1 is linear on each triangle (nodal values phi1). The solid-angle term
+    is taken from the same quadrature: Gauss's identity gives
+    Omega(x)/(4 pi) = -D[1](x) at a boundary node, so
+      phi_2(x) = D[phi_1](x) + (Omega(x)/(4 pi) - 1) phi_1(x)
+               = D[phi_1](x) - phi_1(x) D[1](x) - phi_1(x),
+    which integrates the density phi_1 - phi_1(x), zero at the target, where
+    the rule is least accurate.
+    """
+    from workloads import mesh_quadrature
+
+    pts, nrm, w = mesh_quadrature(verts, tris, bary, weights)
+    phi1 = np.asarray(phi1, dtype=np.float64)
+    phi1_q = (phi1[tris] @ np.asarray(bary).T).reshape(-1)
+    d_phi1, _ = direct_sum(verts, pts, None, (phi1_q * w)[:, None] * nrm, delta)
+    d_one, _ = direct_sum(verts, pts, None, w[:, None] * nrm, delta)
+    return d_phi1 - phi1 * d_one - phi1
+
+
+def stray_energy_on_mesh(phi, m, verts, tris, bary, weights):
+    """E = 1/2 surface-integral phi (M . n) dA (Sec. IV.A) with phi linear on
+    each flat triangle (nodal values) and the same quadrature rule."""
+    from workloads import mesh_quadrature
+
+    _, nrm, w = mesh_quadrature(verts, tris, bary, weights)
+    phi_q = (np.asarray(phi, dtype=np.float64)[tris] @ np.asarray(bary).T).reshape(-1)
+    return 0.5 * float(np.sum(phi_q * (nrm @ np.asarray(m, dtype=np.float64)) * w))

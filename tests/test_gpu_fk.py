@@ -138,3 +138,45 @@ def test_cube_stray_field_energy(basis, order, tol):
     say(f"  energy {e_gpu:.6f} (oracle {e_ref:.6f}, exact {CF.CUBE_ENERGY:.6f})")
     assert abs(e_gpu - e_ref) < tol * CF.CUBE_ENERGY
     assert abs(e_gpu - CF.CUBE_ENERGY) < 1e-2 * CF.CUBE_ENERGY
+
+
+@pytest.mark.parametrize("basis,order,tol", [(0, 8, 1e-4), (1, 8, 1e-4), (1, 5, 3e-3)])
+def test_quadrature_variant_at_the_nodes(basis, order, tol):
+    """The paper's fifth-order quadrature variant (Sec. IV.A): sources at the
+    7 points of a degree-5 rule on every flat triangle of an icosphere (14
+    times as many as the nodes), targets at the mesh nodes, two right-hand
+    sides in one plan (D[phi_1] and D[1], whose combination
+    D[phi_1] - phi_1 D[1] - phi_1 is phi_2 with the solid angle taken from the
+    same rule). phi_2 and the stray-field energy are checked against the
+    oracle's direct sums and the sphere's closed forms (-(2/3) phi_1 and
+    8 pi^2 / 9, up to the mesh's second-order error)."""
+    from gpu_common import fmm_run
+
+    v, t = W.icosphere(24)
+    bary, wr = W.triangle_rule_deg5()
+    pts, nrm, wq = W.mesh_quadrature(v, t, bary, wr)
+    m = np.array([0.6, 0.0, 0.8])
+    # the inputs the GPU consumes are float32; the oracle gets the same values
+    v32 = v.astype(np.float32).astype(np.float64)
+    phi1 = 4.0 * np.pi * (v32 @ m)
+    phi1_q = (phi1[t] @ bary.T).reshape(-1)
+    mu = np.stack([phi1_q * wq, wq])
+    say(f"test_quadrature_variant_at_the_nodes: {len(pts)} quadrature points, {len(v)} nodes, "
+        f"basis {basis} order {order}")
+    r = fmm_run(pts, mu=mu, nrm=nrm, trg=v, nrhs=2, order=order, leaf=64, basis=basis,
+                pinv_eps=1e-7 if order == 8 else 0.0)
+    d = r["pot"]
+    phi2 = d[0] - phi1 * d[1] - phi1
+    ref = OP.fk_phi2_at_nodes(phi1, v32, t, bary, wr)
+    exact = CF.sphere_phi2(v32, m)
+    e_or = np.linalg.norm(phi2 - ref) / np.linalg.norm(ref)
+    e_cf = np.linalg.norm(phi2 - exact) / np.linalg.norm(exact)
+    e_cf_ref = np.linalg.norm(ref - exact) / np.linalg.norm(exact)
+    en = OP.stray_energy_on_mesh(phi1 + phi2, m, v32, t, bary, wr)
+    en_ref = OP.stray_energy_on_mesh(phi1 + ref, m, v32, t, bary, wr)
+    say(f"  phi_2 vs oracle {e_or:.2e}, vs closed form {e_cf:.2e} (oracle {e_cf_ref:.2e}); energy {en:.6f} "
+        f"(oracle {en_ref:.6f}, exact {CF.SPHERE_ENERGY:.6f})")
+    assert e_or < tol
+    assert e_cf < e_cf_ref + tol
+    assert abs(en - en_ref) < tol * CF.SPHERE_ENERGY
+    assert abs(en - CF.SPHERE_ENERGY) < 2.5e-3 * CF.SPHERE_ENERGY

@@ -23,7 +23,8 @@ import math
 
 import numpy as np
 
-from .shapes import icosphere, sphere_quadrature, cube_surface, ellipsoid_surface, random_rotation
+from .shapes import (icosphere, sphere_quadrature, cube_surface, ellipsoid_surface, random_rotation,
+                     triangle_rule_deg5, mesh_quadrature)
 
 __all__ = [
     "cube_uniform",
@@ -35,6 +36,8 @@ __all__ = [
     "sphere_quadrature",
     "cube_surface",
     "ellipsoid_surface",
+    "triangle_rule_deg5",
+    "mesh_quadrature",
     "SINGULAR_RADIUS",
 ]
 

@@ -1,9 +1,12 @@
-"""Surface meshes and one-point (centroid) quadrature for the synthetic workloads.
+"""Surface meshes and quadrature points for the synthetic workloads.
 
 Geometry only: vertices, triangle centroids, outward normals and areas. The
 paper's electrostatic example puts one quadrature point at each element
 centroid, weighted by the element area, with the exact spherical area on
-spheres (Sec. III); these helpers produce exactly those inputs.
+spheres (Sec. III); these helpers produce exactly those inputs. Its
+magnetostatic example also integrates with a fifth-order rule on each
+triangle, so that sources far outnumber the mesh nodes (Sec. IV.A):
+triangle_rule_deg5 and mesh_quadrature.
 """
 
 from __future__ import annotations
@@ -93,6 +96,42 @@ def sphere_quadrature(freq, centre, radius):
     n /= np.linalg.norm(n, axis=1, keepdims=True)
     w = spherical_triangle_area(a, b, c) * radius * radius
     return np.asarray(centre) + radius * n, n, w
+
+
+def triangle_rule_deg5():
+    """Radon's seven-point rule on a triangle, exact for polynomials of degree 5.
+
+    Returns (bary [7, 3], weights [7]) with the weights summing to 1 (multiply
+    by the triangle's area): the centroid and two orbits of three points
+    (a, a, 1 - 2a) with a = (6 -+ sqrt(15)) / 21. Stroud's T2:5-1; the paper's
+    magnetostatic example integrates with a fifth-order rule (Sec. IV.A).
+    """
+    s15 = np.sqrt(15.0)
+    bary = [[1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0]]
+    weights = [9.0 / 40.0]
+    for a, wa in (((6.0 - s15) / 21.0, (155.0 - s15) / 1200.0), ((6.0 + s15) / 21.0, (155.0 + s15) / 1200.0)):
+        b = 1.0 - 2.0 * a
+        bary += [[a, a, b], [a, b, a], [b, a, a]]
+        weights += [wa] * 3
+    return np.array(bary), np.array(weights)
+
+
+def mesh_quadrature(verts, tris, bary, weights):
+    """Quadrature points of a rule on every flat triangle of a mesh.
+
+    Returns (points [T*Q, 3], normals [T*Q, 3], weights [T*Q]), triangle-major:
+    point q of triangle t is sum_k bary[q, k] verts[tris[t, k]], its normal the
+    triangle's unit normal (orientation of tris) and its weight
+    weights[q] * area(t). A field linear on each triangle with vertex values f
+    is, at the points, (f[tris] @ bary.T).reshape(-1).
+    """
+    a, b, c = verts[tris[:, 0]], verts[tris[:, 1]], verts[tris[:, 2]]
+    cr = np.cross(b - a, c - a)
+    area = 0.5 * np.linalg.norm(cr, axis=1)
+    nrm = cr / (2.0 * area[:, None])
+    pts = np.einsum("qk,tkc->tqc", bary, np.stack([a, b, c], axis=1)).reshape(-1, 3)
+    nq = len(weights)
+    return pts, np.repeat(nrm, nq, axis=0), (area[:, None] * weights[None, :]).reshape(-1)
 
 
 def cube_surface(side, n_nodes_target):
