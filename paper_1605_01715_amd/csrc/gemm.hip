@@ -1,4 +1,5 @@
-// Batched box GEMMs in float64 on the CDNA4 matrix cores, and float64 helpers
+// Batched box GEMMs in float64 on the CDNA4 matrix cores, a float32 MFMA GEMM
+// for the Chebyshev basis changes (below, k_gemm_f32), and float64 helpers
 // for the operator precompute.
 //
 // The upward and downward passes apply small dense matrices to per-box
@@ -188,6 +189,129 @@ __global__ __launch_bounds__(256) void k_dgemm(const double *A, size_t sa, const
     if (row < M && col < N) C[(size_t)b * sc + (size_t)row * N + col] = acc;
 }
 
+// One matrix for every column, float32 on the matrix cores
+// (v_mfma_f32_32x32x2f32, float32 accumulation): the Chebyshev form's
+// compression into the M2L basis and expansion out of it, the two largest
+// box GEMMs (every box, 512 x r). One workgroup per tile of 32 columns, so
+// the tile's source vectors are read from memory once: they are staged in
+// LDS 128 k at a time with coalesced loads (rows of k_pad floats) and shared
+// by the waves. Wave w owns the 32-row blocks w, w + NW (MAXRB of them) and
+// reads its matrix fragments from global memory in fragment order (every
+// load instruction reads 1 KB contiguous), the next chunk's while the
+// current chunk's MFMAs run. Lane l supplies row (or column) l % 32 at
+// k = 16 (l / 32) + q for MFMA q, so MFMA q contracts k = q and 16 + q of a
+// 32-k chunk (a permutation of the k order, the same on both operands).
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kF32Slice = 128;            // k staged per slice
+constexpr int kF32BStr = kF32Slice + 4;   // floats per column in LDS
+
+template <int MAXRB>
+__global__ __launch_bounds__(512) void k_gemm_f32(int m_pad, int k_pad, const int32_t *tile_cols, const float *Mf,
+                                                  const float *in, float *out, const double *col_scale,
+                                                  int accumulate) {
+    __shared__ __align__(16) float Bs[kGemmCols * kF32BStr];
+    __shared__ int32_t cols[kGemmCols];
+    const int t = threadIdx.x, lane = t & 63, c = lane & 31, h = lane >> 5;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int nt = blockDim.x, nw = nt >> 6, nrb = m_pad / 32, nkc = k_pad / 32;
+    const int64_t tile = blockIdx.x;
+    if (t < kGemmCols) cols[t] = tile_cols[tile * kGemmCols + t];
+    const float4 *ap[MAXRB];
+    bool live[MAXRB];
+#pragma unroll
+    for (int i = 0; i < MAXRB; ++i) {
+        const int rb = w + nw * i;
+        live[i] = rb < nrb;  // wave-uniform
+        ap[i] = (const float4 *)Mf + (size_t)min(rb, nrb - 1) * nkc * 256 + lane;
+    }
+    float4 a[2][MAXRB][4];
+    auto load_a = [&](int buf, int kc) {
+#pragma unroll
+        for (int i = 0; i < MAXRB; ++i)
+            if (live[i])
+#pragma unroll
+                for (int f = 0; f < 4; ++f) a[buf][i][f] = ap[i][(size_t)kc * 256 + 64 * f];
+    };
+    f32x16 acc[MAXRB];
+#pragma unroll
+    for (int i = 0; i < MAXRB; ++i)
+        for (int v = 0; v < 16; ++v) acc[i][v] = 0.f;
+    auto mma = [&](int buf, int kl) {  // kl: chunk offset inside the staged slice
+        float4 b[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) b[f] = *(const float4 *)&Bs[c * kF32BStr + kl + 16 * h + 4 * f];
+#pragma unroll
+        for (int i = 0; i < MAXRB; ++i) {
+            if (!live[i]) continue;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[buf][i][f].x, b[f].x, acc[i], 0, 0, 0);
+                acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[buf][i][f].y, b[f].y, acc[i], 0, 0, 0);
+                acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[buf][i][f].z, b[f].z, acc[i], 0, 0, 0);
+                acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[buf][i][f].w, b[f].w, acc[i], 0, 0, 0);
+            }
+        }
+    };
+    load_a(0, 0);
+    for (int k0 = 0; k0 < k_pad; k0 += kF32Slice) {
+        const int kn = min(kF32Slice, k_pad - k0), kq = kn / 4;  // kn: a multiple of 32
+        __syncthreads();  // cols; every wave is done with the previous slice
+        for (int idx = t; idx < kGemmCols * kq; idx += nt) {
+            const int col = idx / kq, k4 = (idx % kq) * 4;
+            const int o = cols[col];
+            *(float4 *)&Bs[col * kF32BStr + k4] =
+                o >= 0 ? *(const float4 *)(in + (size_t)o * k_pad + k0 + k4) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        __syncthreads();
+        const int c0 = k0 / 32, c1 = c0 + kn / 32;
+        for (int kc = c0; kc < c1; kc += 2) {
+            if (kc + 1 < nkc) load_a(1, kc + 1);
+            mma(0, (kc - c0) * 32);
+            if (kc + 1 < c1) {
+                if (kc + 2 < nkc) load_a(0, kc + 2);
+                mma(1, (kc + 1 - c0) * 32);
+            }
+        }
+    }
+    const int o = cols[c];
+    if (o < 0) return;
+    const float sc = col_scale ? (float)col_scale[o] : 1.f;
+#pragma unroll
+    for (int i = 0; i < MAXRB; ++i) {
+        if (!live[i]) continue;
+        // 32x32 accumulator: element v of lane l is row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+        float *op = out + (size_t)o * m_pad + (w + nw * i) * 32 + 4 * h;
+#pragma unroll
+        for (int v4 = 0; v4 < 4; ++v4) {
+            float4 r = make_float4(acc[i][4 * v4] * sc, acc[i][4 * v4 + 1] * sc, acc[i][4 * v4 + 2] * sc,
+                                   acc[i][4 * v4 + 3] * sc);
+            float4 *dst = (float4 *)(op + 8 * v4);
+            if (accumulate) {
+                const float4 old = *dst;
+                r.x += old.x;
+                r.y += old.y;
+                r.z += old.z;
+                r.w += old.w;
+            }
+            *dst = r;
+        }
+    }
+}
+
+// float64 row-major [rows][cols] -> the float32 fragment order of k_gemm_f32:
+// out[((rb * nkc + kc) * 4 + f) * 256 + 4 lane + e] = M[32 rb + lane % 32][32 kc + 16 (lane / 32) + 4 f + e]
+__global__ void k_frag_f32(const double *M, int rows, int cols, int m_pad, int k_pad, float *out) {
+    int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)m_pad * k_pad) return;
+    const int nkc = k_pad / 32;
+    const int e = (int)(idx % 4), lane = (int)((idx / 4) % 64), f = (int)((idx / 256) % 4);
+    const int64_t q = idx / 1024;
+    const int kc = (int)(q % nkc), rb = (int)(q / nkc);
+    const int row = rb * 32 + (lane & 31), k = kc * 32 + 16 * (lane >> 5) + 4 * f + e;
+    out[idx] = (row < rows && k < cols) ? (float)M[(int64_t)row * cols + k] : 0.f;
+}
+
 }  // namespace
 
 void box_gemm_f64(const GemmLaunch &a, hipStream_t s) {
@@ -198,6 +322,30 @@ void box_gemm_f64(const GemmLaunch &a, hipStream_t s) {
     const size_t sh = (size_t)std::min(a.k_pad, kKChunk) * kBStr * sizeof(float);
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, b, sh, s, a); };
     go(k_gemm_f64<1>);
+    FMM_HIP(hipGetLastError());
+}
+
+void dense_gemm_f32(int m_pad, int k_pad, int ntile, const int32_t *tile_cols, const float *M, const float *in,
+                    float *out, const double *col_scale, int accumulate, hipStream_t s) {
+    if (ntile <= 0) return;
+    FMM_REQUIRE(m_pad > 0 && k_pad > 0 && m_pad % 32 == 0 && k_pad % 32 == 0 && m_pad <= 512,
+                "dense_gemm_f32: unsupported size");
+    const int nrb = m_pad / 32, nw = std::min(nrb, 8);  // waves per workgroup; each owns ceil(nrb / nw) row blocks
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)ntile), dim3(64 * nw), 0, s, m_pad, k_pad, tile_cols, M, in, out,
+                           col_scale, accumulate);
+    };
+    if (nrb <= 8)
+        go(k_gemm_f32<1>);
+    else
+        go(k_gemm_f32<2>);
+    FMM_HIP(hipGetLastError());
+}
+
+void to_frag_f32(const double *M, int rows, int cols, int m_pad, int k_pad, float *out, hipStream_t s) {
+    FMM_REQUIRE(m_pad % 32 == 0 && k_pad % 32 == 0, "to_frag_f32: sizes must be multiples of 32");
+    int64_t total = (int64_t)m_pad * k_pad;
+    hipLaunchKernelGGL(k_frag_f32, dim3(grid_for(total, 256)), dim3(256), 0, s, M, rows, cols, m_pad, k_pad, out);
     FMM_HIP(hipGetLastError());
 }
 

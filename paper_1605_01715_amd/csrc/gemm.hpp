@@ -31,6 +31,17 @@ struct GemmLaunch {
 constexpr int kGemmCols = 32;
 void box_gemm_f64(const GemmLaunch &a, hipStream_t s);
 
+// One float32 matrix M (m_pad x k_pad, zero-padded, in the fragment order of
+// to_frag_f32) for every column, float32 MFMA arithmetic: for tile t and
+// c < 32 with o = tile_cols[t][c] >= 0,
+//     out[o] (+)= col_scale[o] * M * in[o]
+// (in rows of k_pad floats, out rows of m_pad floats; col_scale may be NULL,
+// accumulate adds to out). m_pad and k_pad are multiples of 32, m_pad <= 512.
+void dense_gemm_f32(int m_pad, int k_pad, int ntile, const int32_t *tile_cols, const float *M, const float *in,
+                    float *out, const double *col_scale, int accumulate, hipStream_t s);
+// float64 row-major M [rows][cols] -> float32 fragment order for dense_gemm_f32, zero-padded to m_pad x k_pad.
+void to_frag_f32(const double *M, int rows, int cols, int m_pad, int k_pad, float *out, hipStream_t s);
+
 // Layout conversions of a dense float64 matrix M [rows][cols] (row-major):
 // fragment order for box_gemm_f64, zero-padded to m_pad x k_pad; and a plain
 // row-major float32 copy zero-padded to m_pad x k_pad.

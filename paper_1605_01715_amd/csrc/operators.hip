@@ -366,6 +366,10 @@ std::shared_ptr<Operators> build_chebyshev(int n, double eps, hipStream_t s) {
     op->cd_f64.alloc((size_t)np * rp);  // M2L basis -> node values
     to_frag_f64(dQT.p, r, nn, rp, np, op->pv_f64.p, s);
     to_frag_f64(dQ.p, nn, r, np, rp, op->cd_f64.p, s);
+    op->pv_f32.alloc((size_t)rp * np);
+    op->cd_f32.alloc((size_t)np * rp);
+    to_frag_f32(dQT.p, r, nn, rp, np, op->pv_f32.p, s);
+    to_frag_f32(dQ.p, nn, r, np, rp, op->cd_f32.p, s);
     {
         DBuf<float> rm;
         build_translations(op->dY.p, nn, r, rp, prm, dQT.p, dQ.p, nullptr, &rm, s);

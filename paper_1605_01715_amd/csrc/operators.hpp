@@ -47,6 +47,7 @@ struct Operators {
     DBuf<double> m2m_f64, l2l_f64; // [8] r_pad x r_pad, float64 fragment layout
     DBuf<double> pu_f64, pv_f64;   // r_pad x n_pad fragment layout
     DBuf<double> cu_f64, cd_f64;   // n_pad x r_pad fragment layout
+    DBuf<float> pv_f32, cd_f32;    // Chebyshev basis: Q^T (r_pad x n_pad) and Q (n_pad x r_pad), to_frag_f32 order
     std::vector<double> U, V;      // host [ns][r] row-major (reconstruction for inspection)
     DBuf<double> cheb_coef;        // Chebyshev basis: [n][n]
     DBuf<double> cheb_s1;          // Chebyshev basis: [2][n][n]

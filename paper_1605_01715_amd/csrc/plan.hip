@@ -894,7 +894,8 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         for (auto &j : P.cheb_m2m)
             cheb_tensor(nrhs, op.p, false, op.cheb_s1.p, j.n, j.dst.p, j.src.p, nullptr, P.phi_u.p, P.phi_u.p, np, s);
         // the upward pass ends with the weights in the M2L basis
-        run_gemm(P.cheb_compress, op.pv_f64.p, rp, np, P.phi_u.p, P.ut.p, nullptr, false, s);
+        dense_gemm_f32(rp, np, P.cheb_compress.ntile, P.cheb_compress.cols.p, op.pv_f32.p, P.phi_u.p, P.ut.p,
+                       nullptr, 0, s);
         // side stream, second: the leaf evaluation, beside M2L and L2L
         FMM_HIP(hipEventRecord(P.fork, s));
         FMM_HIP(hipStreamWaitEvent(P.side, P.fork, 0));
@@ -909,7 +910,8 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         // the downward pass starts by expanding the M2L result onto the nodes,
         // adding to the P2L values
         FMM_HIP(hipStreamWaitEvent(s, P.p2l_done, 0));
-        run_gemm(P.cheb_expand, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_iscale.p, true, s);
+        dense_gemm_f32(np, rp, P.cheb_expand.ntile, P.cheb_expand.cols.p, op.cd_f32.p, P.dt.p, P.phi_d.p,
+                       P.col_iscale.p, 1, s);
         for (auto &j : P.cheb_l2l)
             cheb_tensor(nrhs, op.p, true, op.cheb_s1.p, j.n, j.dst.p, j.src.p, j.oct.p, P.phi_d.p, P.phi_d.p, np, s);
         if (P.timing) FMM_HIP(hipEventRecord(P.ev_l2l_end, s));
