@@ -158,7 +158,10 @@ __global__ __launch_bounds__(64) void k_points_to_nodes(const double *coef, cons
 template <int N, int NRHS, bool FIELD>
 __global__ __launch_bounds__(64) void k_nodes_to_points(const double *coef, EvalArgs a, SurfaceGeom g, const float *L) {
     constexpr int NN = N * N * N;
-    __shared__ double sl[NRHS * NN];  // node values, converted once per work item
+    // node values as stored (float32): every lane reads each of them, so LDS
+    // return bandwidth, not arithmetic, bounds this kernel; float32 halves it
+    // and the float64 arithmetic sees the same values
+    __shared__ __align__(16) float sl[NRHS * NN];
     __shared__ double cf[N * N];
     const int lane = threadIdx.x;
     const int leaf = a.wleaf[blockIdx.x];
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const double *coef, Eval
     const int64_t dst = a.trg_perm ? a.trg_perm[k] : k;
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) {
-        const double *lr = sl + r * NN;
+        const float *lr = sl + r * NN;
         double pot = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
         // the x axis stays a loop (n^2 node values live at a time); S_x(i) is
         // formed from row i of the coefficients
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const double *coef, Eval
                 double az = 0.0, azd = 0.0;
 #pragma unroll
                 for (int kk = 0; kk < N; ++kk) {
-                    const double l = lr[(i * N + j) * N + kk];
+                    const double l = (double)lr[(i * N + j) * N + kk];
                     az += sz[kk] * l;
                     if (FIELD) azd += dsz[kk] * l;
                 }
