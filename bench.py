@@ -110,27 +110,30 @@ def roofline(res, precision, n, cfg):
         "P2M": (p2m_flops, st["P2M"], "alu", PEAK_TFLOPS["fp32_valu"]),
     }
     # Chebyshev form: the leaf evaluation runs on its own stream beside M2L and
-    # its events bracket the kernel itself; the M2L stage (caller's stream)
-    # also holds the wait for CUs the evaluation occupies, so it is not the M2L
-    # kernel's duration and does not choose the dominant kernel
+    # its events bracket the kernel itself; the M2L stage times the translation
+    # kernel, its reduction and gather (the split of its input, which waits for
+    # CUs the evaluation holds, is in no stage)
     overlapped = cfg[0] == 1
-    name = max((k for k in cands if not (overlapped and k == "M2L")), key=lambda k: cands[k][1])
+    name = max(cands, key=lambda k: cands[k][1])
     flops, ms, bound, peak = cands[name]
     achieved = flops / (ms * 1e-3) / 1e12
     out = {"kernel": name, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
            "frac": round(achieved / peak, 5), "traffic": measured_traffic(name, precision, n, cfg),
            "algorithmic_flops": flops, "avg_ms": round(ms, 4)}
-    if name == "M2L":
-        out["rank"] = r
-        out["dense_equivalent_flops"] = 2.0 * ns * ns * info["m2l_pairs"]
+    def m2l_extras(ms_m2l, peak_m2l):
+        ext = {"rank": r, "dense_equivalent_flops": 2.0 * ns * ns * info["m2l_pairs"]}
         if info.get("m2l_columns"):
-            out["m2l_fill"] = round(info["m2l_pairs"] / info["m2l_columns"], 4)
+            ext["m2l_fill"] = round(info["m2l_pairs"] / info["m2l_columns"], 4)
             # MFMA work issued: padded r x r products over every column of every active step,
             # times 6 bf16 products per float32 product in the split form
             rp = (r + 31) // 32 * 32
             issued = 2.0 * rp * rp * info["m2l_columns"] * (6 if precision == 1 else 1)
-            out["mfma_issued_tflops"] = round(issued / (ms * 1e-3) / 1e12, 3)
-            out["mfma_issued_frac"] = round(issued / (ms * 1e-3) / 1e12 / peak, 5)
+            ext["mfma_issued_tflops"] = round(issued / (ms_m2l * 1e-3) / 1e12, 3)
+            ext["mfma_issued_frac"] = round(issued / (ms_m2l * 1e-3) / 1e12 / peak_m2l, 5)
+        return ext
+
+    if name == "M2L":
+        out.update(m2l_extras(ms, peak))
     if bound == "alu":
         out["frac_unpacked"] = round(achieved / PEAK_TFLOPS["fp32_valu_unpacked"], 5)
     others = {}
@@ -138,9 +141,13 @@ def roofline(res, precision, n, cfg):
         a = f / (t * 1e-3) / 1e12 if t > 0 else 0.0
         others[k] = {"bound": b, "achieved_tflops": round(a, 3), "peak": p, "frac": round(a / p, 5),
                      "avg_ms": round(t, 4)}
+    if cands["M2L"][1] > 0:
+        others["M2L"].update(m2l_extras(cands["M2L"][1], cands["M2L"][3]))
+    others["M2L"]["note"] = ("algorithmic FLOP at rank r; mfma_issued counts the padded products and the six "
+                             "bfloat16 products of the split form")
     if overlapped:
-        others["M2L"]["note"] = ("stage time on the caller's stream, concurrent with the leaf evaluation and "
-                                 "including the wait for CUs it occupies; the kernel's own duration is in profiles/")
+        others["M2L"]["note"] += ("; stage time on the caller's stream: the translation kernel, its reduction and "
+                                  "gather, partly beside the leaf evaluation's last workgroups")
     return out, others
 
 

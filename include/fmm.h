@@ -319,7 +319,11 @@ int fmm_set_graph(fmm_plan plan, int enable);
 int fmm_export_stage(fmm_plan plan, int which, float *host_out);
 
 /* Device time (ms) of each stage of the last apply made with timing on
- * (fmm_set_timing); -1 when none was. Order: P2M, M2M, P2L, M2L, L2L, C2E, EVAL. */
+ * (fmm_set_timing); -1 when none was. Order: P2M, M2M, P2L, M2L, L2L, C2E, EVAL.
+ * CHEBYSHEV plans run P2L and EVAL on a second stream (their times are taken
+ * there) and C2E is their L2P; their M2L stage times the translation kernel,
+ * the reduction and the gather, while the split of its input (split-BF16),
+ * which queues behind the evaluation, is in no stage. */
 int fmm_stage_times(fmm_plan plan, double *ms /* [7] */);
 
 #ifdef __cplusplus

