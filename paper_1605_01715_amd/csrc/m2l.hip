@@ -8,19 +8,20 @@
 // paper's interpolation-based far field (Sec. III.A.1 Eq. p2m, K_r between
 // interpolation nodes), grouped by translation direction into dense GEMMs.
 //
-// Blocking. A workgroup (8 waves) owns a tile of 128 target boxes of one
-// octant; each wave takes one 32-column block and one half of the rows, and
-// the workgroup keeps the r_pad x 128 accumulator in registers across all
-// directions, so every output is written once. Each step of the tile is one
+// Blocking. A workgroup owns a tile of 128 target boxes of one octant. With
+// 8 waves each takes one 32-column block and one half of the rows; with 4
+// (split-BF16 up to r_pad 192, two workgroups per CU) each takes one column
+// block and all rows. The workgroup keeps the r_pad x 128 accumulator in
+// registers across all directions, so every output is written once. Each step of the tile is one
 // (direction, 32-wide k-chunk): the chunk of M_d and the tile's 128 source
 // chunks are copied from global memory straight into LDS (global_load_lds,
 // 16 bytes per lane, no registers on the way) and every wave multiplies
 // them. With 32x32 MFMA tiles each staged matrix element is read from LDS once
 // per 32 columns. With two LDS buffers (split-BF16) the copies of step s + 1
 // are issued at the start of step s and run under its MFMAs; with one
-// (float32), two workgroups share each CU. The tiles of one octant run on one XCD (they
-// share most directions, so concurrently running tiles reuse the matrices in
-// that XCD's L2).
+// (float32, and the 4-wave split-BF16 form), two workgroups share each CU.
+// The tiles of one octant run on one XCD (they share most directions, so
+// concurrently running tiles reuse the matrices in that XCD's L2).
 //
 // The k index inside a chunk is permuted so that every lane's operand is a
 // run of consecutive values (16-byte reads); the dot product is the same.
@@ -50,8 +51,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kThreads = 512;  // 8 waves: 4 column blocks of 32 x 2 row halves
-constexpr int kCols = 128;
+constexpr int kCols = 128;     // 4 column blocks of 32
 constexpr int KC = 32;         // k per step
 
 // float32 -> bfloat16, round to nearest even (finite inputs)
@@ -100,10 +100,17 @@ __device__ inline void copy_to_lds(const void *src, void *dst) {
     __builtin_amdgcn_global_load_lds(src, (lds_void *)dst, 16, 0, 0);
 }
 
-template <int NRB, bool BF16>
+// NW = 8 waves: 4 column blocks x 2 row halves, two LDS buffers when they
+// fit. NW = 4 waves: one column block each with every row block, one buffer,
+// so that two workgroups share a CU and cover each other's copies and
+// barriers. Either way every wave reads the matrix chunk rows it multiplies
+// (4 reads of the chunk per step); with 4 waves the source chunk is read
+// once per column block instead of twice (one row half each).
+template <int NRB, bool BF16, int NW>
 struct Shape {
+    static_assert(NW == 8 || NW == 4, "8 or 4 waves");
     static constexpr int RP = NRB * 32;
-    static constexpr int RBH = (NRB + 1) / 2;                  // row blocks per wave
+    static constexpr int RBH = NW == 8 ? (NRB + 1) / 2 : NRB;  // row blocks per wave
     static constexpr int CHUNK = BF16 ? NRB * 32 * KC * 2 * 3 : NRB * 32 * KC * 4;  // A chunk bytes
     static constexpr int NIA = CHUNK / 1024;                   // 1 KB copies per A chunk
     static constexpr int PPC = BF16 ? 12 : 8;                  // 16-byte pieces per column chunk
@@ -111,19 +118,20 @@ struct Shape {
     static constexpr int BSTR = SPC * 16;                      // column stride in LDS: 16 lanes hit distinct banks
     static constexpr int BCH = kCols * BSTR;                   // B chunk bytes in LDS
     static constexpr int NIB = kCols * SPC / 64;               // 1 KB copies per B chunk
-    static constexpr int JA = (NIA + 7) / 8, JB = (NIB + 7) / 8;  // copies per wave (at most)
+    static constexpr int JA = (NIA + NW - 1) / NW, JB = (NIB + NW - 1) / NW;  // copies per wave (at most)
     static constexpr int LDS2 = 2 * (CHUNK + BCH) + 4 * kNumDirs;
     // Split-BF16: two buffers when they fit in LDS. Float32: one buffer (43 KB at r_pad 192), so two workgroups
     // share a CU and each covers the other's barriers (measured 6% faster
     // than two buffers; for split-BF16 two buffers are 6% faster at the
     // tuned leaf size).
-    static constexpr int NBUF = (BF16 && LDS2 <= 160 * 1024) ? 2 : 1;
+    static constexpr int NBUF = (NW == 8 && BF16 && LDS2 <= 160 * 1024) ? 2 : 1;
     static_assert(kCols * SPC % 64 == 0, "B slots must fill whole copies");
 };
 
-template <int NRB, bool BF16>
-__global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
-    using S = Shape<NRB, BF16>;
+template <int NRB, bool BF16, int NW>
+__global__ __launch_bounds__(NW * 64, 2) void k_m2l(M2LLaunch a) {
+    using S = Shape<NRB, BF16, NW>;
+    constexpr int kThreads = NW * 64;
     constexpr int RP = S::RP, RBH = S::RBH, CHUNK = S::CHUNK, NIA = S::NIA, PPC = S::PPC, SPC = S::SPC,
                   BSTR = S::BSTR, BCH = S::BCH, NIB = S::NIB, JA = S::JA, JB = S::JB, NBUF = S::NBUF;
     constexpr int PART = NRB * 2 * 64 * 8;  // bfloat16 elements of one part of an A chunk
@@ -134,9 +142,9 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
     unsigned char *sB[2] = {sB0, sB1};
     __shared__ int32_t s_dir[kNumDirs];
     const int t = threadIdx.x, lane = t & 63;
-    const int w = __builtin_amdgcn_readfirstlane(t >> 6) & 7;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6) & (NW - 1);
     const int hf = lane >> 5, r32 = lane & 31;
-    const int cblk = w & 3, rhalf = w >> 2;
+    const int cblk = w & 3, rhalf = NW == 8 ? w >> 2 : 0;
     const int rb0 = rhalf * RBH;
     const int nrb = (rb0 + RBH <= NRB) ? RBH : NRB - rb0;
 
@@ -149,13 +157,13 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
     const int outv = a.tile_cols[(int64_t)tile * kCols + my_col];
     for (int i = t; i < nact; i += kThreads) s_dir[i] = a.term_dir[toff + i];
 
-    // B copies: copy i = w + 8 j fills LDS slots 64 i .. 64 i + 63; slot q is
+    // B copies: copy i = w + NW j fills LDS slots 64 i .. 64 i + 63; slot q is
     // piece q % SPC of column q / SPC (piece PPC is the pad slot). Columns
     // without a source for the direction, and pad slots, copy zeros.
     int bcol[JB], bpiece[JB];
 #pragma unroll
     for (int j = 0; j < JB; ++j) {
-        const int q = (w + 8 * j) * 64 + lane;
+        const int q = (w + NW * j) * 64 + lane;
         bcol[j] = min(q / SPC, kCols - 1);
         bpiece[j] = q % SPC;
     }
@@ -188,14 +196,14 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LLaunch a) {
                                        : (const unsigned char *)(a.mats + ((int64_t)dir * NGR + kc) * (CHUNK / 4));
 #pragma unroll
         for (int j = 0; j < JA; ++j) {
-            const int i = w + 8 * j;
-            if (NIA % 8 != 0 && i >= NIA) continue;  // wave-uniform
+            const int i = w + NW * j;
+            if (NIA % NW != 0 && i >= NIA) continue;  // wave-uniform
             copy_to_lds(ag + (size_t)i * 1024 + lane * 16, &sA[BUF][i * 1024]);
         }
 #pragma unroll
         for (int j = 0; j < JB; ++j) {
-            const int i = w + 8 * j;
-            if (NIB % 8 != 0 && i >= NIB) continue;
+            const int i = w + NW * j;
+            if (NIB % NW != 0 && i >= NIB) continue;
             const int pc = bpiece[j];
             const unsigned char *src;
             if (cur_sv[j] < 0 || pc == PPC)
@@ -467,10 +475,19 @@ __global__ void k_image_f32(const float *rm, int r_pad, int64_t total, float *ou
     out[idx] = rm[(dir * r_pad + row) * r_pad + k];
 }
 
+// waves per workgroup: 4 for split-BF16 states up to 192 values (the
+// accumulators of every row block fit beside a second workgroup), else 8
+template <int NRB, bool BF16>
+constexpr int waves_for() {
+    return (BF16 && NRB <= 6) ? 4 : 8;
+}
+
 template <int NRB, bool BF16>
 void launch(const M2LLaunch &a, hipStream_t s) {
-    static_assert(Shape<NRB, BF16>::NBUF == 2 || Shape<NRB, BF16>::LDS2 / 2 <= 160 * 1024, "chunks do not fit in LDS");
-    hipLaunchKernelGGL((k_m2l<NRB, BF16>), dim3(a.ntile), dim3(kThreads), 0, s, a);
+    constexpr int NW = waves_for<NRB, BF16>();
+    using S = Shape<NRB, BF16, NW>;
+    static_assert(S::NBUF == 2 || S::LDS2 / 2 <= 160 * 1024, "chunks do not fit in LDS");
+    hipLaunchKernelGGL((k_m2l<NRB, BF16, NW>), dim3(a.ntile), dim3(NW * 64), 0, s, a);
     FMM_HIP(hipGetLastError());
 }
 
@@ -479,7 +496,8 @@ int blocks_per_cu(int nrb) {
     if constexpr (NRB <= 16) {
         if (nrb != NRB) return blocks_per_cu<BF16, NRB + 1>(nrb);
         int n = 0;
-        FMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_m2l<NRB, BF16>, kThreads, 0));
+        constexpr int NW = waves_for<NRB, BF16>();
+        FMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_m2l<NRB, BF16, NW>, NW * 64, 0));
         return n > 0 ? n : 1;
     } else {
         return 1;
