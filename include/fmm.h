@@ -60,9 +60,11 @@ enum { FMM_SRC_SINGLE = 1, FMM_SRC_DOUBLE = 2 };
 /* Outputs (bitmask). FIELD is defined for the single layer only. */
 enum { FMM_OUT_POT = 1, FMM_OUT_FIELD = 2 };
 /* Arithmetic of the box-to-box (M2L) translations. Every other step is float32
- * (float64 for the check-to-equivalent maps). SPLIT_BF16 splits both operands
- * into three bfloat16 parts and sums six partial products with float32
- * accumulation on the matrix cores. */
+ * data (float64 for the SURFACE form's check-to-equivalent maps and the
+ * CHEBYSHEV interpolation weights; the CHEBYSHEV changes of basis into and out
+ * of the M2L basis are float32 on the matrix cores). SPLIT_BF16 splits both
+ * operands into three bfloat16 parts and sums six partial products with
+ * float32 accumulation on the matrix cores. */
 enum { FMM_PREC_FP32 = 0, FMM_PREC_SPLIT_BF16 = 1 };
 /* Far-field representation of a box (Sec. III.A.1 Eq. p2m: the far field is
  * interpolated at the sources, translated with the plain 1/r kernel, and
