@@ -168,8 +168,21 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const double *coef, Eval
     const int64_t t_first = a.tbeg[leaf] + a.wt0[blockIdx.x];
     const int nt = (int)min((int64_t)64, a.tend[leaf] - t_first);
     if (lane < N * N) cf[lane] = coef[lane];
-    for (int m = lane; m < NN; m += 64)
-        for (int r = 0; r < NRHS; ++r) sl[r * NN + m] = L[((int64_t)leaf * NRHS + r) * g.n_pad + m];
+    {
+        // all loads first, then the LDS writes (the loads overlap)
+        constexpr int NV = (NN + 63) / 64;
+        float lv[NRHS][NV];
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r)
+#pragma unroll
+            for (int i = 0; i < NV; ++i)  // clamped index: no branch per load
+                lv[r][i] = L[((int64_t)leaf * NRHS + r) * g.n_pad + min(lane + 64 * i, NN - 1)];
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r)
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (lane + 64 * i < NN) sl[r * NN + lane + 64 * i] = lv[r][i];
+    }
     __syncthreads();
     if (lane >= nt) return;
     const int64_t k = t_first + lane;
@@ -261,7 +274,18 @@ __global__ __launch_bounds__(64) void k_cheb_tensor(const double *s1, const int3
             const int o = L2L ? oct[item] : t;
             const int sx = (o >> 2) & 1, sy = (o >> 1) & 1, szd = o & 1;
             __syncthreads();  // sm loaded; the previous term is done with X and T1
-            for (int m = lane; m < NN; m += 64) X[m] = in[(sb * NRHS + r) * n_pad + m];
+            {
+                // all loads first, then the LDS writes, so the loads are in
+                // flight together rather than one latency each
+                constexpr int NV = (NN + 63) / 64;
+                float xv[NV];
+#pragma unroll
+                for (int i = 0; i < NV; ++i)  // clamped index: no branch per load
+                    xv[i] = in[(sb * NRHS + r) * n_pad + min(lane + 64 * i, NN - 1)];
+#pragma unroll
+                for (int i = 0; i < NV; ++i)
+                    if (lane + 64 * i < NN) X[lane + 64 * i] = xv[i];
+            }
             __syncthreads();
             if (act) {
                 // z pass: T1[p'][q][s] = sum_s' A_z[s][s'] X[p'][q][s']
