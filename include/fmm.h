@@ -175,8 +175,11 @@ typedef struct {
 
 /*
  * Restarted GMRES(restart) on the operator above (Sec. III, matrix-free; the
- * paper's tolerance is 1e-5, Sec. IV.B). Orthogonalisation and residual norms
- * are float64 on the device; one fmm_apply per iteration.
+ * paper's tolerance is 1e-5, Sec. IV.B). Orthogonalisation (classical
+ * Gram-Schmidt twice) and residual norms are float64 on the device; one
+ * fmm_apply and one device-to-host copy of the step's coefficients per
+ * iteration. restart is 1..500; the Krylov basis takes (restart + 1) n
+ * float64 of device memory, allocated per call.
  *   b        device double [n]    right-hand side
  *   x        device double [n]    in: initial guess, out: solution (best iterate)
  *   iters    host int             iterations done
@@ -219,7 +222,12 @@ int fmm_body_forces(fmm_plan plan, const float *sigma_f, const float *sigma_b, c
                     const float *curvature, float eps_m, const double *e0, int n_body, const int64_t *body_off,
                     double *forces, void *hip_stream);
 
-/* Release the plan and its device memory. NULL is a no-op. */
+/* Release the plan and its device memory. NULL is a no-op. The handle stays
+ * known to the library as destroyed (a few bytes are kept per handle until the
+ * process ends, so no later plan reuses it): every later call that takes it,
+ * fmm_destroy included, returns FMM_ERR_STATE without touching freed memory.
+ * A pointer the library never issued gives FMM_ERR_ARG. Destroying a plan
+ * while another thread is inside a call on it is not allowed. */
 int fmm_destroy(fmm_plan plan);
 
 /* Thread-local message of the last failing call on this thread ("" if none). */
@@ -277,6 +285,24 @@ typedef struct {
     uint64_t *keys;                     /* sorted Morton keys of the combined points */
 } fmm_tree_export;
 int fmm_export_tree(fmm_plan plan, const fmm_tree_export *out);
+
+/*
+ * Inspection hook (no plan): split float32 values into the three bfloat16
+ * parts x = h + m + l that the split-BF16 M2L form multiplies (h = bf16(x),
+ * m = bf16(x - h), l = bf16(x - h - m), round to nearest even; the bf16x6
+ * scheme of Henry, Tang and Heinecke, ARITH 2019), with the same device code
+ * the library runs:
+ *   which = 0  the split of the far-field state made at every apply: `in`
+ *              holds count vectors of r_pad values;
+ *   which = 1  the split of the translation matrices made when operators are
+ *              built: `in` holds count r_pad x r_pad row-major matrices.
+ *   in     device float [count * r_pad] or [count * r_pad * r_pad]
+ *   parts  device uint16 [3][the same number], bit patterns of h, m, l, in
+ *          the values' row-major order
+ * r_pad is a multiple of 32 in 32..512, count in 0..2^24 (FMM_ERR_ARG
+ * otherwise). Allocates a temporary; synchronous on the stream.
+ */
+int fmm_split_bf16(int which, int r_pad, int64_t count, const float *in, uint16_t *parts, void *hip_stream);
 
 /* Host utility (no device work): truncated-SVD pseudo-inverse of the n x n
  * row-major float64 matrix K (host), singular values below eps * sigma_max

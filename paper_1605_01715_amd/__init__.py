@@ -20,7 +20,7 @@ from ._lib import (FMM_BASIS_CHEBYSHEV, FMM_BASIS_SURFACE, FMM_ERR_ARG, FMM_ERR_
 
 __all__ = ["fmm_setup_batch", "Plan", "FmmError", "fmm_default_options", "fmm_setup", "fmm_apply", "gmres_solve", "fmm_destroy",
            "fmm_last_error", "fmm_direct", "fmm_plan_info", "fmm_export_tree", "fmm_export_stage",
-           "fmm_set_timing", "fmm_set_graph", "fmm_dielectric_rhs", "fmm_body_forces", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "library_path"]
+           "fmm_set_timing", "fmm_set_graph", "fmm_dielectric_rhs", "fmm_body_forces", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "fmm_split_bf16", "library_path"]
 
 
 class FmmError(RuntimeError):
@@ -275,3 +275,19 @@ def fmm_unit_surface(p):
     out = np.zeros((ns.value, 3))
     _check(L.load().fmm_unit_surface(int(p), out.ctypes.data, ctypes.byref(ns)))
     return out
+
+
+def fmm_split_bf16(which, r_pad, values, stream=None):
+    """The library's three-part bfloat16 split of a float32 device tensor
+    (which 0: count vectors of r_pad values; which 1: count r_pad x r_pad
+    matrices). Returns a device uint16-bit int16 tensor [3][values.numel()]."""
+    import torch
+
+    n = int(values.numel())
+    per = r_pad * (r_pad if which == 1 else 1)
+    if n % per:
+        raise ValueError("fmm_split_bf16: values do not fill whole vectors or matrices")
+    parts = torch.empty(3 * n, dtype=torch.int16, device=values.device)
+    _check(L.load().fmm_split_bf16(int(which), int(r_pad), n // per, _ptr(values, torch.float32, "values"),
+                                    parts.data_ptr(), _stream(stream)))
+    return parts.view(3, n)

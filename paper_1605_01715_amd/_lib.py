@@ -70,6 +70,7 @@ SIGNATURES = {
     "fmm_export_stage": (c_int, [c_void_p, c_int, c_void_p]),
     "fmm_stage_times": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
     "fmm_pinv": (c_int, [c_void_p, c_int, c_double, c_void_p]),
+    "fmm_split_bf16": (c_int, [c_int, c_int, c_int64, c_void_p, c_void_p, c_void_p]),
     "fmm_unit_surface": (c_int, [c_int, c_void_p, ctypes.POINTER(c_int)]),
 }
 

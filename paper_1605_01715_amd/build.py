@@ -44,6 +44,31 @@ def build(verbose=False, jobs=8):
     return LIB
 
 
+def build_sanitized(outdir, jobs=8):
+    """Build the same library with AddressSanitizer and UndefinedBehaviorSanitizer
+    instrumenting the host code only (device code is built as usual), for
+    host-side checks of the C ABI on a machine without a GPU. Returns the path
+    of the shared library (outdir/libfmm_mi355x_san.so)."""
+    os.makedirs(outdir, exist_ok=True)
+    cc = hipcc()
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"] + san
+    procs, objs = [], []
+    for src in SOURCES:
+        obj = os.path.join(outdir, src.replace(".hip", ".o"))
+        objs.append(obj)
+        cmd = [cc, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        if len(procs) >= jobs:
+            _wait(procs.pop(0), False)
+    for p in procs:
+        _wait(p, False)
+    lib = os.path.join(outdir, "libfmm_mi355x_san.so")
+    subprocess.check_call([cc, "-shared", "-fopenmp", "--offload-arch=gfx950", *san, "-o", lib, *objs])
+    return lib
+
+
 def _wait(item, verbose):
     src, p = item
     out = p.communicate()[0].decode(errors="replace")

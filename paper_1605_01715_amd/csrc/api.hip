@@ -1,11 +1,17 @@
 // C ABI of the library (declared in include/fmm.h).
 #include <chrono>
 #include <cmath>
+#include <mutex>
+#include <unordered_map>
 
 #include "plan.hpp"
 
+// A handle is a small shell around the plan. fmm_destroy frees the plan and
+// keeps the shell as a tombstone for the rest of the process, so a handle
+// once issued is never reused for another plan and every later call on it can
+// be answered with FMM_ERR_STATE without touching freed memory.
 struct fmm_plan_s {
-    fmm::Plan p;
+    std::unique_ptr<fmm::Plan> p;
 };
 
 namespace {
@@ -34,10 +40,24 @@ int guarded(F &&f) {
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Every handle the library has issued, live or destroyed (true = live).
+std::mutex g_handles_mu;
+std::unordered_map<const fmm_plan_s *, bool> g_handles;
+
+void register_handle(fmm_plan_s *h) {
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    g_handles[h] = true;
+}
+
+// Look a handle up: NULL and pointers the library never issued are argument
+// errors, destroyed handles are state errors.
 fmm::Plan &live(fmm_plan plan) {
     if (!plan) throw fmm::Error(FMM_ERR_ARG, "plan is NULL");
-    if (!plan->p.alive) throw fmm::Error(FMM_ERR_STATE, "plan was destroyed");
-    return plan->p;
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    auto it = g_handles.find(plan);
+    if (it == g_handles.end()) throw fmm::Error(FMM_ERR_ARG, "not a plan handle issued by fmm_setup");
+    if (!it->second) throw fmm::Error(FMM_ERR_STATE, "plan was destroyed");
+    return *plan->p;
 }
 
 }  // namespace
@@ -178,8 +198,9 @@ int fmm_setup(const float *src_xyz, const float *src_nrm, int64_t n_src, const f
         auto t0 = std::chrono::steady_clock::now();
         hipStream_t s = as_stream(hip_stream);
         auto *h = new fmm_plan_s();
+        h->p.reset(new Plan());
         try {
-            Plan &P = h->p;
+            Plan &P = *h->p;
             init_plan(P, opt);
             build_tree(P.t, src_xyz, src_nrm, n_src, trg_xyz, trg_nrm, n_trg, tree_options(opt), s);
             finish_plan(P, opt, trg_nrm, s);
@@ -188,6 +209,7 @@ int fmm_setup(const float *src_xyz, const float *src_nrm, int64_t n_src, const f
             delete h;
             throw;
         }
+        register_handle(h);
         *out = h;
     });
 }
@@ -221,8 +243,9 @@ int fmm_setup_batch(int n_inst, const int64_t *src_off, const int64_t *trg_off, 
         auto t0 = std::chrono::steady_clock::now();
         hipStream_t s = as_stream(hip_stream);
         auto *h = new fmm_plan_s();
+        h->p.reset(new Plan());
         try {
-            Plan &P = h->p;
+            Plan &P = *h->p;
             init_plan(P, opt);
             const TreeOptions topt = tree_options(opt);
             std::vector<Tree> parts(n_inst);
@@ -242,6 +265,7 @@ int fmm_setup_batch(int n_inst, const int64_t *src_off, const int64_t *trg_off, 
             delete h;
             throw;
         }
+        register_handle(h);
         *out = h;
     });
 }
@@ -342,10 +366,17 @@ int gmres_solve(fmm_plan plan, const fmm_operator *op, const double *b, double *
 int fmm_destroy(fmm_plan plan) {
     if (!plan) return FMM_OK;
     return guarded([&] {
-        fmm::plan_release_graph(plan->p);
-        fmm::plan_release_events(plan->p);
-        plan->p.alive = false;
-        delete plan;
+        std::unique_ptr<fmm::Plan> dead;
+        {
+            std::lock_guard<std::mutex> lk(g_handles_mu);
+            auto it = g_handles.find(plan);
+            if (it == g_handles.end()) throw fmm::Error(FMM_ERR_ARG, "not a plan handle issued by fmm_setup");
+            if (!it->second) throw fmm::Error(FMM_ERR_STATE, "plan was already destroyed");
+            it->second = false;  // the shell stays allocated as a tombstone
+            dead = std::move(plan->p);
+        }
+        fmm::plan_release_graph(*dead);
+        fmm::plan_release_events(*dead);
     });
 }
 
@@ -461,6 +492,17 @@ int fmm_export_stage(fmm_plan plan, int which, float *host_out) {
                 host_out[box * P.ns + m] = (float)v;
             }
         }
+    });
+}
+
+int fmm_split_bf16(int which, int r_pad, int64_t count, const float *in, uint16_t *parts, void *hip_stream) {
+    return guarded([&] {
+        using namespace fmm;
+        FMM_REQUIRE(which == 0 || which == 1, "fmm_split_bf16: which must be 0 or 1");
+        FMM_REQUIRE(m2l_supported(r_pad), "fmm_split_bf16: r_pad must be a multiple of 32 in 32..512");
+        FMM_REQUIRE(count >= 0 && count <= (int64_t(1) << 24), "fmm_split_bf16: count out of range");
+        FMM_REQUIRE(count == 0 || (in && parts), "fmm_split_bf16: NULL argument");
+        m2l_split_plain(which, r_pad, count, in, parts, as_stream(hip_stream));
     });
 }
 

@@ -4,9 +4,10 @@
 // matrix-free form: only the action of A is defined, and the boundary integral
 // inside it is the dominant cost (Sec. III, electrostatic problem). Here every
 // iteration is one FMM apply plus float64 vector work on the device:
-// classical Gram-Schmidt applied twice (CGS2) for the Arnoldi step, the small
-// Hessenberg least-squares problem kept triangular by Givens rotations on the
-// host, and the true residual recomputed at every restart.
+// classical Gram-Schmidt applied twice (CGS2) for the Arnoldi step, its dot
+// products reduced on the device and brought back in one copy per step, the
+// small Hessenberg least-squares problem kept triangular by Givens rotations
+// on the host, and the true residual recomputed at every restart.
 #include <cmath>
 
 #include "plan.hpp"
@@ -36,6 +37,22 @@ __global__ __launch_bounds__(kBlock) void k_multi_dot(const double *V, int64_t l
     if (threadIdx.x == 0) partial[(int64_t)k * gridDim.x + blockIdx.x] = sh[0];
 }
 
+// out[k] = sum over blocks of partial[k][blk], reduced in a fixed tree order
+// (one workgroup per k; deterministic)
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(const double *partial, int nblk, double *out) {
+    __shared__ double sh[kBlock];
+    const int k = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) acc += partial[(int64_t)k * nblk + b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sh[0];
+}
+
 // w -= sum_k h[k] V[k]
 __global__ void k_multi_axpy(const double *V, int64_t ldv, int nk, const double *h, double *w, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -43,6 +60,13 @@ __global__ void k_multi_axpy(const double *V, int64_t ldv, int nk, const double 
     double acc = w[i];
     for (int k = 0; k < nk; ++k) acc -= h[k] * V[(int64_t)k * ldv + i];
     w[i] = acc;
+}
+
+// v /= sqrt(*sumsq) unless sqrt(*sumsq) <= floor (Arnoldi breakdown: v is left as it is)
+__global__ void k_normalise(double *v, const double *sumsq, double floor, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const double nrm = sqrt(*sumsq);
+    if (i < n && !(nrm <= floor)) v[i] = v[i] / nrm;
 }
 
 // x += sum_k y[k] V[k]
@@ -91,16 +115,20 @@ struct Gmres {
     const fmm_operator &op;
     hipStream_t s;
     int64_t n;
+    int kmax;                        // most vectors a Gram-Schmidt pass works on (restart + 1)
     DBuf<float> dens, pot, field;
-    DBuf<double> partial, hbuf;
-    std::vector<double> hpart;
+    DBuf<double> partial;            // [kmax][kDotBlocks] per-block dot products
+    DBuf<double> hdev;               // [2 kmax + 1]: both Gram-Schmidt passes and the squared norm
+    std::vector<double> hhost;
 
-    Gmres(Plan &p, const fmm_operator &o, hipStream_t st) : P(p), op(o), s(st), n(p.t.n_src) {
+    Gmres(Plan &p, const fmm_operator &o, int restart, hipStream_t st)
+        : P(p), op(o), s(st), n(p.t.n_src), kmax(restart + 1) {
         dens.alloc(n);
         if (op.kind == FMM_OP_FK) pot.alloc(n);
         else field.alloc(3 * n);
-        partial.alloc((size_t)kDotBlocks * 64);
-        hbuf.alloc(64);
+        partial.alloc((size_t)kDotBlocks * kmax);
+        hdev.alloc(2 * (size_t)kmax + 1);
+        hhost.resize(2 * (size_t)kmax + 1);
     }
 
     void matvec(const double *x, double *y) {
@@ -120,27 +148,41 @@ struct Gmres {
         FMM_HIP(hipGetLastError());
     }
 
-    // h[k] = V[k] . w for k < nk (deterministic two-level sum)
-    void dots(const double *V, int64_t ldv, int nk, const double *w, double *h) {
+    // hd[k] = V[k] . w for k < nk, on the device (deterministic two-level sum)
+    void dots(const double *V, int64_t ldv, int nk, const double *w, double *hd) {
+        if (nk > kmax) throw Error(FMM_ERR_ARG, "gmres: more Krylov vectors than the restart length");
         hipLaunchKernelGGL(k_multi_dot, dim3(kDotBlocks, nk), dim3(kBlock), 0, s, V, ldv, nk, w, n, partial.p);
         FMM_HIP(hipGetLastError());
-        hpart.resize((size_t)kDotBlocks * nk);
-        d2h(hpart.data(), partial.p, hpart.size(), s);
-        for (int k = 0; k < nk; ++k) {
-            double acc = 0.0;
-            for (int b = 0; b < kDotBlocks; ++b) acc += hpart[(size_t)k * kDotBlocks + b];
-            h[k] = acc;
-        }
+        hipLaunchKernelGGL(k_reduce_partials, dim3(nk), dim3(kBlock), 0, s, partial.p, kDotBlocks, hd);
+        FMM_HIP(hipGetLastError());
     }
     double norm(const double *v) {
+        dots(v, 0, 1, v, hdev.p);
         double h;
-        dots(v, 0, 1, v, &h);
+        d2h(&h, hdev.p, 1, s);
         return std::sqrt(h);
     }
-    void axpy_many(const double *V, int64_t ldv, int nk, const double *h, double *w) {
-        h2d(hbuf.p, h, nk, s);
-        hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, V, ldv, nk, hbuf.p, w, n);
+    void axpy_many(const double *V, int64_t ldv, int nk, const double *hd, double *w) {
+        hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, V, ldv, nk, hd, w, n);
         FMM_HIP(hipGetLastError());
+    }
+
+    // One Arnoldi step's orthogonalisation of w against V[0..nk): classical
+    // Gram-Schmidt twice, then w normalised unless its norm is at most
+    // `floor`. Everything stays on the device; one copy brings back both
+    // passes' coefficients (summed into h[0..nk)) and the norm.
+    double cgs2(const double *V, int64_t ldv, int nk, double *w, double floor, double *h) {
+        double *h1 = hdev.p, *h2 = hdev.p + kmax, *nn = hdev.p + 2 * kmax;
+        dots(V, ldv, nk, w, h1);
+        axpy_many(V, ldv, nk, h1, w);
+        dots(V, ldv, nk, w, h2);
+        axpy_many(V, ldv, nk, h2, w);
+        dots(w, 0, 1, w, nn);
+        hipLaunchKernelGGL(k_normalise, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, w, nn, floor, n);
+        FMM_HIP(hipGetLastError());
+        d2h(hhost.data(), hdev.p, hhost.size(), s);
+        for (int i = 0; i < nk; ++i) h[i] = hhost[i] + hhost[kmax + i];
+        return std::sqrt(hhost[2 * kmax]);
     }
 };
 
@@ -148,11 +190,11 @@ struct Gmres {
 
 void plan_gmres(Plan &P, const fmm_operator &op, const double *b, double *x, double rtol, int restart, int max_iter,
                 int *iters_out, double *rel_out, int *status, hipStream_t s) {
-    Gmres G(P, op, s);
+    Gmres G(P, op, restart, s);
     const int64_t n = G.n;
     const int m = restart;
-    DBuf<double> V((size_t)(m + 1) * n), w(n), r(n);
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1), h2(m + 1);
+    DBuf<double> V((size_t)(m + 1) * n), w(n), r(n), dy(m);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1);
     const double bnorm = G.norm(b);
     int iters = 0;
     *status = FMM_OK;
@@ -181,21 +223,12 @@ void plan_gmres(Plan &P, const fmm_operator &op, const double *b, double *x, dou
         g[0] = beta;
         int k = 0;
         const int mm = std::min(m, max_iter - iters);
+        const double floor = 1e-14 * beta;
         for (int j = 0; j < mm; ++j) {
             double *vj1 = V.p + (int64_t)(j + 1) * n;
             G.matvec(V.p + (int64_t)j * n, vj1);
-            // CGS2 against V[0..j]
-            G.dots(V.p, n, j + 1, vj1, h.data());
-            G.axpy_many(V.p, n, j + 1, h.data(), vj1);
-            G.dots(V.p, n, j + 1, vj1, h2.data());
-            G.axpy_many(V.p, n, j + 1, h2.data(), vj1);
-            for (int i = 0; i <= j; ++i) h[i] += h2[i];
-            const double hn = G.norm(vj1);
-            const bool breakdown = hn <= 1e-14 * beta;
-            if (!breakdown) {
-                hipLaunchKernelGGL(k_scale, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, vj1, 1.0 / hn, vj1, n);
-                FMM_HIP(hipGetLastError());
-            }
+            const double hn = G.cgs2(V.p, n, j + 1, vj1, floor, h.data());
+            const bool breakdown = hn <= floor;
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
             H[(size_t)(j + 1) * m + j] = hn;
             for (int i = 0; i < j; ++i) {
@@ -219,11 +252,9 @@ void plan_gmres(Plan &P, const fmm_operator &op, const double *b, double *x, dou
             for (int l = i + 1; l < k; ++l) acc -= H[(size_t)i * m + l] * y[l];
             y[i] = acc / H[(size_t)i * m + i];
         }
-        DBuf<double> dy(k);
         h2d(dy.p, y.data(), k, s);
         hipLaunchKernelGGL(k_update, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, V.p, n, k, dy.p, x, n);
         FMM_HIP(hipGetLastError());
-        FMM_HIP(hipStreamSynchronize(s));
     }
     FMM_HIP(hipStreamSynchronize(s));
     *iters_out = iters;

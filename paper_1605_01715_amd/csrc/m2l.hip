@@ -456,6 +456,31 @@ __global__ void k_split_vecs(const float *in, int r_pad, int64_t total, uint16_t
     o[2 * KC] = l;
 }
 
+// Inverse maps of the two split layouts, for inspection: parts[p][i] is part
+// p of the i-th value in row-major order (vectors of r_pad values, or
+// r_pad x r_pad matrices).
+__global__ void k_unsplit_vecs(const uint16_t *img, int r_pad, int64_t total, uint16_t *parts) {
+    int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const int64_t v = idx / r_pad;
+    const int k = (int)(idx % r_pad), kc = k / KC, kk = k % KC;
+    const uint16_t *src = img + v * vec_bf_stride(r_pad) + kc * 3 * KC + kk;
+    for (int p = 0; p < 3; ++p) parts[p * total + idx] = src[p * KC];
+}
+
+__global__ void k_unsplit_mats(const uint16_t *img, int r_pad, int64_t total, uint16_t *parts) {
+    int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;  // total = ndir * r_pad * r_pad, idx = (dir, row, k)
+    const int nrb = r_pad / 32, nkc = r_pad / KC;
+    const int64_t part_sz = (int64_t)nrb * 2 * 64 * 8;
+    const int k = (int)(idx % r_pad), row = (int)((idx / r_pad) % r_pad);
+    const int64_t dir = idx / ((int64_t)r_pad * r_pad);
+    const int kc = k / KC, kk = k % KC;
+    const int h2 = kk / 16, ln = (row & 31) + 32 * ((kk % 16) / 8), slot = kk % 8, rb = row / 32;
+    const uint16_t *src = img + (dir * nkc + kc) * 3 * part_sz + ((int64_t)(rb * 2 + h2) * 64 + ln) * 8 + slot;
+    for (int p = 0; p < 3; ++p) parts[p * total + idx] = src[p * part_sz];
+}
+
 // Matrices [ndir][r_pad][r_pad] float32 -> float32 chunks in LDS image order.
 __global__ void k_image_f32(const float *rm, int r_pad, int64_t total, float *out) {
     int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -549,6 +574,22 @@ void m2l_split_vecs(const float *in, int r_pad, int64_t nvec, uint16_t *out, hip
     if (total == 0) return;
     hipLaunchKernelGGL(k_split_vecs, dim3(grid_for(total, 256)), dim3(256), 0, s, in, r_pad, total, out);
     FMM_HIP(hipGetLastError());
+}
+
+void m2l_split_plain(int which, int r_pad, int64_t count, const float *in, uint16_t *parts, hipStream_t s) {
+    FMM_REQUIRE(m2l_supported(r_pad), "m2l: unsupported state size");
+    if (count <= 0) return;
+    const int64_t total = count * r_pad * (which == 1 ? r_pad : 1);
+    DBuf<uint16_t> img(3 * (size_t)total);
+    if (which == 1) {
+        m2l_split_mats(in, r_pad, (int)count, img.p, s);
+        hipLaunchKernelGGL(k_unsplit_mats, dim3(grid_for(total, 256)), dim3(256), 0, s, img.p, r_pad, total, parts);
+    } else {
+        m2l_split_vecs(in, r_pad, count, img.p, s);
+        hipLaunchKernelGGL(k_unsplit_vecs, dim3(grid_for(total, 256)), dim3(256), 0, s, img.p, r_pad, total, parts);
+    }
+    FMM_HIP(hipGetLastError());
+    FMM_HIP(hipStreamSynchronize(s));
 }
 
 int m2l_blocks_per_cu(bool bf16, int r_pad) {

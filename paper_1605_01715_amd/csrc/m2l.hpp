@@ -50,5 +50,9 @@ size_t m2l_split_mats_elems(int r_pad, int ndir);    // uint16 elements of the s
 size_t m2l_split_vecs_elems(int r_pad, int64_t nvec);
 void m2l_split_mats(const float *rm, int r_pad, int ndir, uint16_t *out, hipStream_t s);
 void m2l_split_vecs(const float *in, int r_pad, int64_t nvec, uint16_t *out, hipStream_t s);
+// The same splits written out plainly: parts[p][i], p = 0..2, of the values in
+// row-major order (which = 0: count vectors of r_pad; which = 1: count
+// r_pad x r_pad matrices). Synchronises the stream.
+void m2l_split_plain(int which, int r_pad, int64_t count, const float *in, uint16_t *parts, hipStream_t s);
 
 }  // namespace fmm

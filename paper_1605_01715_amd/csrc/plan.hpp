@@ -33,7 +33,6 @@ struct Plan {
     int nrhs = 1;
     int n_inst = 1;  // independent instances (fmm_setup_batch)
     bool sl = true, dl = false, want_pot = true, want_field = false;
-    bool alive = true;
     Tree t;
     std::shared_ptr<const Operators> ops;
     int ns = 0, n_pad = 0, r = 0, r_pad = 0;

@@ -56,3 +56,24 @@ def fmm_run(xyz, q=None, mu=None, nrm=None, trg=None, trg_nrm=None, field=False,
     else:
         F.fmm_destroy(plan)
     return out
+
+
+def errors(got, ref):
+    """(relative L2 error, worst-target error): the worst target's error
+    relative to the root-mean-square output, max_i |got_i - ref_i| / rms(ref),
+    with vector outputs (last axis 3) compared per target as vectors. A bound
+    on the second catches a few wrong targets that an L2 norm over many would
+    average away."""
+    g = np.asarray(got, dtype=np.float64)
+    r = np.asarray(ref, dtype=np.float64)
+    den = np.linalg.norm(r)
+    l2 = float(np.linalg.norm(g - r) / den) if den > 0 else float(np.linalg.norm(g))
+    if r.ndim >= 1 and r.shape[-1] == 3 and r.ndim >= 2:
+        d = np.linalg.norm(g - r, axis=-1).ravel()
+        m = np.linalg.norm(r, axis=-1).ravel()
+    else:
+        d = np.abs(g - r).ravel()
+        m = np.abs(r).ravel()
+    rms = float(np.sqrt(np.mean(m * m))) if m.size else 0.0
+    worst = float(d.max() / rms) if rms > 0 and d.size else float(d.max() if d.size else 0.0)
+    return l2, worst

@@ -160,6 +160,32 @@ def test_single_dielectric_sphere_closed_form():
     assert err < 2e-3
 
 
+def test_long_restart_cycle_against_oracle():
+    """A restart length above 64 (the Krylov basis and the per-step dot
+    products sized by it): 70 iterations in one cycle with a tolerance the
+    float32 matvec cannot reach, then the iterate against the oracle GMRES on
+    the direct sum at the FMM error level."""
+    import paper_1605_01715_amd as F
+
+    d = W.spheres_8(freq=6)
+    xyz, nrm, w, g = d["xyz"], d["normals"], d["weights"], d["g"]
+    n = len(w)
+    say(f"test_long_restart_cycle_against_oracle: n={n} restart=80 max_iter=70")
+    a = np.full(n, -0.5)
+    plan = _plan(xyz, nrm, F.FMM_SRC_DOUBLE, F.FMM_OUT_POT, order=6)
+    rc, it, rr, x = _solve(plan, F.FMM_OP_FK, a, None, w, g, rtol=1e-15, restart=80, max_iter=70)
+    F.fmm_destroy(plan)
+    say(f"  GPU GMRES: rc={rc} iterations={it} relative residual={rr:.2e}")
+    assert rc == F.FMM_ERR_NOT_CONVERGED and it == 70
+    assert rr < 1e-5 and np.all(np.isfinite(x))
+    x64, w64, n64 = xyz.astype(np.float64), w.astype(np.float64), nrm.astype(np.float64)
+    ref, _, _, ok = gmres(lambda v: OP.fk_apply(v, x64, n64, w64, a), g, rtol=1e-10)
+    assert ok
+    err = D.rel_l2(x, ref)
+    say(f"  solution rel L2 against the oracle = {err:.2e}")
+    assert err < 5e-5
+
+
 def test_gmres_not_converged_and_argument_errors():
     import paper_1605_01715_amd as F
 

@@ -154,3 +154,48 @@ def test_pseudo_inverse_truncates_small_singular_values():
     keep = s > 1e-6
     expect = (v[:, keep] / s[keep]) @ u[:, keep].T
     np.testing.assert_allclose(P, expect, rtol=1e-6, atol=1e-6 * np.abs(expect).max())
+
+
+def test_unknown_handles_are_rejected_without_being_read():
+    """A pointer the library never issued is an argument error in every entry
+    point that takes a plan; the library looks it up instead of reading it."""
+    F = _lib()
+    lib = F._lib.load()
+    bogus = ctypes.c_void_p(0x10)
+    assert lib.fmm_apply(bogus, None, None, None, None, None) == F.FMM_ERR_ARG
+    assert "not a plan handle" in F.fmm_last_error()
+    assert lib.fmm_destroy(bogus) == F.FMM_ERR_ARG
+    info = F._lib.FmmInfo()
+    assert lib.fmm_plan_info(bogus, ctypes.byref(info)) == F.FMM_ERR_ARG
+    assert lib.fmm_set_timing(bogus, 1) == F.FMM_ERR_ARG
+    assert lib.fmm_set_graph(bogus, 1) == F.FMM_ERR_ARG
+    assert lib.fmm_destroy(None) == F.FMM_OK
+
+
+@pytest.mark.slow
+def test_host_abi_under_address_and_ub_sanitizers(tmp_path):
+    """The library's host code built with AddressSanitizer and
+    UndefinedBehaviorSanitizer, driven through every C entry point path that
+    needs no GPU (argument checks, unknown handles, the host SVD, the unit
+    surface)."""
+    import shutil
+    import subprocess
+
+    from paper_1605_01715_amd import build as B
+
+    cxx = "/opt/rocm/llvm/bin/clang++"
+    if not os.path.exists(cxx):
+        pytest.skip("no clang++ for the sanitizer runtime")
+    lib = B.build_sanitized(str(tmp_path / "san"))
+    blob = open(lib, "rb").read()
+    assert b"__asan_report" in blob and b"__ubsan_handle" in blob  # the host code is instrumented
+    exe = tmp_path / "abi_host_checks"
+    subprocess.check_call([cxx, "-std=c++17", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "native",
+                                                                              "abi_host_checks.cpp"),
+                           "-L", str(tmp_path / "san"), "-lfmm_mi355x_san", "-Wl,-rpath," + str(tmp_path / "san"),
+                           "-o", str(exe)])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    out = subprocess.run([str(exe)], env=env, capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "host ABI checks passed" in out.stdout

@@ -39,6 +39,7 @@ __all__ = [
     "triangle_rule_deg5",
     "mesh_quadrature",
     "SINGULAR_RADIUS",
+    "float32_bits",
 ]
 
 # Pairs closer than this are excluded from every sum (Sec. III.A.1).
@@ -47,6 +48,21 @@ SINGULAR_RADIUS = 1.0e-5
 
 def _f32(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
+
+
+def float32_bits(n, seed, lo=-30, hi=30, ties=0):
+    """float32 values with random signs, binary exponents in [lo, hi) and
+    uniformly random 23-bit fractions, so that every rounding position of a
+    narrower format is exercised; the last `ties` values have their low 16
+    bits set to 0x8000 (exactly halfway between two bfloat16 values)."""
+    rng = np.random.default_rng(seed)
+    frac = rng.integers(0, 1 << 23, n, dtype=np.uint32)
+    exp = rng.integers(lo + 127, hi + 127, n).astype(np.uint32)
+    sign = rng.integers(0, 2, n).astype(np.uint32)
+    bits = (sign << 31) | (exp << 23) | frac
+    if ties:
+        bits[n - ties:] = (bits[n - ties:] & np.uint32(0xFFFF0000)) | np.uint32(0x8000)
+    return bits.view(np.float32)
 
 
 def cube_uniform(n=4096, seed=0):
