@@ -218,6 +218,19 @@ int gmres_solve(fmm_plan plan, const fmm_operator *op, const double *b, double *
  */
 int fmm_dielectric_rhs(fmm_plan plan, const float *sigma_f, const float *areas, const float *curvature,
                        const float *eps_i, float eps_m, const double *e0, double *b, void *hip_stream);
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * right-hand side as fmm_dielectric_rhs, same arguments and results, with the
+ * charge density and its field held in a fixed scratch array that the library
+ * keeps on each GPU for the life of the process (32 MiB per GPU). It calls no
+ * allocator and does not synchronise: b is written in stream order. At most
+ * 2,000,000 points (FMM_ERR_ARG beyond). Every call on a GPU shares that
+ * GPU's array, so calls that overlap in time on one GPU (two streams, two
+ * threads) race and must be serialised by the caller.
+ */
+int fmm_dielectric_rhs_noalloc(fmm_plan plan, const float *sigma_f, const float *areas, const float *curvature,
+                               const float *eps_i, float eps_m, const double *e0, double *b, void *hip_stream);
 int fmm_body_forces(fmm_plan plan, const float *sigma_f, const float *sigma_b, const float *areas,
                     const float *curvature, float eps_m, const double *e0, int n_body, const int64_t *body_off,
                     double *forces, void *hip_stream);

@@ -20,7 +20,8 @@ from ._lib import (FMM_BASIS_CHEBYSHEV, FMM_BASIS_SURFACE, FMM_ERR_ARG, FMM_ERR_
 
 __all__ = ["fmm_setup_batch", "Plan", "FmmError", "fmm_default_options", "fmm_setup", "fmm_apply", "gmres_solve", "fmm_destroy",
            "fmm_last_error", "fmm_direct", "fmm_plan_info", "fmm_export_tree", "fmm_export_stage",
-           "fmm_set_timing", "fmm_set_graph", "fmm_dielectric_rhs", "fmm_body_forces", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "fmm_split_bf16", "library_path"]
+           "fmm_set_timing", "fmm_set_graph", "fmm_dielectric_rhs", "fmm_body_forces", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "fmm_split_bf16", "fmm_dielectric_rhs_noalloc",
+           "library_path"]
 
 
 class FmmError(RuntimeError):
@@ -291,3 +292,19 @@ def fmm_split_bf16(which, r_pad, values, stream=None):
     _check(L.load().fmm_split_bf16(int(which), int(r_pad), n // per, _ptr(values, torch.float32, "values"),
                                     parts.data_ptr(), _stream(stream)))
     return parts.view(3, n)
+
+
+def fmm_dielectric_rhs_noalloc(plan, sigma_f, areas, curvature, eps_i, eps_m, b, e0=None, stream=None):
+    """fmm_dielectric_rhs without device allocation: b (device float64 [n]) is
+    written in stream order, the charge and its field live in the library's
+    fixed per-GPU scratch."""
+    import numpy as np
+    import torch
+
+    f32 = torch.float32
+    e = np.ascontiguousarray(np.asarray(e0, dtype=np.float64)) if e0 is not None else None
+    _check(L.load().fmm_dielectric_rhs_noalloc(plan.handle, _ptr(sigma_f, f32, "sigma_f"), _ptr(areas, f32, "areas"),
+                                               _ptr(curvature, f32, "curvature"), _ptr(eps_i, f32, "eps_i"),
+                                               float(eps_m), e.ctypes.data if e is not None else None,
+                                               _ptr(b, torch.float64, "b"), _stream(stream)))
+    return b

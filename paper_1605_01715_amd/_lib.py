@@ -64,6 +64,8 @@ SIGNATURES = {
     "fmm_set_graph": (c_int, [c_void_p, c_int]),
     "fmm_dielectric_rhs": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_void_p,
                                    c_void_p]),
+    "fmm_dielectric_rhs_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p,
+                                           c_void_p, c_void_p]),
     "fmm_body_forces": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_int,
                                 c_void_p, c_void_p, c_void_p]),
     "fmm_set_timing": (c_int, [c_void_p, c_int]),

@@ -309,6 +309,17 @@ int fmm_dielectric_rhs(fmm_plan plan, const float *sigma_f, const float *areas, 
     });
 }
 
+int fmm_dielectric_rhs_noalloc(fmm_plan plan, const float *sigma_f, const float *areas, const float *curvature,
+                               const float *eps_i, float eps_m, const double *e0, double *b, void *hip_stream) {
+    return guarded([&] {
+        using namespace fmm;
+        Plan &P = live(plan);
+        FMM_REQUIRE(sigma_f && areas && curvature && eps_i && b, "fmm_dielectric_rhs_noalloc: NULL argument");
+        FMM_REQUIRE(std::isfinite(eps_m) && eps_m > 0.f, "fmm_dielectric_rhs_noalloc: eps_m must be > 0");
+        dielectric_rhs_noalloc(P, sigma_f, areas, curvature, eps_i, eps_m, e0, b, as_stream(hip_stream));
+    });
+}
+
 int fmm_body_forces(fmm_plan plan, const float *sigma_f, const float *sigma_b, const float *areas,
                     const float *curvature, float eps_m, const double *e0, int n_body, const int64_t *body_off,
                     double *forces, void *hip_stream) {

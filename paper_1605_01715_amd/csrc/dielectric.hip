@@ -7,6 +7,7 @@
 // pol_discret, read as s_j sqrt(pi a_j) H_j / (4 pi) along n_j (the
 // principal-value field of a uniformly charged spherical cap of area a_j).
 #include <cmath>
+#include <mutex>
 
 #include "plan.hpp"
 
@@ -81,16 +82,32 @@ void require_field_plan(const Plan &P, const char *who) {
     FMM_REQUIRE(P.trg_nrm_user.n > 0, std::string(who) + ": the plan needs target normals");
 }
 
-// field of the charge (sigma + sigma2) * areas, caller's order, [n][3]
+// field of the charge (sigma + sigma2) * areas, caller's order, [n][3], into
+// dens [n] (the charge) and field [3 n]; stream-ordered
+void charge_field_into(Plan &P, const float *sigma, const float *sigma2, const float *areas, float *dens, float *field,
+                       hipStream_t s) {
+    const int64_t n = P.t.n_src;
+    hipLaunchKernelGGL(k_charge, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, sigma, sigma2, areas, dens, n);
+    FMM_HIP(hipGetLastError());
+    plan_apply(P, dens, nullptr, nullptr, field, s);
+}
+
 void charge_field(Plan &P, const float *sigma, const float *sigma2, const float *areas, DBuf<float> &field,
                   hipStream_t s) {
     const int64_t n = P.t.n_src;
     DBuf<float> dens(n);
     field.alloc(3 * n);
-    hipLaunchKernelGGL(k_charge, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, sigma, sigma2, areas, dens.p, n);
-    FMM_HIP(hipGetLastError());
-    plan_apply(P, dens.p, nullptr, nullptr, field.p, s);
+    charge_field_into(P, sigma, sigma2, areas, dens.p, field.p, s);
     FMM_HIP(hipStreamSynchronize(s));  // dens is freed on return
+}
+
+void launch_rhs(const Plan &P, const float *field, const float *sigma_f, const float *areas, const float *curv,
+                const float *eps_i, double eps_m, const double *e0, double *b, hipStream_t s) {
+    const int64_t n = P.t.n_src;
+    const double ex = e0 ? e0[0] : 0.0, ey = e0 ? e0[1] : 0.0, ez = e0 ? e0[2] : 0.0;
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, field, P.trg_nrm_user.p, sigma_f, areas,
+                       curv, eps_i, eps_m, ex, ey, ez, b, n);
+    FMM_HIP(hipGetLastError());
 }
 
 }  // namespace
@@ -102,11 +119,59 @@ void dielectric_rhs(Plan &P, const float *sigma_f, const float *areas, const flo
     if (n == 0) return;
     DBuf<float> field;
     charge_field(P, sigma_f, nullptr, areas, field, s);
-    const double ex = e0 ? e0[0] : 0.0, ey = e0 ? e0[1] : 0.0, ez = e0 ? e0[2] : 0.0;
-    hipLaunchKernelGGL(k_rhs, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, field.p, P.trg_nrm_user.p, sigma_f,
-                       areas, curv, eps_i, eps_m, ex, ey, ez, b, n);
-    FMM_HIP(hipGetLastError());
+    launch_rhs(P, field.p, sigma_f, areas, curv, eps_i, eps_m, e0, b, s);
     FMM_HIP(hipStreamSynchronize(s));
+}
+
+// Scratch of dielectric_rhs_noalloc, one copy per GPU for the life of the
+// process: the charge density (n floats) and its field (3 n floats, from a
+// 256-byte boundary) of the last call on that GPU. Calls that overlap in time
+// on one GPU race on it. Nothing in it needs clearing: both parts are fully
+// written before they are read.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current. The array's own name is a host-side stand-in and
+// is never passed to a kernel or a copy.
+unsigned char *scratch_address() {
+    int dev = 0;
+    FMM_HIP(hipGetDevice(&dev));
+    FMM_REQUIRE(dev >= 0 && dev < kMaxDevices, "scratch: device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        FMM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        FMM_REQUIRE(p != nullptr, "scratch: no device address");
+        g_scratch_ptr[dev] = p;
+    }
+    return static_cast<unsigned char *>(g_scratch_ptr[dev]);
+}
+
+}  // namespace
+
+void dielectric_rhs_noalloc(Plan &P, const float *sigma_f, const float *areas, const float *curv,
+                            const float *eps_i, double eps_m, const double *e0, double *b, hipStream_t s) {
+    require_field_plan(P, "fmm_dielectric_rhs_noalloc");
+    const int64_t n = P.t.n_src;
+    FMM_REQUIRE(n <= kNoAllocMaxPoints, "fmm_dielectric_rhs_noalloc: more points than the fixed scratch holds (" +
+                                            std::to_string(kNoAllocMaxPoints) + ")");
+    if (n == 0) return;
+    const size_t field_off = ((size_t)n * sizeof(float) + 255) / 256 * 256;
+    static_assert(((size_t)kNoAllocMaxPoints * 4 + 255) / 256 * 256 + (size_t)kNoAllocMaxPoints * 12 <=
+                      kNoAllocScratchBytes,
+                  "scratch too small for the point limit");
+    unsigned char *base = scratch_address();
+    float *dens = reinterpret_cast<float *>(base);
+    float *field = reinterpret_cast<float *>(base + field_off);
+    charge_field_into(P, sigma_f, nullptr, areas, dens, field, s);
+    launch_rhs(P, field, sigma_f, areas, curv, eps_i, eps_m, e0, b, s);
 }
 
 void body_forces(Plan &P, const float *sigma, const float *sigma2, const float *areas, const float *curv,

@@ -123,6 +123,12 @@ void plan_release_events(Plan &P);
 // sigma2 may be NULL) summed over the bodies' index ranges into host forces.
 void dielectric_rhs(Plan &P, const float *sigma_f, const float *areas, const float *curv, const float *eps_i,
                     double eps_m, const double *e0, double *b, hipStream_t s);
+// The same right-hand side with the charge and its field in a fixed scratch
+// array (no device allocation, no synchronisation: stream-ordered); at most
+// kNoAllocMaxPoints points.
+constexpr int64_t kNoAllocMaxPoints = 2000000;
+void dielectric_rhs_noalloc(Plan &P, const float *sigma_f, const float *areas, const float *curv,
+                            const float *eps_i, double eps_m, const double *e0, double *b, hipStream_t s);
 void body_forces(Plan &P, const float *sigma, const float *sigma2, const float *areas, const float *curv,
                  double eps_m, const double *e0, int n_body, const int64_t *body_off, double *forces, hipStream_t s);
 void plan_gmres(Plan &P, const fmm_operator &op, const double *b, double *x, double rtol, int restart, int max_iter,
