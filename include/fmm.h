@@ -62,10 +62,18 @@ enum { FMM_OUT_POT = 1, FMM_OUT_FIELD = 2 };
 /* Arithmetic of the box-to-box (M2L) translations. Every other step is float32
  * data (float64 for the SURFACE form's check-to-equivalent maps and the
  * CHEBYSHEV interpolation weights; the CHEBYSHEV changes of basis into and out
- * of the M2L basis are float32 on the matrix cores). SPLIT_BF16 splits both
- * operands into three bfloat16 parts and sums six partial products with
- * float32 accumulation on the matrix cores. */
-enum { FMM_PREC_FP32 = 0, FMM_PREC_SPLIT_BF16 = 1 };
+ * of the M2L basis are float32 on the matrix cores). The split forms run on
+ * the bfloat16 matrix cores with float32 accumulation (the schemes of Henry,
+ * Tang and Heinecke, ARITH 2019):
+ *   SPLIT_BF16    both operands in three bfloat16 parts x = h + m + l, six
+ *                 products hh hm mh mm hl lh (bf16x6): about float32 accuracy
+ *   SPLIT_BF16X4  two parts x = h + m, four products (bf16x4): each operand
+ *                 rounded to 16 significant bits, products of those exact
+ *   SPLIT_BF16X3  two parts, three products hh hm mh (bf16x3)
+ * The two-part forms copy two thirds of the bytes and issue two thirds (x4)
+ * or half (x3) of the matrix-core work of bf16x6, at about 2^-16 relative
+ * error per product instead of 2^-22. */
+enum { FMM_PREC_FP32 = 0, FMM_PREC_SPLIT_BF16 = 1, FMM_PREC_SPLIT_BF16X3 = 2, FMM_PREC_SPLIT_BF16X4 = 3 };
 /* Far-field representation of a box (Sec. III.A.1 Eq. p2m: the far field is
  * interpolated at the sources, translated with the plain 1/r kernel, and
  * interpolated at the targets).
@@ -83,7 +91,8 @@ enum { FMM_BASIS_SURFACE = 0, FMM_BASIS_CHEBYSHEV = 1 };
 typedef struct {
     int order;          /* SURFACE: p, points per edge of the equivalent/check surfaces, 2..10;
                            CHEBYSHEV: n, interpolation nodes per axis, 2..8 */
-    int leaf_size;      /* s: adaptive tree splits boxes holding more than s points (targets + sources) */
+    int leaf_size;      /* s: adaptive tree splits boxes holding more than s points (targets + sources);
+                           0: the cap fmm_autotune stored for this configuration (see there), else 128 */
     int uniform_depth;  /* > 0: uniform tree, every box above this level is split (0 = adaptive) */
     int max_depth;      /* deepest level, <= 21 */
     int precision;      /* FMM_PREC_* */
@@ -243,6 +252,46 @@ int fmm_body_forces(fmm_plan plan, const float *sigma_f, const float *sigma_b, c
  * while another thread is inside a call on it is not allowed. */
 int fmm_destroy(fmm_plan plan);
 
+/*
+ * Leaf-size tuning by trial runs (the paper tunes its octree height per problem
+ * by trial runs, Sec. III.A.1 and Sec. IV.A). For every leaf cap in
+ * space->leaf_sizes (and every M2L piece count in space->pieces, or the
+ * setup's own choice when n_pieces = 0) a plan is built with the caller's
+ * other options, applied once to random densities to warm up and then
+ * space->reps times, timed with HIP events on the stream; the median apply
+ * time decides. Accuracy is not tuned (the form, order and threshold stay the
+ * caller's). Points are given as for fmm_setup (n_inst = 0) or
+ * fmm_setup_batch (n_inst >= 1 with its offsets; n_src, n_trg unused).
+ *   cache_path  host string: file to record the choice in (JSON lines), "" for
+ *               the default (FMM_TUNE_CACHE, else ~/.cache/fmm_mi355x_tune.jsonl),
+ *               NULL to record nothing. fmm_setup and fmm_setup_batch with
+ *               leaf_size = 0 look the choice up in the default file by the
+ *               key of their configuration: device, basis, order, threshold,
+ *               arithmetic, kernels, outputs, nrhs, separate targets, batch,
+ *               and floor(log2(points per instance)).
+ *   out         host: the choice, its median apply time, and every trial.
+ * Builds and releases one plan per trial (device memory of one plan at a time
+ * plus the random densities and outputs).
+ */
+typedef struct {
+    int n_leaf;          /* 1..8 */
+    int leaf_sizes[8];
+    int n_pieces;        /* 0..4; 0: the setup's own choice */
+    int pieces[4];
+    int reps;            /* timed applies per trial, 1..100 */
+} fmm_tune_space;
+typedef struct {
+    int leaf_size, m2l_pieces;  /* the choice (m2l_pieces as the plan used it) */
+    double ms;                  /* its median apply time */
+    int n_tried;
+    int tried_leaf[32], tried_pieces[32];
+    double tried_ms[32], tried_setup_ms[32];
+} fmm_tune_result;
+int fmm_autotune(int n_inst, const int64_t *src_off, const int64_t *trg_off, const float *src_xyz,
+                 const float *src_nrm, int64_t n_src, const float *trg_xyz, const float *trg_nrm, int64_t n_trg,
+                 const fmm_options *opt, const fmm_tune_space *space, const char *cache_path, fmm_tune_result *out,
+                 void *hip_stream);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char *fmm_last_error(void);
 
@@ -266,7 +315,7 @@ typedef struct {
     int64_t m2l_pairs;                   /* M2L box pairs (V-list entries with sources) per rhs */
     int64_t surf_evals;                  /* target x surface-point kernel evaluations (L2P + M2P; for
                                             CHEBYSHEV M2P only, its L2P interpolates) per rhs */
-    int64_t p2m_evals;                   /* surface-point x source evaluations (P2M + P2L) per rhs */
+    int64_t p2m_evals;                   /* P2M: (surface point or node) x source pairs per rhs */
     int64_t m2l_columns;                 /* matrix-vector products the M2L kernel computes, padding
                                             included (m2l_pairs / m2l_columns is its fill) */
     int64_t rank;                        /* r: singular values kept (SURFACE: of the check-from-
@@ -279,6 +328,9 @@ typedef struct {
     int64_t basis;                       /* FMM_BASIS_* of the plan */
     double root[4];                      /* root cube actually used */
     double setup_ms;                     /* wall time of fmm_setup */
+    int64_t leaf_size;                   /* leaf cap the plan was built with */
+    int64_t leaf_from_cache;             /* 1 when leaf_size = 0 was resolved from the tuning cache */
+    int64_t p2l_evals;                   /* P2L: (check point or node) x X-list source evaluations per rhs */
 } fmm_info;
 int fmm_plan_info(fmm_plan plan, fmm_info *info);
 
@@ -361,10 +413,12 @@ int fmm_export_stage(fmm_plan plan, int which, float *host_out);
 
 /* Device time (ms) of each stage of the last apply made with timing on
  * (fmm_set_timing); -1 when none was. Order: P2M, M2M, P2L, M2L, L2L, C2E, EVAL.
- * CHEBYSHEV plans run P2L and EVAL on a second stream (their times are taken
- * there) and C2E is their L2P; their M2L stage times the translation kernel,
- * the reduction and the gather, while the split of its input (split-BF16),
- * which queues behind the evaluation, is in no stage. */
+ * Both forms run the leaf evaluation's near field on a second stream beside
+ * M2L (its time is taken there). CHEBYSHEV plans also run P2L there, C2E is
+ * their L2P, and their M2L stage times the translation kernel, the reduction
+ * and the gather, while the split of its input (split-BF16) is in no stage.
+ * SURFACE plans expand the upward densities in the M2M stage, and their EVAL
+ * is the near field (second stream) plus the L2P pass after the join. */
 int fmm_stage_times(fmm_plan plan, double *ms /* [7] */);
 
 #ifdef __cplusplus

@@ -16,11 +16,12 @@ import numpy as np
 from . import _lib as L
 from ._lib import (FMM_BASIS_CHEBYSHEV, FMM_BASIS_SURFACE, FMM_ERR_ARG, FMM_ERR_DEVICE, FMM_ERR_NOMEM,
                    FMM_ERR_NOT_CONVERGED, FMM_ERR_STATE, FMM_OK, FMM_OP_DIELECTRIC, FMM_OP_FK, FMM_OUT_FIELD,
-                   FMM_OUT_POT, FMM_PREC_FP32, FMM_PREC_SPLIT_BF16, FMM_SRC_DOUBLE, FMM_SRC_SINGLE, STAGES)
+                   FMM_OUT_POT, FMM_PREC_FP32, FMM_PREC_SPLIT_BF16, FMM_PREC_SPLIT_BF16X3, FMM_PREC_SPLIT_BF16X4,
+                   FMM_SRC_DOUBLE, FMM_SRC_SINGLE, STAGES)
 
 __all__ = ["fmm_setup_batch", "Plan", "FmmError", "fmm_default_options", "fmm_setup", "fmm_apply", "gmres_solve", "fmm_destroy",
            "fmm_last_error", "fmm_direct", "fmm_plan_info", "fmm_export_tree", "fmm_export_stage",
-           "fmm_set_timing", "fmm_set_graph", "fmm_dielectric_rhs", "fmm_body_forces", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "fmm_split_bf16", "fmm_dielectric_rhs_noalloc",
+           "fmm_set_timing", "fmm_set_graph", "fmm_dielectric_rhs", "fmm_body_forces", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "fmm_split_bf16", "fmm_dielectric_rhs_noalloc", "fmm_autotune",
            "library_path"]
 
 
@@ -308,3 +309,37 @@ def fmm_dielectric_rhs_noalloc(plan, sigma_f, areas, curvature, eps_i, eps_m, b,
                                                float(eps_m), e.ctypes.data if e is not None else None,
                                                _ptr(b, torch.float64, "b"), _stream(stream)))
     return b
+
+
+def fmm_autotune(src_xyz, src_nrm=None, trg_xyz=None, trg_nrm=None, options=None, leaf_sizes=(64, 128, 192, 256),
+                 pieces=(), reps=3, cache_path="", src_off=None, trg_off=None, stream=None):
+    """Leaf-size tuning by trial runs; returns a dict with the choice and every
+    trial. cache_path: "" the default cache file, None no cache, else a path.
+    src_off / trg_off (host prefix offsets) make it a batch as in fmm_setup_batch."""
+    import torch
+
+    lib = L.load()
+    opts = options if options is not None else fmm_default_options()
+    sp = L.FmmTuneSpace()
+    sp.n_leaf = len(leaf_sizes)
+    for i, v in enumerate(leaf_sizes):
+        sp.leaf_sizes[i] = int(v)
+    sp.n_pieces = len(pieces)
+    for i, v in enumerate(pieces):
+        sp.pieces[i] = int(v)
+    sp.reps = int(reps)
+    res = L.FmmTuneResult()
+    f32 = torch.float32
+    so = np.ascontiguousarray(np.asarray(src_off, dtype=np.int64)) if src_off is not None else None
+    to = np.ascontiguousarray(np.asarray(trg_off, dtype=np.int64)) if trg_off is not None else None
+    n_inst = len(so) - 1 if so is not None else 0
+    n_src = int(src_xyz.shape[0])
+    n_trg = int(trg_xyz.shape[0]) if trg_xyz is not None else 0
+    cp = None if cache_path is None else str(cache_path).encode()
+    _check(lib.fmm_autotune(n_inst, so.ctypes.data if so is not None else None, to.ctypes.data if to is not None else None,
+                            _ptr(src_xyz, f32, "src_xyz"), _ptr(src_nrm, f32, "src_nrm"), n_src,
+                            _ptr(trg_xyz, f32, "trg_xyz"), _ptr(trg_nrm, f32, "trg_nrm"), n_trg, ctypes.byref(opts),
+                            ctypes.byref(sp), cp, ctypes.byref(res), _stream(stream)))
+    tried = [{"leaf": res.tried_leaf[i], "m2l_pieces": res.tried_pieces[i], "ms": res.tried_ms[i],
+              "setup_ms": res.tried_setup_ms[i]} for i in range(res.n_tried)]
+    return {"leaf_size": res.leaf_size, "m2l_pieces": res.m2l_pieces, "ms": res.ms, "tried": tried}

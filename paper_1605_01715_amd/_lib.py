@@ -15,7 +15,7 @@ c_int, c_int64, c_float, c_double, c_void_p = (ctypes.c_int, ctypes.c_int64, cty
 FMM_OK, FMM_ERR_ARG, FMM_ERR_NOMEM, FMM_ERR_DEVICE, FMM_ERR_NOT_CONVERGED, FMM_ERR_STATE = range(6)
 FMM_SRC_SINGLE, FMM_SRC_DOUBLE = 1, 2
 FMM_OUT_POT, FMM_OUT_FIELD = 1, 2
-FMM_PREC_FP32, FMM_PREC_SPLIT_BF16 = 0, 1
+FMM_PREC_FP32, FMM_PREC_SPLIT_BF16, FMM_PREC_SPLIT_BF16X3, FMM_PREC_SPLIT_BF16X4 = 0, 1, 2, 3
 FMM_BASIS_SURFACE, FMM_BASIS_CHEBYSHEV = 0, 1
 FMM_OP_FK, FMM_OP_DIELECTRIC = 1, 2
 STAGES = ("P2M", "M2M", "P2L", "M2L", "L2L", "C2E", "EVAL")
@@ -36,7 +36,21 @@ class FmmInfo(ctypes.Structure):
     _fields_ = [(n, c_int64) for n in ("n_src", "n_trg", "n_points", "n_boxes", "n_leaves", "n_levels", "n_u", "n_v",
                                        "n_w", "n_x", "n_surface", "p2p_pairs", "m2l_pairs", "surf_evals",
                                        "p2m_evals", "m2l_columns", "rank", "m2l_pieces", "m2l_pair_tiles", "basis")] + [("root", c_double * 4),
-                                                                                 ("setup_ms", c_double)]
+                                                                                 ("setup_ms", c_double),
+                                                                                 ("leaf_size", c_int64),
+                                                                                 ("leaf_from_cache", c_int64),
+                                                                                 ("p2l_evals", c_int64)]
+
+
+class FmmTuneSpace(ctypes.Structure):
+    _fields_ = [("n_leaf", c_int), ("leaf_sizes", c_int * 8), ("n_pieces", c_int), ("pieces", c_int * 4),
+                ("reps", c_int)]
+
+
+class FmmTuneResult(ctypes.Structure):
+    _fields_ = [("leaf_size", c_int), ("m2l_pieces", c_int), ("ms", c_double), ("n_tried", c_int),
+                ("tried_leaf", c_int * 32), ("tried_pieces", c_int * 32), ("tried_ms", c_double * 32),
+                ("tried_setup_ms", c_double * 32)]
 
 
 class FmmTreeExport(ctypes.Structure):
@@ -72,6 +86,9 @@ SIGNATURES = {
     "fmm_export_stage": (c_int, [c_void_p, c_int, c_void_p]),
     "fmm_stage_times": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
     "fmm_pinv": (c_int, [c_void_p, c_int, c_double, c_void_p]),
+    "fmm_autotune": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_int64,
+                             ctypes.POINTER(FmmOptions), ctypes.POINTER(FmmTuneSpace), ctypes.c_char_p,
+                             ctypes.POINTER(FmmTuneResult), c_void_p]),
     "fmm_split_bf16": (c_int, [c_int, c_int, c_int64, c_void_p, c_void_p, c_void_p]),
     "fmm_unit_surface": (c_int, [c_int, c_void_p, ctypes.POINTER(c_int)]),
 }

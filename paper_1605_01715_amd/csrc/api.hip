@@ -96,12 +96,13 @@ void check_options(const fmm_options *opt) {
         FMM_REQUIRE(opt->order >= 2 && opt->order <= 8, "fmm_setup: Chebyshev order must be in 2..8");
     else
         FMM_REQUIRE(opt->order >= 2 && opt->order <= 10, "fmm_setup: order must be in 2..10");
-    FMM_REQUIRE(opt->leaf_size >= 1, "fmm_setup: leaf_size must be >= 1");
+    FMM_REQUIRE(opt->leaf_size >= 0, "fmm_setup: leaf_size must be >= 0 (0: from the tuning cache)");
     FMM_REQUIRE(opt->max_depth >= 1 && opt->max_depth <= kMaxLevel, "fmm_setup: max_depth must be in 1..21");
     FMM_REQUIRE(opt->uniform_depth >= 0 && opt->uniform_depth <= kMaxLevel,
                 "fmm_setup: uniform_depth must be in 0..21");
     FMM_REQUIRE(opt->nrhs >= 1 && opt->nrhs <= 4, "fmm_setup: nrhs must be in 1..4");
-    FMM_REQUIRE(opt->precision == FMM_PREC_FP32 || opt->precision == FMM_PREC_SPLIT_BF16,
+    FMM_REQUIRE(opt->precision == FMM_PREC_FP32 || opt->precision == FMM_PREC_SPLIT_BF16 ||
+                    opt->precision == FMM_PREC_SPLIT_BF16X3 || opt->precision == FMM_PREC_SPLIT_BF16X4,
                 "fmm_setup: unknown precision");
     FMM_REQUIRE((opt->src_kernels & ~3) == 0 && opt->src_kernels != 0,
                 "fmm_setup: src_kernels must be a nonzero FMM_SRC_* mask");
@@ -114,6 +115,26 @@ void check_options(const fmm_options *opt) {
                 "fmm_setup: root cube is not finite");
     FMM_REQUIRE(opt->pinv_eps >= 0.0 && std::isfinite(opt->pinv_eps), "fmm_setup: pinv_eps must be finite and >= 0");
     FMM_REQUIRE(opt->m2l_pieces >= 0 && opt->m2l_pieces <= 8, "fmm_setup: m2l_pieces must be in 0..8");
+}
+
+// leaf_size = 0: the tuned cap for this configuration from the cache, else
+// the default; the resolved options are returned (m2l_pieces from the cache
+// only when the caller left it at 0)
+fmm_options resolve_auto_leaf(const fmm_options *opt, int64_t points_per_instance, bool tsm, bool batch,
+                              int &from_cache) {
+    fmm_options o = *opt;
+    from_cache = 0;
+    if (o.leaf_size != 0) return o;
+    int leaf = 0, pieces = 0;
+    if (fmm::tune_cache_lookup(fmm::tune_cache_path(), fmm::tune_key(o, points_per_instance, tsm, batch), leaf,
+                               pieces)) {
+        o.leaf_size = leaf;
+        if (o.m2l_pieces == 0) o.m2l_pieces = pieces;
+        from_cache = 1;
+    } else {
+        o.leaf_size = fmm::kDefaultAutoLeaf;
+    }
+    return o;
 }
 
 fmm::TreeOptions tree_options(const fmm_options *opt) {
@@ -132,7 +153,10 @@ void init_plan(fmm::Plan &P, const fmm_options *opt) {
     P.dl = opt->src_kernels & FMM_SRC_DOUBLE;
     P.want_pot = opt->outputs & FMM_OUT_POT;
     P.want_field = opt->outputs & FMM_OUT_FIELD;
-    P.m2l_bf16 = opt->precision == FMM_PREC_SPLIT_BF16;
+    P.m2l_form = opt->precision == FMM_PREC_SPLIT_BF16     ? 6
+                 : opt->precision == FMM_PREC_SPLIT_BF16X4 ? 4
+                 : opt->precision == FMM_PREC_SPLIT_BF16X3 ? 3
+                                                           : 0;
 }
 
 // Everything after the tree: operators, per-box buffers, work lists.
@@ -149,7 +173,7 @@ void finish_plan(fmm::Plan &P, const fmm_options *opt, const float *trg_nrm, hip
     P.ut.alloc(nvec * P.r_pad);
     P.dt.alloc(nvec * P.r_pad);
     P.chk.alloc(nvec * P.n_pad);
-    if (P.m2l_bf16) P.ut_bf.alloc(m2l_split_vecs_elems(P.r_pad, (int64_t)nvec));
+    if (P.m2l_form) P.ut_bf.alloc(m2l_split_vecs_elems(P.r_pad, (int64_t)nvec, m2l_form_parts(P.m2l_form)));
     P.phi_u.alloc(nvec * P.n_pad);
     P.phi_d.alloc(nvec * P.n_pad);
     if (P.cheb) {
@@ -174,7 +198,7 @@ void finish_plan(fmm::Plan &P, const fmm_options *opt, const float *trg_nrm, hip
         FMM_HIP(hipMemcpyAsync(P.trg_nrm_user.p, trg_nrm, 3 * P.t.n_src * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
     if (P.t.nb) plan_build_worklists(P, s);
-    if (P.cheb) plan_create_side(P);
+    if (P.t.nb) plan_create_side(P);
     FMM_HIP(hipStreamSynchronize(s));
 }
 
@@ -197,11 +221,16 @@ int fmm_setup(const float *src_xyz, const float *src_nrm, int64_t n_src, const f
 
         auto t0 = std::chrono::steady_clock::now();
         hipStream_t s = as_stream(hip_stream);
+        int from_cache = 0;
+        const fmm_options ro = resolve_auto_leaf(opt, n_src + (trg_xyz ? n_trg : 0), trg_xyz != nullptr, false,
+                                                 from_cache);
+        opt = &ro;
         auto *h = new fmm_plan_s();
         h->p.reset(new Plan());
         try {
             Plan &P = *h->p;
             init_plan(P, opt);
+            P.leaf_from_cache = from_cache;
             build_tree(P.t, src_xyz, src_nrm, n_src, trg_xyz, trg_nrm, n_trg, tree_options(opt), s);
             finish_plan(P, opt, trg_nrm, s);
             P.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -242,11 +271,15 @@ int fmm_setup_batch(int n_inst, const int64_t *src_off, const int64_t *trg_off, 
 
         auto t0 = std::chrono::steady_clock::now();
         hipStream_t s = as_stream(hip_stream);
+        int from_cache = 0;
+        const fmm_options ro = resolve_auto_leaf(opt, (n_src + (tsm ? n_trg : 0)) / n_inst, tsm, true, from_cache);
+        opt = &ro;
         auto *h = new fmm_plan_s();
         h->p.reset(new Plan());
         try {
             Plan &P = *h->p;
             init_plan(P, opt);
+            P.leaf_from_cache = from_cache;
             const TreeOptions topt = tree_options(opt);
             std::vector<Tree> parts(n_inst);
             for (int i = 0; i < n_inst; ++i) {
@@ -436,6 +469,9 @@ int fmm_plan_info(fmm_plan plan, fmm_info *info) {
         for (int c = 0; c < 3; ++c) r.root[c] = P.t.x0[c];
         r.root[3] = P.t.w;
         r.setup_ms = P.setup_ms;
+        r.leaf_size = P.opt.leaf_size;
+        r.leaf_from_cache = P.leaf_from_cache;
+        r.p2l_evals = P.p2l_evals;
         *info = r;
     });
 }
@@ -503,6 +539,107 @@ int fmm_export_stage(fmm_plan plan, int which, float *host_out) {
                 host_out[box * P.ns + m] = (float)v;
             }
         }
+    });
+}
+
+int fmm_autotune(int n_inst, const int64_t *src_off, const int64_t *trg_off, const float *src_xyz,
+                 const float *src_nrm, int64_t n_src, const float *trg_xyz, const float *trg_nrm, int64_t n_trg,
+                 const fmm_options *opt, const fmm_tune_space *space, const char *cache_path, fmm_tune_result *out,
+                 void *hip_stream) {
+    return guarded([&] {
+        using namespace fmm;
+        FMM_REQUIRE(opt && space && out, "fmm_autotune: NULL argument");
+        FMM_REQUIRE(n_inst >= 0, "fmm_autotune: n_inst must be >= 0");
+        FMM_REQUIRE(n_inst == 0 || src_off != nullptr, "fmm_autotune: a batch needs src_off");
+        FMM_REQUIRE(space->n_leaf >= 1 && space->n_leaf <= 8, "fmm_autotune: n_leaf must be in 1..8");
+        FMM_REQUIRE(space->n_pieces >= 0 && space->n_pieces <= 4, "fmm_autotune: n_pieces must be in 0..4");
+        FMM_REQUIRE(space->reps >= 1 && space->reps <= 100, "fmm_autotune: reps must be in 1..100");
+        for (int i = 0; i < space->n_leaf; ++i)
+            FMM_REQUIRE(space->leaf_sizes[i] >= 1, "fmm_autotune: leaf sizes must be >= 1");
+        for (int i = 0; i < space->n_pieces; ++i)
+            FMM_REQUIRE(space->pieces[i] >= 0 && space->pieces[i] <= 8, "fmm_autotune: pieces must be in 0..8");
+        check_options(opt);
+        const bool batch = n_inst > 0;
+        const bool tsm = batch ? trg_off != nullptr : trg_xyz != nullptr;
+        const int64_t ns_all = batch ? src_off[n_inst] : n_src;
+        const int64_t nt_all = batch ? (tsm ? trg_off[n_inst] : ns_all) : (tsm ? n_trg : n_src);
+        FMM_REQUIRE(ns_all >= 1, "fmm_autotune: no sources");
+        const int64_t ppi = batch ? (ns_all + (tsm ? nt_all : 0)) / n_inst : ns_all + (tsm ? nt_all : 0);
+        hipStream_t s = as_stream(hip_stream);
+        const int nrhs = opt->nrhs;
+        DBuf<float> q, mu, pot, fld;
+        if (opt->src_kernels & FMM_SRC_SINGLE) {
+            q.alloc((size_t)nrhs * ns_all);
+            fill_random(q.p, (int64_t)q.n, 1u, s);
+        }
+        if (opt->src_kernels & FMM_SRC_DOUBLE) {
+            mu.alloc((size_t)nrhs * ns_all);
+            fill_random(mu.p, (int64_t)mu.n, 2u, s);
+        }
+        if (opt->outputs & FMM_OUT_POT) pot.alloc((size_t)nrhs * nt_all);
+        else fld.alloc((size_t)3 * nrhs * nt_all);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        FMM_HIP(hipEventCreate(&e0));
+        FMM_HIP(hipEventCreate(&e1));
+        fmm_tune_result res{};
+        double best = 1e300;
+        try {
+            const int np = space->n_pieces > 0 ? space->n_pieces : 1;
+            for (int il = 0; il < space->n_leaf; ++il) {
+                for (int ip = 0; ip < np; ++ip) {
+                    fmm_options o = *opt;
+                    o.leaf_size = space->leaf_sizes[il];
+                    o.m2l_pieces = space->n_pieces > 0 ? space->pieces[ip] : opt->m2l_pieces;
+                    fmm_plan plan = nullptr;
+                    int rc = batch ? fmm_setup_batch(n_inst, src_off, trg_off, src_xyz, src_nrm, trg_xyz, trg_nrm, &o,
+                                                     hip_stream, &plan)
+                                   : fmm_setup(src_xyz, src_nrm, n_src, trg_xyz, trg_nrm, n_trg, &o, hip_stream,
+                                               &plan);
+                    if (rc != FMM_OK) throw Error(rc, std::string("fmm_autotune: ") + fmm_last_error());
+                    fmm_info info{};
+                    fmm_plan_info(plan, &info);
+                    std::vector<float> times;
+                    for (int k = 0; k <= space->reps && rc == FMM_OK; ++k) {  // one warm-up apply first
+                        FMM_HIP(hipEventRecord(e0, s));
+                        rc = fmm_apply(plan, q.p, mu.p, pot.p, fld.p, hip_stream);
+                        FMM_HIP(hipEventRecord(e1, s));
+                        FMM_HIP(hipEventSynchronize(e1));
+                        float ms = 0.f;
+                        FMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        if (k > 0) times.push_back(ms);
+                    }
+                    const std::string msg = rc == FMM_OK ? "" : fmm_last_error();
+                    fmm_destroy(plan);
+                    if (rc != FMM_OK) throw Error(rc, "fmm_autotune: " + msg);
+                    std::sort(times.begin(), times.end());
+                    const double med = times[times.size() / 2];
+                    if (res.n_tried < 32) {
+                        res.tried_leaf[res.n_tried] = o.leaf_size;
+                        res.tried_pieces[res.n_tried] = (int)info.m2l_pieces;
+                        res.tried_ms[res.n_tried] = med;
+                        res.tried_setup_ms[res.n_tried] = info.setup_ms;
+                        ++res.n_tried;
+                    }
+                    if (med < best) {
+                        best = med;
+                        res.leaf_size = o.leaf_size;
+                        res.m2l_pieces = (int)info.m2l_pieces;
+                        res.ms = med;
+                    }
+                }
+            }
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (cache_path) {
+            const std::string path = cache_path[0] ? std::string(cache_path) : tune_cache_path();
+            tune_cache_store(path, tune_key(*opt, ppi, tsm, batch), res.leaf_size, res.m2l_pieces, res.ms);
+        }
+        *out = res;
     });
 }
 

@@ -29,14 +29,18 @@
 // Forms:
 //   FP32        v_mfma_f32_32x32x2_f32; the float32 matrices are stored chunk
 //               by chunk in fragment order (the exact LDS image).
-//   split-BF16  both operands split into three bfloat16 parts x = h + m + l;
-//               the six products hh hm mh mm hl lh are accumulated in float32
-//               with v_mfma_f32_32x32x16_bf16 (the bf16x6 scheme of Henry,
-//               Tang and Heinecke, 2019). The split is done once, outside the
-//               inner loop: the matrices when the operators are built (stored
-//               chunk by chunk in the exact LDS image), the source vectors by
-//               one pass over the upward state per apply. The inner loop is
-//               then only copies and MFMAs.
+//   split-BF16  both operands split into bfloat16 parts and the part products
+//               accumulated in float32 with v_mfma_f32_32x32x16_bf16 (the
+//               schemes of Henry, Tang and Heinecke, 2019): three parts
+//               x = h + m + l and the six products hh hm mh mm hl lh (bf16x6,
+//               about float32 accuracy), or two parts x = h + m and the
+//               products hh hm mh (bf16x3), optionally with mm (bf16x4), with
+//               two thirds of the bytes and half (or two thirds) of the MFMAs.
+//               The split is done once, outside the inner loop: the matrices
+//               when the operators are built (stored chunk by chunk in the
+//               exact LDS image), the source vectors by one pass over the
+//               upward state per apply. The inner loop is then only copies
+//               and MFMAs.
 #include <type_traits>
 
 #include "m2l.hpp"
@@ -61,7 +65,8 @@ __device__ inline uint16_t f2bf(float x) {
     return (uint16_t)(u >> 16);
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-// x = h + m + l up to 2^-24 |x| (each residual is exact in float32)
+// x = h + m + l up to 2^-24 |x| (each residual is exact in float32); the
+// two-part split is h and m (x = h + m up to 2^-16 |x|)
 __device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
     h = f2bf(x);
     float r1 = x - bf2f(h);
@@ -70,13 +75,16 @@ __device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
 }
 
 // One A chunk (r_pad rows x 32 k) in LDS and in the global image, fragment order:
-//   BF16 (32x32x16): part p, row block rb, k-half h (16 k each), lane, 8 slots;
+//   BF16 (32x32x16): part p (of NP = 3 or 2), row block rb, k-half h (16 k each), lane, 8 slots;
 //                    element (row, k) -> lane = row % 32 + 32 * ((k % 16) / 8), slot = k % 8
 //   FP32 (32x32x2):  row block rb, lane, 16 slots;
 //                    element (row, k) -> lane = row % 32 + 32 * (k / 16), slot = k % 16
-// Split-BF16 source vector layout: per vector, per 32-k chunk, 3 parts of 32
-// bfloat16 (192 bytes); float32 vectors are plain rows of r_pad values.
-__host__ __device__ constexpr int64_t vec_bf_stride(int r_pad) { return 3 * (int64_t)r_pad; }
+// Split-BF16 source vector layout: per vector, per 32-k chunk, NP parts of 32
+// bfloat16 (64 NP bytes); float32 vectors are plain rows of r_pad values.
+__host__ __device__ constexpr int64_t vec_bf_stride(int r_pad, int np) { return np * (int64_t)r_pad; }
+
+// M2L arithmetic: 0 float32; 6, 4, 3 the split-BF16 products (parts: 3, 2, 2)
+__host__ __device__ constexpr int form_parts(int form) { return form == 6 ? 3 : 2; }
 
 // XCD-aware tile order: blocks are dealt to the 8 XCDs round-robin, so
 // block b runs on XCD b % 8. XCD x receives cnt(x) blocks and owns tiles
@@ -106,14 +114,16 @@ __device__ inline void copy_to_lds(const void *src, void *dst) {
 // barriers. Either way every wave reads the matrix chunk rows it multiplies
 // (4 reads of the chunk per step); with 4 waves the source chunk is read
 // once per column block instead of twice (one row half each).
-template <int NRB, bool BF16, int NW>
+template <int NRB, int FORM, int NW>
 struct Shape {
     static_assert(NW == 8 || NW == 4, "8 or 4 waves");
+    static constexpr bool BF16 = FORM != 0;
+    static constexpr int NP = form_parts(FORM);                // bfloat16 parts per value
     static constexpr int RP = NRB * 32;
     static constexpr int RBH = NW == 8 ? (NRB + 1) / 2 : NRB;  // row blocks per wave
-    static constexpr int CHUNK = BF16 ? NRB * 32 * KC * 2 * 3 : NRB * 32 * KC * 4;  // A chunk bytes
+    static constexpr int CHUNK = BF16 ? NRB * 32 * KC * 2 * NP : NRB * 32 * KC * 4;  // A chunk bytes
     static constexpr int NIA = CHUNK / 1024;                   // 1 KB copies per A chunk
-    static constexpr int PPC = BF16 ? 12 : 8;                  // 16-byte pieces per column chunk
+    static constexpr int PPC = BF16 ? 4 * NP : 8;              // 16-byte pieces per column chunk
     static constexpr int SPC = PPC + 1;                        // LDS slots per column (one pad slot)
     static constexpr int BSTR = SPC * 16;                      // column stride in LDS: 16 lanes hit distinct banks
     static constexpr int BCH = kCols * BSTR;                   // B chunk bytes in LDS
@@ -128,9 +138,11 @@ struct Shape {
     static_assert(kCols * SPC % 64 == 0, "B slots must fill whole copies");
 };
 
-template <int NRB, bool BF16, int NW>
+template <int NRB, int FORM, int NW>
 __global__ __launch_bounds__(NW * 64, 2) void k_m2l(M2LLaunch a) {
-    using S = Shape<NRB, BF16, NW>;
+    using S = Shape<NRB, FORM, NW>;
+    constexpr bool BF16 = S::BF16;
+    constexpr int NP = S::NP;
     constexpr int kThreads = NW * 64;
     constexpr int RP = S::RP, RBH = S::RBH, CHUNK = S::CHUNK, NIA = S::NIA, PPC = S::PPC, SPC = S::SPC,
                   BSTR = S::BSTR, BCH = S::BCH, NIB = S::NIB, JA = S::JA, JB = S::JB, NBUF = S::NBUF;
@@ -192,7 +204,7 @@ __global__ __launch_bounds__(NW * 64, 2) void k_m2l(M2LLaunch a) {
         constexpr int BUF = decltype(buf_tag)::value;
         const int dir = __builtin_amdgcn_readfirstlane(s_dir[min(e_ld, nact - 1)]);
         const int kc = st_ld;
-        const unsigned char *ag = BF16 ? (const unsigned char *)(a.mats_bf + ((int64_t)dir * NGR + kc) * 3 * PART)
+        const unsigned char *ag = BF16 ? (const unsigned char *)(a.mats_bf + ((int64_t)dir * NGR + kc) * NP * PART)
                                        : (const unsigned char *)(a.mats + ((int64_t)dir * NGR + kc) * (CHUNK / 4));
 #pragma unroll
         for (int j = 0; j < JA; ++j) {
@@ -209,7 +221,7 @@ __global__ __launch_bounds__(NW * 64, 2) void k_m2l(M2LLaunch a) {
             if (cur_sv[j] < 0 || pc == PPC)
                 src = (const unsigned char *)a.zero + 16 * (pc % PPC);
             else if (BF16)
-                src = (const unsigned char *)(a.in_bf + cur_sv[j] * vec_bf_stride(RP) + kc * 3 * KC + 8 * pc);
+                src = (const unsigned char *)(a.in_bf + cur_sv[j] * vec_bf_stride(RP, NP) + kc * NP * KC + 8 * pc);
             else
                 src = (const unsigned char *)(a.in + (size_t)cur_sv[j] * RP + kc * KC + 4 * pc);
             copy_to_lds(src, &sB[BUF][i * 1024]);
@@ -231,14 +243,14 @@ __global__ __launch_bounds__(NW * 64, 2) void k_m2l(M2LLaunch a) {
     // objects, so the compiler can tell that reads of one do not wait for
     // copies into the other: the next step's copies are issued first and
     // the fragments are read one row block at a time under the MFMAs.
-    constexpr int NFA = BF16 ? 6 : 4;  // 16-byte A fragments per row block
-    constexpr int NFB = BF16 ? 6 : 4;
+    constexpr int NFA = BF16 ? 2 * NP : 4;  // 16-byte A fragments per row block
+    constexpr int NFB = BF16 ? 2 * NP : 4;
     u32x4 fa[NFA], fb[NFB];
     auto read_b = [&](int buf) {
         const unsigned char *bb = sB[buf] + my_col * BSTR;
 #pragma unroll
         for (int f = 0; f < NFB; ++f)
-            fb[f] = BF16 ? *(const u32x4 *)(bb + (f % 3) * 64 + 32 * (f / 3) + 16 * hf)  // part f % 3, k-half f / 3
+            fb[f] = BF16 ? *(const u32x4 *)(bb + (f % NP) * 64 + 32 * (f / NP) + 16 * hf)  // part f % NP, k-half f / NP
                          : *(const u32x4 *)(bb + 64 * hf + 16 * f);
     };
     auto read_a = [&](int buf, int rb, u32x4 (&fr)[NFA]) {
@@ -246,7 +258,7 @@ __global__ __launch_bounds__(NW * 64, 2) void k_m2l(M2LLaunch a) {
             const uint16_t *p = (const uint16_t *)sA[buf];
 #pragma unroll
             for (int f = 0; f < NFA; ++f)
-                fr[f] = *(const u32x4 *)(p + (f % 3) * PART + ((rb * 2 + f / 3) * 64 + lane) * 8);
+                fr[f] = *(const u32x4 *)(p + (f % NP) * PART + ((rb * 2 + f / NP) * 64 + lane) * 8);
         } else {
             const float *p = (const float *)sA[buf];
 #pragma unroll
@@ -259,13 +271,16 @@ __global__ __launch_bounds__(NW * 64, 2) void k_m2l(M2LLaunch a) {
         if (BF16) {
 #pragma unroll
             for (int h2 = 0; h2 < 2; ++h2) {
-                const bf16x8 ah = __builtin_bit_cast(bf16x8, fr[3 * h2]), am = __builtin_bit_cast(bf16x8, fr[3 * h2 + 1]),
-                             al = __builtin_bit_cast(bf16x8, fr[3 * h2 + 2]);
-                const bf16x8 bh = __builtin_bit_cast(bf16x8, fb[3 * h2]), bm = __builtin_bit_cast(bf16x8, fb[3 * h2 + 1]),
-                             bl = __builtin_bit_cast(bf16x8, fb[3 * h2 + 2]);
-                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, c, 0, 0, 0);
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, fr[NP * h2]), am = __builtin_bit_cast(bf16x8, fr[NP * h2 + 1]);
+                const bf16x8 bh = __builtin_bit_cast(bf16x8, fb[NP * h2]), bm = __builtin_bit_cast(bf16x8, fb[NP * h2 + 1]);
+                // smallest products first
+                if constexpr (NP == 3) {
+                    const bf16x8 al = __builtin_bit_cast(bf16x8, fr[NP * h2 + 2]);
+                    const bf16x8 bl = __builtin_bit_cast(bf16x8, fb[NP * h2 + 2]);
+                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, c, 0, 0, 0);
+                }
+                if constexpr (FORM != 3) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, c, 0, 0, 0);
                 c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, c, 0, 0, 0);
                 c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, c, 0, 0, 0);
                 c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, c, 0, 0, 0);
@@ -416,13 +431,14 @@ __global__ __launch_bounds__(256) void k_m2l_gather(int r_pad, int n, const int3
     }
 }
 
-// Matrices [ndir][r_pad][r_pad] float32 -> split-BF16 chunks in LDS image order.
-__global__ void k_split_mats(const float *rm, int r_pad, int64_t total, uint16_t *out) {
+// Matrices [ndir][r_pad][r_pad] float32 -> split-BF16 chunks (np = 3 or 2
+// parts) in LDS image order.
+__global__ void k_split_mats(const float *rm, int r_pad, int np, int64_t total, uint16_t *out) {
     int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;  // total = ndir * r_pad * r_pad
     const int nrb = r_pad / 32, nkc = r_pad / KC;
     const int64_t part_sz = (int64_t)nrb * 2 * 64 * 8;
-    // idx enumerates (dir, kc, rb, h2, lane, slot); each thread writes all three parts
+    // idx enumerates (dir, kc, rb, h2, lane, slot); each thread writes all parts
     const int slot = (int)(idx % 8);
     int64_t r = idx / 8;
     const int ln = (int)(r % 64);
@@ -437,34 +453,34 @@ __global__ void k_split_mats(const float *rm, int r_pad, int64_t total, uint16_t
     const int k = kc * KC + 16 * h2 + 8 * (ln >> 5) + slot;
     uint16_t h, m, l;
     split3(rm[(dir * r_pad + row) * r_pad + k], h, m, l);
-    uint16_t *o = out + (dir * nkc + kc) * 3 * part_sz + ((int64_t)(rb * 2 + h2) * 64 + ln) * 8 + slot;
+    uint16_t *o = out + (dir * nkc + kc) * np * part_sz + ((int64_t)(rb * 2 + h2) * 64 + ln) * 8 + slot;
     o[0] = h;
     o[part_sz] = m;
-    o[2 * part_sz] = l;
+    if (np == 3) o[2 * part_sz] = l;
 }
 
-__global__ void k_split_vecs(const float *in, int r_pad, int64_t total, uint16_t *out) {
+__global__ void k_split_vecs(const float *in, int r_pad, int np, int64_t total, uint16_t *out) {
     int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;  // total = nvec * r_pad
     const int64_t v = idx / r_pad;
     const int k = (int)(idx % r_pad), kc = k / KC, kk = k % KC;
     uint16_t h, m, l;
     split3(in[idx], h, m, l);
-    uint16_t *o = out + v * vec_bf_stride(r_pad) + kc * 3 * KC + kk;
+    uint16_t *o = out + v * vec_bf_stride(r_pad, np) + kc * np * KC + kk;
     o[0] = h;
     o[KC] = m;
-    o[2 * KC] = l;
+    if (np == 3) o[2 * KC] = l;
 }
 
-// Inverse maps of the two split layouts, for inspection: parts[p][i] is part
-// p of the i-th value in row-major order (vectors of r_pad values, or
-// r_pad x r_pad matrices).
+// Inverse maps of the two split layouts (three parts), for inspection:
+// parts[p][i] is part p of the i-th value in row-major order (vectors of
+// r_pad values, or r_pad x r_pad matrices).
 __global__ void k_unsplit_vecs(const uint16_t *img, int r_pad, int64_t total, uint16_t *parts) {
     int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
     const int64_t v = idx / r_pad;
     const int k = (int)(idx % r_pad), kc = k / KC, kk = k % KC;
-    const uint16_t *src = img + v * vec_bf_stride(r_pad) + kc * 3 * KC + kk;
+    const uint16_t *src = img + v * vec_bf_stride(r_pad, 3) + kc * 3 * KC + kk;
     for (int p = 0; p < 3; ++p) parts[p * total + idx] = src[p * KC];
 }
 
@@ -502,40 +518,40 @@ __global__ void k_image_f32(const float *rm, int r_pad, int64_t total, float *ou
 
 // waves per workgroup: 4 for split-BF16 states up to 192 values (the
 // accumulators of every row block fit beside a second workgroup), else 8
-template <int NRB, bool BF16>
+template <int NRB, int FORM>
 constexpr int waves_for() {
-    return (BF16 && NRB <= 6) ? 4 : 8;
+    return (FORM != 0 && NRB <= 6) ? 4 : 8;
 }
 
-template <int NRB, bool BF16>
+template <int NRB, int FORM>
 void launch(const M2LLaunch &a, hipStream_t s) {
-    constexpr int NW = waves_for<NRB, BF16>();
-    using S = Shape<NRB, BF16, NW>;
+    constexpr int NW = waves_for<NRB, FORM>();
+    using S = Shape<NRB, FORM, NW>;
     static_assert(S::NBUF == 2 || S::LDS2 / 2 <= 160 * 1024, "chunks do not fit in LDS");
-    hipLaunchKernelGGL((k_m2l<NRB, BF16, NW>), dim3(a.ntile), dim3(NW * 64), 0, s, a);
+    hipLaunchKernelGGL((k_m2l<NRB, FORM, NW>), dim3(a.ntile), dim3(NW * 64), 0, s, a);
     FMM_HIP(hipGetLastError());
 }
 
-template <bool BF16, int NRB = 1>
+template <int FORM, int NRB = 1>
 int blocks_per_cu(int nrb) {
     if constexpr (NRB <= 16) {
-        if (nrb != NRB) return blocks_per_cu<BF16, NRB + 1>(nrb);
+        if (nrb != NRB) return blocks_per_cu<FORM, NRB + 1>(nrb);
         int n = 0;
-        constexpr int NW = waves_for<NRB, BF16>();
-        FMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_m2l<NRB, BF16, NW>, NW * 64, 0));
+        constexpr int NW = waves_for<NRB, FORM>();
+        FMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_m2l<NRB, FORM, NW>, NW * 64, 0));
         return n > 0 ? n : 1;
     } else {
         return 1;
     }
 }
 
-template <bool BF16, int NRB = 1>
+template <int FORM, int NRB = 1>
 void dispatch(int nrb, const M2LLaunch &a, hipStream_t s) {
     if constexpr (NRB <= 16) {
         if (nrb == NRB)
-            launch<NRB, BF16>(a, s);
+            launch<NRB, FORM>(a, s);
         else
-            dispatch<BF16, NRB + 1>(nrb, a, s);
+            dispatch<FORM, NRB + 1>(nrb, a, s);
     } else {
         throw Error(FMM_ERR_ARG, "m2l: unsupported state size");
     }
@@ -550,14 +566,16 @@ int m2l_ncol(int r_pad) {
 
 bool m2l_supported(int r_pad) { return r_pad > 0 && r_pad % 32 == 0 && r_pad <= 512; }
 
-size_t m2l_split_mats_elems(int r_pad, int ndir) { return (size_t)ndir * 3 * r_pad * r_pad; }
-size_t m2l_split_vecs_elems(int r_pad, int64_t nvec) { return (size_t)nvec * vec_bf_stride(r_pad); }
+int m2l_form_parts(int form) { return form_parts(form); }
+size_t m2l_split_mats_elems(int r_pad, int ndir, int np) { return (size_t)ndir * np * r_pad * r_pad; }
+size_t m2l_split_vecs_elems(int r_pad, int64_t nvec, int np) { return (size_t)nvec * vec_bf_stride(r_pad, np); }
 
-void m2l_split_mats(const float *rm, int r_pad, int ndir, uint16_t *out, hipStream_t s) {
+void m2l_split_mats(const float *rm, int r_pad, int ndir, int np, uint16_t *out, hipStream_t s) {
     FMM_REQUIRE(m2l_supported(r_pad), "m2l: unsupported state size");
+    FMM_REQUIRE(np == 2 || np == 3, "m2l: 2 or 3 bfloat16 parts");
     const int64_t total = (int64_t)ndir * r_pad * r_pad;
     if (total == 0) return;
-    hipLaunchKernelGGL(k_split_mats, dim3(grid_for(total, 256)), dim3(256), 0, s, rm, r_pad, total, out);
+    hipLaunchKernelGGL(k_split_mats, dim3(grid_for(total, 256)), dim3(256), 0, s, rm, r_pad, np, total, out);
     FMM_HIP(hipGetLastError());
 }
 
@@ -569,10 +587,11 @@ void m2l_image_mats(const float *rm, int r_pad, int ndir, float *out, hipStream_
     FMM_HIP(hipGetLastError());
 }
 
-void m2l_split_vecs(const float *in, int r_pad, int64_t nvec, uint16_t *out, hipStream_t s) {
+void m2l_split_vecs(const float *in, int r_pad, int64_t nvec, int np, uint16_t *out, hipStream_t s) {
+    FMM_REQUIRE(np == 2 || np == 3, "m2l: 2 or 3 bfloat16 parts");
     const int64_t total = nvec * r_pad;
     if (total == 0) return;
-    hipLaunchKernelGGL(k_split_vecs, dim3(grid_for(total, 256)), dim3(256), 0, s, in, r_pad, total, out);
+    hipLaunchKernelGGL(k_split_vecs, dim3(grid_for(total, 256)), dim3(256), 0, s, in, r_pad, np, total, out);
     FMM_HIP(hipGetLastError());
 }
 
@@ -582,19 +601,25 @@ void m2l_split_plain(int which, int r_pad, int64_t count, const float *in, uint1
     const int64_t total = count * r_pad * (which == 1 ? r_pad : 1);
     DBuf<uint16_t> img(3 * (size_t)total);
     if (which == 1) {
-        m2l_split_mats(in, r_pad, (int)count, img.p, s);
+        m2l_split_mats(in, r_pad, (int)count, 3, img.p, s);
         hipLaunchKernelGGL(k_unsplit_mats, dim3(grid_for(total, 256)), dim3(256), 0, s, img.p, r_pad, total, parts);
     } else {
-        m2l_split_vecs(in, r_pad, count, img.p, s);
+        m2l_split_vecs(in, r_pad, count, 3, img.p, s);
         hipLaunchKernelGGL(k_unsplit_vecs, dim3(grid_for(total, 256)), dim3(256), 0, s, img.p, r_pad, total, parts);
     }
     FMM_HIP(hipGetLastError());
     FMM_HIP(hipStreamSynchronize(s));
 }
 
-int m2l_blocks_per_cu(bool bf16, int r_pad) {
+int m2l_blocks_per_cu(int form, int r_pad) {
     FMM_REQUIRE(m2l_supported(r_pad), "m2l: unsupported state size");
-    return bf16 ? blocks_per_cu<true>(r_pad / 32) : blocks_per_cu<false>(r_pad / 32);
+    switch (form) {
+    case 0: return blocks_per_cu<0>(r_pad / 32);
+    case 3: return blocks_per_cu<3>(r_pad / 32);
+    case 4: return blocks_per_cu<4>(r_pad / 32);
+    case 6: return blocks_per_cu<6>(r_pad / 32);
+    default: throw Error(FMM_ERR_ARG, "m2l: unknown arithmetic");
+    }
 }
 
 void m2l_reduce(int r_pad, int ntile, int ncol, const int32_t *cols, const int32_t *slot0, const int32_t *kpieces,
@@ -614,16 +639,19 @@ void m2l_gather(int r_pad, int n, const int32_t *targets, const int32_t *off, co
     FMM_HIP(hipGetLastError());
 }
 
-void m2l_run(bool bf16, const M2LLaunch &a, hipStream_t s) {
+void m2l_run(int form, const M2LLaunch &a, hipStream_t s) {
     if (a.ntile <= 0) return;
     FMM_REQUIRE(m2l_supported(a.r_pad), "m2l: unsupported state size");
     FMM_REQUIRE(a.ncol == m2l_ncol(a.r_pad), "m2l: tile width mismatch");
-    FMM_REQUIRE(bf16 ? (a.mats_bf && a.in_bf) : (a.mats && a.in), "m2l: operands missing for this form");
+    FMM_REQUIRE(form ? (a.mats_bf && a.in_bf) : (a.mats && a.in), "m2l: operands missing for this form");
     FMM_REQUIRE(a.zero, "m2l: zero source chunk missing");
-    if (bf16)
-        dispatch<true>(a.r_pad / 32, a, s);
-    else
-        dispatch<false>(a.r_pad / 32, a, s);
+    switch (form) {
+    case 0: dispatch<0>(a.r_pad / 32, a, s); break;
+    case 3: dispatch<3>(a.r_pad / 32, a, s); break;
+    case 4: dispatch<4>(a.r_pad / 32, a, s); break;
+    case 6: dispatch<6>(a.r_pad / 32, a, s); break;
+    default: throw Error(FMM_ERR_ARG, "m2l: unknown arithmetic");
+    }
 }
 
 }  // namespace fmm

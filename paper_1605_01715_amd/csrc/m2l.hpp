@@ -33,7 +33,10 @@ struct M2LLaunch {
 };
 
 int m2l_ncol(int r_pad);
-int m2l_blocks_per_cu(bool bf16, int r_pad);  // workgroups of the kernel that fit on one CU
+// M2L arithmetic ("form"): 0 float32; 6, 4 or 3 the split-BF16 part products
+// (bf16x6 of three parts; bf16x4 and bf16x3 of two parts)
+int m2l_form_parts(int form);                  // bfloat16 parts per value of a split form
+int m2l_blocks_per_cu(int form, int r_pad);    // workgroups of the kernel that fit on one CU
 // cut tiles: out[cols[t][c]] += sum over q < kpieces[t] of partial[slot0[t] + q][c] (q in order)
 void m2l_reduce(int r_pad, int ntile, int ncol, const int32_t *cols, const int32_t *slot0, const int32_t *kpieces,
                 const float *partial, float *out, hipStream_t s);
@@ -41,16 +44,16 @@ void m2l_reduce(int r_pad, int ntile, int ncol, const int32_t *cols, const int32
 void m2l_gather(int r_pad, int n, const int32_t *targets, const int32_t *off, const int32_t *rows,
                 const float *partial, float *out, hipStream_t s);
 bool m2l_supported(int r_pad);  // any multiple of 32 up to 512
-void m2l_run(bool bf16, const M2LLaunch &a, hipStream_t s);
+void m2l_run(int form, const M2LLaunch &a, hipStream_t s);
 
 // FP32 operands: row-major [ndir][r_pad][r_pad] -> the kernel's chunk order.
 void m2l_image_mats(const float *rm, int r_pad, int ndir, float *out, hipStream_t s);
-// Split-BF16 operands: each float32 value becomes three bfloat16 parts.
-size_t m2l_split_mats_elems(int r_pad, int ndir);    // uint16 elements of the split matrices
-size_t m2l_split_vecs_elems(int r_pad, int64_t nvec);
-void m2l_split_mats(const float *rm, int r_pad, int ndir, uint16_t *out, hipStream_t s);
-void m2l_split_vecs(const float *in, int r_pad, int64_t nvec, uint16_t *out, hipStream_t s);
-// The same splits written out plainly: parts[p][i], p = 0..2, of the values in
+// Split-BF16 operands: each float32 value becomes np = 3 or 2 bfloat16 parts.
+size_t m2l_split_mats_elems(int r_pad, int ndir, int np);    // uint16 elements of the split matrices
+size_t m2l_split_vecs_elems(int r_pad, int64_t nvec, int np);
+void m2l_split_mats(const float *rm, int r_pad, int ndir, int np, uint16_t *out, hipStream_t s);
+void m2l_split_vecs(const float *in, int r_pad, int64_t nvec, int np, uint16_t *out, hipStream_t s);
+// The three-part splits written out plainly: parts[p][i], p = 0..2, of the values in
 // row-major order (which = 0: count vectors of r_pad; which = 1: count
 // r_pad x r_pad matrices). Synchronises the stream.
 void m2l_split_plain(int which, int r_pad, int64_t count, const float *in, uint16_t *parts, hipStream_t s);

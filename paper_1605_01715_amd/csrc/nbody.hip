@@ -206,6 +206,7 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
     // surfaces: L2P (own downward equivalent density) and M2P (W-list boxes);
     // surface points never coincide with targets (they lie outside the box)
     for (int e = a.soff[leaf]; e < a.soff[leaf + 1]; ++e) {
+        if (!(a.surf_mask & (1 << a.skind[e]))) continue;  // the same for every lane
         const int box = a.sbox[e];
         const bool down = a.skind[e] == 0;
         const double rr = (down ? a.rad_down : a.rad_up) * g.half[box];
@@ -349,9 +350,11 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
             __syncthreads();
         }
     };
-    const int pmid = a.pmid ? a.pmid[leaf] : a.poff[leaf + 1];
-    for (int e = a.poff[leaf]; e < pmid; ++e) range(std::true_type{}, e);
-    for (int e = pmid; e < a.poff[leaf + 1]; ++e) range(std::false_type{}, e);
+    if (a.points) {
+        const int pmid = a.pmid ? a.pmid[leaf] : a.poff[leaf + 1];
+        for (int e = a.poff[leaf]; e < pmid; ++e) range(std::true_type{}, e);
+        for (int e = pmid; e < a.poff[leaf + 1]; ++e) range(std::false_type{}, e);
+    }
 
     // sum the slices of each target through LDS, then slice 0 writes
     constexpr int NV = TPL * NRHS * NOUT;

@@ -54,6 +54,8 @@ struct EvalArgs {
     float delta2 = 0.f;
     float *pot = nullptr, *field = nullptr;
     int accumulate = 0;
+    int surf_mask = 3;  // surface kinds evaluated: bit 0 kind 0 (phi_d), bit 1 kind 1 (phi_u)
+    int points = 1;     // 0: skip the point ranges (surfaces only)
 };
 void eval_leaves(int nrhs, bool sl, bool dl, const EvalArgs &a, const SurfaceGeom &g, const PointSrc &src,
                  hipStream_t s);

@@ -259,8 +259,10 @@ std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
         build(pm2l, dPV, dVrSi, nullptr, &rm);
         op->m2l_f32.alloc(rr * kNumDirs);
         m2l_image_mats(rm.p, rp, kNumDirs, op->m2l_f32.p, s);
-        op->m2l_bf.alloc(m2l_split_mats_elems(rp, kNumDirs));
-        m2l_split_mats(rm.p, rp, kNumDirs, op->m2l_bf.p, s);
+        op->m2l_bf.alloc(m2l_split_mats_elems(rp, kNumDirs, 3));
+        m2l_split_mats(rm.p, rp, kNumDirs, 3, op->m2l_bf.p, s);
+        op->m2l_bf2.alloc(m2l_split_mats_elems(rp, kNumDirs, 2));
+        m2l_split_mats(rm.p, rp, kNumDirs, 2, op->m2l_bf2.p, s);
         FMM_HIP(hipStreamSynchronize(s));
     }
     return op;
@@ -375,8 +377,10 @@ std::shared_ptr<Operators> build_chebyshev(int n, double eps, hipStream_t s) {
         build_translations(op->dY.p, nn, r, rp, prm, dQT.p, dQ.p, nullptr, &rm, s);
         op->m2l_f32.alloc((size_t)rp * rp * kNumDirs);
         m2l_image_mats(rm.p, rp, kNumDirs, op->m2l_f32.p, s);
-        op->m2l_bf.alloc(m2l_split_mats_elems(rp, kNumDirs));
-        m2l_split_mats(rm.p, rp, kNumDirs, op->m2l_bf.p, s);
+        op->m2l_bf.alloc(m2l_split_mats_elems(rp, kNumDirs, 3));
+        m2l_split_mats(rm.p, rp, kNumDirs, 3, op->m2l_bf.p, s);
+        op->m2l_bf2.alloc(m2l_split_mats_elems(rp, kNumDirs, 2));
+        m2l_split_mats(rm.p, rp, kNumDirs, 2, op->m2l_bf2.p, s);
         FMM_HIP(hipStreamSynchronize(s));
     }
     return op;

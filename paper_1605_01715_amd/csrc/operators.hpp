@@ -43,7 +43,8 @@ struct Operators {
     std::vector<double> Y;         // [ns][3]
     DBuf<double> dY;
     DBuf<float> m2l_f32;           // [316] r_pad x r_pad float32, M2L kernel chunk order (FP32 form)
-    DBuf<uint16_t> m2l_bf;         // the same, split into bfloat16 parts (M2L kernel, split-BF16 form)
+    DBuf<uint16_t> m2l_bf;         // the same, split into three bfloat16 parts (M2L kernel, bf16x6)
+    DBuf<uint16_t> m2l_bf2;        // the same, split into two bfloat16 parts (bf16x3, bf16x4)
     DBuf<double> m2m_f64, l2l_f64; // [8] r_pad x r_pad, float64 fragment layout
     DBuf<double> pu_f64, pv_f64;   // r_pad x n_pad fragment layout
     DBuf<double> cu_f64, cd_f64;   // n_pad x r_pad fragment layout

@@ -348,7 +348,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         // workgroup slot) for k = 1..6 unless the options force k. Pieces of a cut tile write partial
         // sums, added to the output in piece order by a second kernel.
         {
-            const int slots = 32 * m2l_blocks_per_cu(P.m2l_bf16, P.r_pad);  // concurrent workgroups per XCD
+            const int slots = 32 * m2l_blocks_per_cu(P.m2l_form, P.r_pad);  // concurrent workgroups per XCD
             auto ndir = [&](int tl) { return (int)(toff[tl + 1] - toff[tl]); };
             // makespan of one XCD in steps, with a cost of 2 directions per piece of a cut tile
             auto makespan = [&](int k) {
@@ -501,7 +501,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             }
             if (rng.size() == from) continue;
             merge_ranges(rng, from);
-            for (size_t e = from; e < rng.size(); e += 2) P.p2m_evals += (int64_t)(rng[e + 1] - rng[e]) * ns;
+            for (size_t e = from; e < rng.size(); e += 2) P.p2l_evals += (int64_t)(rng[e + 1] - rng[e]) * ns;
             items.push_back((int32_t)b);
             roff.push_back((int32_t)(rng.size() / 2));
         }
@@ -813,7 +813,7 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     g.half = t.half.p;
 
     auto split_m2l_input = [&] {
-        if (P.m2l_bf16) m2l_split_vecs(P.ut.p, rp, t.nb * nrhs, P.ut_bf.p, s);
+        if (P.m2l_form) m2l_split_vecs(P.ut.p, rp, t.nb * nrhs, m2l_form_parts(P.m2l_form), P.ut_bf.p, s);
     };
     auto run_m2l = [&] {
         M2LLaunch m;
@@ -826,13 +826,13 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         m.tile_cols = P.m2l_cols.p;
         m.mats = op.m2l_f32.p;
         m.in = P.ut.p;
-        m.mats_bf = op.m2l_bf.p;
+        m.mats_bf = m2l_form_parts(P.m2l_form) == 3 ? op.m2l_bf.p : op.m2l_bf2.p;
         m.in_bf = P.ut_bf.p;
         m.zero = P.m2l_zero.p;
         m.piece_slot = P.m2l_slot.p;
         m.partial = P.m2l_partial.p;
         m.out = P.dt.p;
-        m2l_run(P.m2l_bf16, m, s);
+        m2l_run(P.m2l_form, m, s);
         if (P.m2l_nsplit > 0)
             m2l_reduce(rp, P.m2l_nsplit, P.m2l_ncol, P.m2l_red_cols.p, P.m2l_red_slot0.p, P.m2l_red_k.p, P.m2l_partial.p,
                        P.dt.p, s);
@@ -928,12 +928,25 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         nodes_to_points(nrhs, op.p, op.cheb_coef.p, el, g, P.phi_d.p, s);
         mark(ST_EVAL);  // the evaluation itself is timed on the side stream
     } else {
+        // Surface form: the near field and M2P (the leaf evaluation without
+        // L2P) need only the upward equivalent densities, so after the upward
+        // pass they run on the side stream beside P2L, M2L, L2L and the
+        // downward expansion; L2P adds to the outputs after the join.
         mark(ST_P2M);
         points_to_surface(nrhs, sl, dl, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, kRadOut, g, src, P.chk.p,
                           false, s);
         run_gemm(P.p2m_proj, op.pu_f64.p, rp, np, P.chk.p, P.ut.p, nullptr, false, s);
         mark(ST_M2M);
         for (auto &j : P.m2m_jobs) run_gemm(j, op.m2m_f64.p, rp, rp, P.ut.p, P.ut.p, nullptr, false, s);
+        run_gemm(P.c2e_up, op.cu_f64.p, np, rp, P.ut.p, P.phi_u.p, P.col_scale.p, false, s);
+        FMM_HIP(hipEventRecord(P.fork, s));
+        FMM_HIP(hipStreamWaitEvent(P.side, P.fork, 0));
+        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[2], P.side));
+        EvalArgs en = e;
+        en.surf_mask = 2;  // M2P surfaces and the point ranges
+        eval_leaves(nrhs, sl, dl, en, g, src, P.side);
+        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[3], P.side));
+        FMM_HIP(hipEventRecord(P.join, P.side));
         mark(ST_P2L);
         points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, kRadIn, g, src, P.chk.p,
                           false, s);
@@ -945,9 +958,13 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         for (auto &j : P.l2l_jobs) run_gemm(j, op.l2l_f64.p, rp, rp, P.dt.p, P.dt.p, nullptr, true, s);
         mark(ST_C2E);
         run_gemm(P.c2e_down, op.cd_f64.p, np, rp, P.dt.p, P.phi_d.p, P.col_scale.p, false, s);
-        run_gemm(P.c2e_up, op.cu_f64.p, np, rp, P.ut.p, P.phi_u.p, P.col_scale.p, false, s);
+        FMM_HIP(hipStreamWaitEvent(s, P.join, 0));
         mark(ST_EVAL);
-        eval_leaves(nrhs, sl, dl, e, g, src, s);
+        EvalArgs ef = e;
+        ef.surf_mask = 1;  // L2P: the leaf's own downward surface, added to the near field
+        ef.points = 0;
+        ef.accumulate = 1;
+        eval_leaves(nrhs, sl, dl, ef, g, src, s);
     }
     mark(ST_COUNT);
     if (P.timing && !capturing) plan_collect_times(P);
@@ -969,6 +986,11 @@ void plan_collect_times(Plan &P) {
         P.stage_ms[ST_P2L] = ms;
         FMM_HIP(hipEventElapsedTime(&ms, P.ev_side[2], P.ev_side[3]));
         P.stage_ms[ST_EVAL] = ms;
+    } else {
+        // the near field ran on the side stream; EVAL is it plus the L2P pass
+        float ms = 0.f;
+        FMM_HIP(hipEventElapsedTime(&ms, P.ev_side[2], P.ev_side[3]));
+        P.stage_ms[ST_EVAL] += ms;
     }
     P.have_times = true;
 }

@@ -36,11 +36,11 @@ struct Plan {
     Tree t;
     std::shared_ptr<const Operators> ops;
     int ns = 0, n_pad = 0, r = 0, r_pad = 0;
-    bool m2l_bf16 = false;
+    int m2l_form = 0;  // M2L arithmetic: 0 float32; 6, 4, 3 split-BF16 products (m2l.hpp)
     bool cheb = false;  // Chebyshev basis: node weights W in phi_u, node values L in phi_d
 
     DBuf<float> ut, dt;                     // [nb * nrhs][r_pad] compressed upward / downward state
-    DBuf<uint16_t> ut_bf;                   // ut split into bfloat16 parts (split-BF16 M2L)
+    DBuf<uint16_t> ut_bf;                   // ut split into bfloat16 parts (split-BF16 M2L forms)
     DBuf<float> chk;                        // [nb * nrhs][n_pad] check potentials made from points
     DBuf<float> phi_u, phi_d;               // [nb * nrhs][n_pad] equivalent densities
     DBuf<float> q_sorted, mx, my, mz;       // [nrhs][n_src]
@@ -81,7 +81,9 @@ struct Plan {
     int64_t m2l_pairs = 0;
     int64_t surf_evals = 0;
     int64_t p2m_evals = 0;
+    int64_t p2l_evals = 0;
     double setup_ms = 0;
+    int leaf_from_cache = 0;  // leaf_size = 0 resolved from the tuning cache (1) or the default (0)
 
     // captured apply (fmm_set_graph): replayed while the argument pointers match
     struct Graph {
@@ -131,6 +133,16 @@ void dielectric_rhs_noalloc(Plan &P, const float *sigma_f, const float *areas, c
                             const float *eps_i, double eps_m, const double *e0, double *b, hipStream_t s);
 void body_forces(Plan &P, const float *sigma, const float *sigma2, const float *areas, const float *curv,
                  double eps_m, const double *e0, int n_body, const int64_t *body_off, double *forces, hipStream_t s);
+// Leaf-size tuning cache (tune.hip): the key of a plan's configuration, the
+// cache file (FMM_TUNE_CACHE, else ~/.cache/fmm_mi355x_tune.jsonl), lookup
+// and store; random densities for trial runs.
+std::string tune_key(const fmm_options &o, int64_t points_per_instance, bool tsm, bool batch);
+std::string tune_cache_path();
+bool tune_cache_lookup(const std::string &path, const std::string &key, int &leaf, int &pieces);
+void tune_cache_store(const std::string &path, const std::string &key, int leaf, int pieces, double ms);
+void fill_random(float *out, int64_t n, uint32_t seed, hipStream_t s);
+constexpr int kDefaultAutoLeaf = 128;  // leaf_size = 0 with no cache entry
+
 void plan_gmres(Plan &P, const fmm_operator &op, const double *b, double *x, double rtol, int restart, int max_iter,
                 int *iters, double *rel_res, int *status, hipStream_t s);
 

@@ -79,7 +79,7 @@ def test_binding_structs_match_the_header(tmp_path):
         assert int(v) == want, (st, f)
 
 
-@pytest.mark.parametrize("field,value", [("order", 1), ("order", 11), ("leaf_size", 0), ("max_depth", 22),
+@pytest.mark.parametrize("field,value", [("order", 1), ("order", 11), ("leaf_size", -1), ("max_depth", 22),
                                          ("nrhs", 0), ("nrhs", 5), ("precision", 7), ("src_kernels", 0),
                                          ("outputs", 4), ("basis", 2), ("basis", -1), ("cheb_order", 9),
                                          ("cheb_order", 1)])
