@@ -196,8 +196,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle (errors and baselines)")
     ap.add_argument("--basis", choices=("surface", "chebyshev"), default="chebyshev",
                     help="far-field form for --no-tune runs")
-    ap.add_argument("--precision", choices=("split_bf16", "fp32"), default="split_bf16",
-                    help="M2L arithmetic for --no-tune --no-fp32 runs")
+    ap.add_argument("--precision", choices=("bf16x3", "bf16x4", "bf16x6", "fp32"), default="bf16x3",
+                    help="M2L arithmetic of the split leg in --no-tune runs (fp32 with --no-fp32: the plain leg only)")
     ap.add_argument("--setup-only", type=int, default=0, metavar="K",
                     help="only set up the --basis/--order/--leaf/--eps plan K times and report the setup times")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -236,7 +236,7 @@ def main():
     q = torch.from_numpy(d["q"]).to(dev)
     mu = torch.from_numpy(d["mu"]).to(dev)
     basis_arg = BASES.index(args.basis)
-    prec_arg = F.FMM_PREC_SPLIT_BF16 if args.precision == "split_bf16" else F.FMM_PREC_FP32
+    prec_arg = PREC_NAMES.index(args.precision)
 
     if args.setup_only:
         opts = options(F, prec_arg, basis_arg, args.order, args.eps, args.leaf)
@@ -300,10 +300,10 @@ def main():
     # (leg name, candidate M2L arithmetics): the split-BF16 leg tries the
     # six-product and three-product schemes, the plain leg float32
     legs = [("split_bf16", (F.FMM_PREC_SPLIT_BF16, F.FMM_PREC_SPLIT_BF16X3))]
-    if not args.no_fp32:
+    if args.no_tune:
+        legs = [("split_bf16" if prec_arg else "fp32", (prec_arg,))]
+    if not args.no_fp32 and prec_arg:
         legs.append(("fp32", (F.FMM_PREC_FP32,)))
-    if args.no_tune and args.no_fp32:
-        legs = [(args.precision, (prec_arg,))]
     results = {}
     for name, precs in legs:
         tune = []
