@@ -249,8 +249,10 @@ def main():
             times.append(time.perf_counter() - t0)
             info = F.fmm_plan_info(plan)
             F.fmm_destroy(plan)
-            log(f"bench: setup {k}: {times[-1]:.3f} s")
-        print(json.dumps({"setup_s": times, "boxes": info["n_boxes"], "levels": info["n_levels"],
+            log(f"bench: setup {k}: {times[-1]:.3f} s, phases (ms) "
+                f"{json.dumps({p: round(v, 2) for p, v in info['setup_phase_ms'].items()})}")
+        print(json.dumps({"setup_s": times, "phases_ms": {p: round(v, 2) for p, v in info["setup_phase_ms"].items()},
+                          "boxes": info["n_boxes"], "levels": info["n_levels"],
                           "config": form_tag((basis_arg, args.order, args.leaf, args.eps))}), flush=True)
         return
 
@@ -385,6 +387,10 @@ def main():
         "rel_l2_error": main_r.get("err"),
         "rel_l2_error_seed7": main_r.get("err_seed7"),
         "setup_s": round(main_r["setup_s"], 3),
+        "setup": {"s": round(main_r["setup_s"], 3), "what": "fmm_setup of the timed plan: tree, lists, operators "
+                  "(cached per device after the tuning runs), work lists; host wall time per phase, each phase "
+                  "ended by a stream synchronisation",
+                  "phases_ms": {k: round(v, 2) for k, v in info["setup_phase_ms"].items()}},
         "stages_ms": {k: round(v, 4) for k, v in main_r["stages"].items()},
         "roofline": main_r["roofline"],
         "kernels": main_r["kernels"],
@@ -393,6 +399,15 @@ def main():
         "split_products": {"config": "Chebyshev, 8 nodes per axis, leaf 192, threshold 1e-7",
                            "by_arith": products} if products else None,
     }
+    # the equivalent-surface form's best tuned candidate in the same run, beside the selected form
+    surf = [c for c in (main_r["tune"] or []) if c["basis"] == "surface"
+            and max(c["err"], c["err_seed7"]) <= args.target]
+    if surf:
+        c = min(surf, key=lambda c: c["ms"])
+        line["surface_form"] = {"value": round(info["n_points"] / (c["ms"] * 1e-3) / 1e6, 3), "arith": c["arith"],
+                                "order_leaf_eps": [c["order"], c["leaf"], c["eps"]], "ms_per_step": c["ms"],
+                                "rel_l2_error": c["err"], "rel_l2_error_seed7": c["err_seed7"],
+                                "timing": "3 tuning applies after 1 warm-up"}
     if "fp32" in results and main_name != "fp32":
         f = results["fp32"]
         line["fp32_form"] = {"value": round(info["n_points"] / (f["ms"] * 1e-3) / 1e6, 3), "arith": "fp32",

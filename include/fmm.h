@@ -331,6 +331,15 @@ typedef struct {
     int64_t leaf_size;                   /* leaf cap the plan was built with */
     int64_t leaf_from_cache;             /* 1 when leaf_size = 0 was resolved from the tuning cache */
     int64_t p2l_evals;                   /* P2L: (check point or node) x X-list source evaluations per rhs */
+    double setup_phase_ms[8];            /* host wall time of the setup phases, each ended by a stream
+                                            synchronisation: [0] bounding box, Morton keys and radix
+                                            sort; [1] octree levels, boxes and sorted point data;
+                                            [2] U/V/W/X lists and their host copies; [3] operators
+                                            (cached per device after the first plan of a form);
+                                            [4] per-box buffers; [5] the M2L schedule (tiles,
+                                            pieces, partial-sum slots); [6] the other work lists;
+                                            [7] unused (0). A batch builds all its instance trees
+                                            in the one pass of [0]-[2] */
 } fmm_info;
 int fmm_plan_info(fmm_plan plan, fmm_info *info);
 

@@ -180,11 +180,15 @@ def fmm_direct(src_xyz, trg_xyz, q=None, mu=None, src_nrm=None, cutoff=1e-5, pot
                                _stream(stream)))
 
 
+SETUP_PHASES = ("sort", "octree", "lists", "operators", "buffers", "m2l_schedule", "worklists", "unused")
+
+
 def fmm_plan_info(plan):
     info = L.FmmInfo()
     _check(L.load().fmm_plan_info(plan.handle, ctypes.byref(info)))
-    d = {name: getattr(info, name) for name, _ in L.FmmInfo._fields_ if name != "root"}
+    d = {name: getattr(info, name) for name, _ in L.FmmInfo._fields_ if name not in ("root", "setup_phase_ms")}
     d["root"] = tuple(info.root)
+    d["setup_phase_ms"] = dict(zip(SETUP_PHASES, info.setup_phase_ms))
     return d
 
 

@@ -39,7 +39,8 @@ class FmmInfo(ctypes.Structure):
                                                                                  ("setup_ms", c_double),
                                                                                  ("leaf_size", c_int64),
                                                                                  ("leaf_from_cache", c_int64),
-                                                                                 ("p2l_evals", c_int64)]
+                                                                                 ("p2l_evals", c_int64),
+                                                                                 ("setup_phase_ms", c_double * 8)]
 
 
 class FmmTuneSpace(ctypes.Structure):

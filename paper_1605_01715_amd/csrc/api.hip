@@ -162,8 +162,17 @@ void init_plan(fmm::Plan &P, const fmm_options *opt) {
 // Everything after the tree: operators, per-box buffers, work lists.
 void finish_plan(fmm::Plan &P, const fmm_options *opt, const float *trg_nrm, hipStream_t s) {
     using namespace fmm;
+    auto clock0 = std::chrono::steady_clock::now();
+    auto phase_end = [&](int k) {
+        FMM_HIP(hipStreamSynchronize(s));
+        const auto now = std::chrono::steady_clock::now();
+        P.setup_phase_ms[k] += std::chrono::duration<double, std::milli>(now - clock0).count();
+        clock0 = now;
+    };
+    for (int k = 0; k < 3; ++k) P.setup_phase_ms[k] += P.t.phase_ms[k];
     double eps = opt->pinv_eps > 0 ? opt->pinv_eps : default_pinv_eps(opt->basis, opt->order);
     P.ops = get_operators(opt->basis, opt->order, eps, s);
+    phase_end(3);
     P.cheb = opt->basis == FMM_BASIS_CHEBYSHEV;
     P.ns = P.ops->ns;
     P.n_pad = P.ops->n_pad;
@@ -197,6 +206,7 @@ void finish_plan(fmm::Plan &P, const fmm_options *opt, const float *trg_nrm, hip
         P.trg_nrm_user.alloc(3 * (size_t)P.t.n_src);
         FMM_HIP(hipMemcpyAsync(P.trg_nrm_user.p, trg_nrm, 3 * P.t.n_src * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
+    phase_end(4);
     if (P.t.nb) plan_build_worklists(P, s);
     if (P.t.nb) plan_create_side(P);
     FMM_HIP(hipStreamSynchronize(s));
@@ -280,17 +290,7 @@ int fmm_setup_batch(int n_inst, const int64_t *src_off, const int64_t *trg_off, 
             Plan &P = *h->p;
             init_plan(P, opt);
             P.leaf_from_cache = from_cache;
-            const TreeOptions topt = tree_options(opt);
-            std::vector<Tree> parts(n_inst);
-            for (int i = 0; i < n_inst; ++i) {
-                const int64_t ns = so[i + 1] - so[i];
-                const float *sx = src_xyz ? src_xyz + 3 * so[i] : nullptr;
-                const float *sn = src_nrm ? src_nrm + 3 * so[i] : nullptr;
-                const float *tx = tsm ? trg_xyz + 3 * to[i] : nullptr;
-                const float *tn = trg_nrm ? trg_nrm + 3 * (tsm ? to[i] : so[i]) : nullptr;
-                build_tree(parts[i], sx, sn, ns, tx, tn, tsm ? to[i + 1] - to[i] : 0, topt, s);
-            }
-            merge_forest(parts, so, to, src_nrm != nullptr, trg_nrm != nullptr, P.t, s);
+            build_forest(P.t, so, to, src_xyz, src_nrm, tsm ? trg_xyz : nullptr, trg_nrm, tree_options(opt), s);
             P.n_inst = n_inst;
             finish_plan(P, opt, trg_nrm, s);
             P.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -469,6 +469,7 @@ int fmm_plan_info(fmm_plan plan, fmm_info *info) {
         for (int c = 0; c < 3; ++c) r.root[c] = P.t.x0[c];
         r.root[3] = P.t.w;
         r.setup_ms = P.setup_ms;
+        for (int k = 0; k < 8; ++k) r.setup_phase_ms[k] = P.setup_phase_ms[k];
         r.leaf_size = P.opt.leaf_size;
         r.leaf_from_cache = P.leaf_from_cache;
         r.p2l_evals = P.p2l_evals;

@@ -88,6 +88,15 @@ DBuf<T> upload(const std::vector<T> &v, hipStream_t s) {
     return b;
 }
 
+// Diagnostics on stderr, on when the environment variable FMM_LOG is set to
+// a value other than 0 (read once per process).
+bool log_enabled();
+void log_printf(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+#define FMM_LOG(...)                                            \
+    do {                                                        \
+        if (::fmm::log_enabled()) ::fmm::log_printf(__VA_ARGS__); \
+    } while (0)
+
 inline unsigned grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
     return (unsigned)(g < 1 ? 1 : g);

@@ -12,8 +12,9 @@
 // evaluated directly rather than through a surface (this never changes what
 // is computed, only how).
 #include <algorithm>
-#include <cmath>
 #include <array>
+#include <chrono>
+#include <cmath>
 #include <limits>
 #include <queue>
 
@@ -52,6 +53,54 @@ __global__ __launch_bounds__(64) void k_point_boxes(const int32_t *boxes, const 
             out[6 * b + c] = lo[c];
             out[6 * b + 3 + c] = hi[c];
         }
+}
+
+constexpr int kMaskWords = (kNumDirs + 63) / 64;
+
+// Host wall time since the previous call (or construction), logged with FMM_LOG.
+struct Lap {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    void operator()(const char *what) {
+        const auto now = std::chrono::steady_clock::now();
+        FMM_LOG("setup: %s %.2f ms\n", what, std::chrono::duration<double, std::milli>(now - t0).count());
+        t0 = now;
+    }
+};
+
+// Per box b, bit 63 - d % 64 of out[b * kMaskWords + d / 64] is set when the
+// V partner in direction d exists and holds sources.
+__global__ void k_dir_masks(const int32_t *vdense, int64_t nb, const int64_t *sbeg, const int64_t *send,
+                            uint64_t *out) {
+    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (b >= nb) return;
+    for (int w = 0; w < kMaskWords; ++w) {
+        uint64_t m = 0;
+        for (int i = 0; i < 64 && w * 64 + i < kNumDirs; ++i) {
+            const int32_t a = vdense[b * kNumDirs + w * 64 + i];
+            if (a >= 0 && send[a] > sbeg[a]) m |= 1ull << (63 - i);
+        }
+        out[b * kMaskWords + w] = m;
+    }
+}
+
+// M2L sources: for step e (work item item[e], direction dir[e]) and column c
+// with target vector v = cols[item[e] * nc + c] (box v / nrhs, rhs v % nrhs),
+// out[e * nc + c] = a * nrhs + v % nrhs for the V partner a of that box in
+// that direction when it holds sources, else -1.
+__global__ void k_m2l_sources(const int32_t *item, const int32_t *dir, int64_t nsteps, const int32_t *cols, int nc,
+                              const int32_t *vdense, const int64_t *sbeg, const int64_t *send, int nrhs,
+                              int32_t *out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nsteps * nc) return;
+    const int64_t e = i / nc;
+    const int c = (int)(i - e * nc);
+    const int32_t v = cols[(int64_t)item[e] * nc + c];
+    int32_t sv = -1;
+    if (v >= 0) {
+        const int32_t a = vdense[(int64_t)(v / nrhs) * kNumDirs + dir[e]];
+        if (a >= 0 && send[a] > sbeg[a]) sv = a * nrhs + v % nrhs;
+    }
+    out[i] = sv;
 }
 
 __global__ void k_zero(float *p, int64_t n) {
@@ -118,7 +167,15 @@ void merge_ranges(std::vector<int32_t> &r, size_t from) {
 }  // namespace
 
 void plan_build_worklists(Plan &P, hipStream_t s) {
+    auto clock0 = std::chrono::steady_clock::now();
+    auto phase_end = [&](int k) {
+        FMM_HIP(hipStreamSynchronize(s));
+        const auto now = std::chrono::steady_clock::now();
+        P.setup_phase_ms[k] += std::chrono::duration<double, std::milli>(now - clock0).count();
+        clock0 = now;
+    };
     Tree &t = P.t;
+    Lap wl;
     const int64_t nb = t.nb;
     const int nrhs = P.nrhs, ns = P.ns;
     auto nsrc = [&](int64_t b) { return t.h_send[b] - t.h_sbeg[b]; };
@@ -156,6 +213,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         j.src = upload(cols, s);
     }
 
+    wl("scales and P2M lists");
     const int ncol64 = kGemmCols;
     // M2M, bottom-up (float64 tiles)
     for (int l = t.nlev - 2; l >= 2; --l) {
@@ -182,26 +240,40 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         P.m2m_jobs.push_back(std::move(j));
     }
 
+    wl("M2M lists");
+    phase_end(6);
     // M2L: every target box at level >= 2 with at least one V partner holding sources
     {
+        Lap lap;
+        // per box, the directions whose V partner holds sources, as a bit mask
+        // (direction d is bit 63 - d % 64 of word d / 64, so that comparing the
+        // words in order compares the sets lexicographically)
+        std::vector<uint64_t> mask((size_t)nb * kMaskWords);
+        {
+            DBuf<uint64_t> dm(mask.size());
+            hipLaunchKernelGGL(k_dir_masks, dim3(grid_for(nb, kBlock)), dim3(kBlock), 0, s, t.vdense.p, nb,
+                               t.sbeg.p, t.send.p, dm.p);
+            FMM_HIP(hipGetLastError());
+            d2h(mask.data(), dm.p, mask.size(), s);
+        }
+        lap("m2l direction masks");
+        auto mask_of = [&](int64_t b) { return &mask[(size_t)b * kMaskWords]; };
         std::vector<int32_t> boxes;
         for (int64_t b = 0; b < nb; ++b) {
             if (lvl(b) < 2 || ntrg(b) == 0) continue;
-            bool any = false;
-            for (int32_t k = t.V.h_off[b]; k < t.V.h_off[b + 1] && !any; ++k) any = nsrc(t.V.h_idx[k]) > 0;
-            if (any) {
+            int64_t live = 0;
+            for (int w = 0; w < kMaskWords; ++w) live += __builtin_popcountll(mask_of(b)[w]);
+            if (live) {
                 boxes.push_back((int32_t)b);
-                for (int32_t k = t.V.h_off[b]; k < t.V.h_off[b + 1]; ++k)
-                    if (nsrc(t.V.h_idx[k]) > 0) ++P.m2l_pairs;
+                P.m2l_pairs += live;
             }
         }
         FMM_REQUIRE(m2l_supported(P.r_pad), "M2L: unsupported compressed state size");
+        lap("m2l target boxes");
         // Tiles of m2l_ncol output vectors, each with its list of active
         // directions. A box's V-list offsets are fixed by its octant inside
         // its parent (189 of the 316), so tiles hold one octant only: the
         // directions a tile runs are then (nearly) the ones every column needs.
-        std::vector<int32_t> vd((size_t)nb * kNumDirs);
-        d2h(vd.data(), t.vdense.p, vd.size(), s);
         const int nc = m2l_ncol(P.r_pad);
         int ntile = 0;
         std::vector<int32_t> cols;
@@ -211,20 +283,14 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         // boxes with similar V lists and runs few directions that most of its
         // columns do not need (measured: fill 0.69 -> 0.78 on the clustered
         // cloud, worth more than the spatial locality it gives up).
-        constexpr int kMaskWords = (kNumDirs + 63) / 64;
-        auto dir_mask = [&](int32_t b) {
-            std::array<uint64_t, kMaskWords> m{};
-            for (int d = 0; d < kNumDirs; ++d) {
-                const int32_t a = vd[(size_t)b * kNumDirs + d];
-                if (a >= 0 && nsrc(a) > 0) m[d / 64] |= 1ull << (63 - d % 64);
-            }
-            return m;
-        };
         for (int o = 0; o < 8; ++o) {
             std::vector<std::pair<std::array<uint64_t, kMaskWords>, int32_t>> keyed;
             for (int32_t b : boxes) {
                 const int32_t *an = &t.h_anchor[3 * (size_t)b];
-                if ((((an[0] & 1) << 2) | ((an[1] & 1) << 1) | (an[2] & 1)) == o) keyed.push_back({dir_mask(b), b});
+                if ((((an[0] & 1) << 2) | ((an[1] & 1) << 1) | (an[2] & 1)) != o) continue;
+                std::array<uint64_t, kMaskWords> m;
+                std::copy(mask_of(b), mask_of(b) + kMaskWords, m.begin());
+                keyed.push_back({m, b});
             }
             std::sort(keyed.begin(), keyed.end());
             std::vector<int32_t> grp;
@@ -235,99 +301,105 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             ntile += nt;
             tile_oct.insert(tile_oct.end(), nt, o);
         }
-        std::vector<int64_t> toff{0};
-        std::vector<int32_t> tdir, tsrc, colsrc(nc);
+        lap("m2l tiles");
+        // per tile and direction, the columns with a source there
+        std::vector<int32_t> tcnt((size_t)ntile * kNumDirs, 0);
+#pragma omp parallel for schedule(dynamic, 8)
         for (int tl = 0; tl < ntile; ++tl) {
-            for (int d = 0; d < kNumDirs; ++d) {
-                bool any = false;
-                for (int c = 0; c < nc; ++c) {
-                    int32_t v = cols[(size_t)tl * nc + c], sv = -1;
-                    if (v >= 0) {
-                        int32_t a = vd[(size_t)(v / nrhs) * kNumDirs + d];
-                        if (a >= 0 && nsrc(a) > 0) {
-                            sv = a * nrhs + v % nrhs;
-                            any = true;
-                        }
-                    }
-                    colsrc[c] = sv;
-                }
-                if (!any) continue;
-                tdir.push_back(d);
-                tsrc.insert(tsrc.end(), colsrc.begin(), colsrc.end());
+            int32_t *cnt = &tcnt[(size_t)tl * kNumDirs];
+            for (int c = 0; c < nc; ++c) {
+                const int32_t v = cols[(size_t)tl * nc + c];
+                if (v < 0) continue;
+                const uint64_t *m = mask_of(v / nrhs);
+                for (int w = 0; w < kMaskWords; ++w)
+                    for (uint64_t bits = m[w]; bits; bits &= bits - 1) ++cnt[w * 64 + 63 - __builtin_ctzll(bits)];
             }
+        }
+        lap("m2l direction counts");
+        std::vector<int64_t> toff{0};
+        std::vector<int32_t> tdir;
+        for (int tl = 0; tl < ntile; ++tl) {
+            for (int d = 0; d < kNumDirs; ++d)
+                if (tcnt[(size_t)tl * kNumDirs + d]) tdir.push_back(d);
             toff.push_back((int64_t)tdir.size());
         }
         // Sparse tiles become pair tiles. Where boxes have few and varied V
         // partners (points on surfaces), a tile runs every direction for
         // only a fraction of its columns (fill 0.2-0.3 on the sphere
-        // workloads). The (direction, target, source) triples of tiles with
-        // fill below kPairFill are regrouped by octant and direction into
-        // tiles of one direction whose columns are pairs, all live; each
-        // writes its products to a partial-sum slot, and a gather adds each
-        // target's partials in direction order. Costs: a tile does 6 steps per
+        // workloads). The (direction, target) pairs of tiles with fill below
+        // kPairFill are regrouped by octant and direction into tiles of one
+        // direction whose columns are pairs, all live; each writes its
+        // products to a partial-sum slot, and a gather adds each target's
+        // partials in direction order. Costs: a tile does 6 steps per
         // direction; a pair tile 6 steps plus writing and reading back its
         // partials (about 3 more), so the switch pays below fill 0.6.
+        lap("m2l direction lists");
         constexpr double kPairFill = 0.6;
         std::vector<uint8_t> pair_tile(ntile, 0);
         {
-            struct PairE {
-                int32_t dir, v, sv;
-            };
-            std::vector<std::vector<PairE>> pool(8);
+            // the columns of the sparse tiles, per octant
+            std::vector<std::vector<int32_t>> sparse(8);
             std::vector<uint8_t> keep(ntile, 1);
             bool moved = false;
             for (int tl = 0; tl < ntile; ++tl) {
                 const int64_t n = toff[tl + 1] - toff[tl];
                 int64_t live = 0;
-                for (int64_t e = toff[tl]; e < toff[tl + 1]; ++e)
-                    for (int c = 0; c < nc; ++c) live += tsrc[(size_t)e * nc + c] >= 0;
+                for (int d = 0; d < kNumDirs; ++d) live += tcnt[(size_t)tl * kNumDirs + d];
                 if (n == 0 || (double)live >= kPairFill * (double)n * nc) continue;
                 keep[tl] = 0;
                 moved = true;
-                for (int64_t e = toff[tl]; e < toff[tl + 1]; ++e)
-                    for (int c = 0; c < nc; ++c) {
-                        const int32_t sv = tsrc[(size_t)e * nc + c];
-                        if (sv >= 0) pool[tile_oct[tl]].push_back({tdir[e], cols[(size_t)tl * nc + c], sv});
-                    }
+                for (int c = 0; c < nc; ++c) {
+                    const int32_t v = cols[(size_t)tl * nc + c];
+                    if (v >= 0) sparse[tile_oct[tl]].push_back(v);
+                }
             }
             if (moved) {
                 std::vector<int64_t> toff2{0};
-                std::vector<int32_t> tdir2, tsrc2, cols2;
+                std::vector<int32_t> tdir2, cols2;
                 std::vector<int> oct2;
                 std::vector<uint8_t> pair2;
                 for (int tl = 0; tl < ntile; ++tl) {
                     if (!keep[tl]) continue;
-                    for (int64_t e = toff[tl]; e < toff[tl + 1]; ++e) {
-                        tdir2.push_back(tdir[e]);
-                        tsrc2.insert(tsrc2.end(), tsrc.begin() + (size_t)e * nc, tsrc.begin() + (size_t)(e + 1) * nc);
-                    }
+                    tdir2.insert(tdir2.end(), tdir.begin() + toff[tl], tdir.begin() + toff[tl + 1]);
                     toff2.push_back((int64_t)tdir2.size());
                     cols2.insert(cols2.end(), cols.begin() + (size_t)tl * nc, cols.begin() + (size_t)(tl + 1) * nc);
                     oct2.push_back(tile_oct[tl]);
                     pair2.push_back(0);
                 }
+                // per octant, the (direction, target) pairs ordered by direction,
+                // then target: a counting sort over the directions of the
+                // targets taken in increasing order
                 for (int o = 0; o < 8; ++o) {
-                    auto &v = pool[o];
-                    std::sort(v.begin(), v.end(), [](const PairE &x, const PairE &y) {
-                        return x.dir != y.dir ? x.dir < y.dir : x.v < y.v;
-                    });
-                    for (size_t i = 0; i < v.size();) {
-                        size_t j = i;
-                        while (j < v.size() && j - i < (size_t)nc && v[j].dir == v[i].dir) ++j;
-                        tdir2.push_back(v[i].dir);
-                        for (size_t q = i; q < i + nc; ++q) {
-                            cols2.push_back(q < j ? v[q].v : -1);
-                            tsrc2.push_back(q < j ? v[q].sv : -1);
-                        }
-                        toff2.push_back((int64_t)tdir2.size());
-                        oct2.push_back(o);
-                        pair2.push_back(1);
-                        i = j;
+                    std::vector<int32_t> &sv = sparse[o];
+                    std::sort(sv.begin(), sv.end());
+                    std::vector<int64_t> start(kNumDirs + 1, 0);
+                    for (int32_t v : sv) {
+                        const uint64_t *m = mask_of(v / nrhs);
+                        for (int w = 0; w < kMaskWords; ++w)
+                            for (uint64_t bits = m[w]; bits; bits &= bits - 1)
+                                ++start[w * 64 + 63 - __builtin_ctzll(bits) + 1];
                     }
+                    for (int d = 0; d < kNumDirs; ++d) start[d + 1] += start[d];
+                    std::vector<int32_t> by_dir(start[kNumDirs]);
+                    std::vector<int64_t> pos(start.begin(), start.end() - 1);
+                    for (int32_t v : sv) {
+                        const uint64_t *m = mask_of(v / nrhs);
+                        for (int w = 0; w < kMaskWords; ++w)
+                            for (uint64_t bits = m[w]; bits; bits &= bits - 1)
+                                by_dir[pos[w * 64 + 63 - __builtin_ctzll(bits)]++] = v;
+                    }
+                    for (int d = 0; d < kNumDirs; ++d)
+                        for (int64_t i = start[d]; i < start[d + 1]; i += nc) {
+                            const int64_t j = std::min(start[d + 1], i + nc);
+                            tdir2.push_back(d);
+                            for (int64_t q = i; q < i + nc; ++q) cols2.push_back(q < j ? by_dir[q] : -1);
+                            toff2.push_back((int64_t)tdir2.size());
+                            oct2.push_back(o);
+                            pair2.push_back(1);
+                        }
                 }
                 toff.swap(toff2);
                 tdir.swap(tdir2);
-                tsrc.swap(tsrc2);
                 cols.swap(cols2);
                 tile_oct.swap(oct2);
                 pair_tile.swap(pair2);
@@ -386,6 +458,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
                     }
                 }
             }
+            lap("m2l pair tiles and piece model");
             P.m2l_pieces_per_tile = kbest;
             // pieces: (tile, first direction, last direction + 1, partial slot or -1)
             struct Piece {
@@ -427,7 +500,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
                 len = std::max(len, v.size());
             }
             std::vector<int64_t> toff2{0};
-            std::vector<int32_t> tdir2, tsrc2, cols2, slot2;
+            std::vector<int32_t> tdir2, cols2, slot2;
             for (int x = 0; x < 8; ++x)
                 for (size_t k = 0; k < len; ++k) {
                     if (k >= per_oct[x].size()) {  // empty work item
@@ -437,19 +510,16 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
                         continue;
                     }
                     const Piece &pc = per_oct[x][k];
-                    for (int e = pc.e0; e < pc.e1; ++e) {
-                        tdir2.push_back(tdir[e]);
-                        tsrc2.insert(tsrc2.end(), tsrc.begin() + (size_t)e * nc, tsrc.begin() + (size_t)(e + 1) * nc);
-                    }
+                    tdir2.insert(tdir2.end(), tdir.begin() + pc.e0, tdir.begin() + pc.e1);
                     toff2.push_back((int64_t)tdir2.size());
                     cols2.insert(cols2.end(), cols.begin() + (size_t)pc.tile * nc, cols.begin() + (size_t)(pc.tile + 1) * nc);
                     slot2.push_back(pc.slot);
                 }
             toff.swap(toff2);
             tdir.swap(tdir2);
-            tsrc.swap(tsrc2);
             cols.swap(cols2);
             ntile = (int)(8 * len);
+            lap("m2l pieces");
             P.m2l_slot = upload(slot2, s);
             P.m2l_nsplit = (int)red_k.size();
             if (nslot > 0) P.m2l_partial.alloc((size_t)nslot * nc * P.r_pad);
@@ -458,19 +528,25 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
                 P.m2l_red_slot0 = upload(red_slot0, s);
                 P.m2l_red_k = upload(red_k, s);
             }
-            // pair tiles: per target vector, its partial rows in direction order
-            std::sort(gather.begin(), gather.end(), [](const GatherE &x, const GatherE &y) {
-                return x.v != y.v ? x.v < y.v : x.dir < y.dir;
-            });
-            std::vector<int32_t> gt, goff{0}, gidx;
-            for (size_t i = 0; i < gather.size(); ++i) {
-                if (i == 0 || gather[i].v != gather[i - 1].v) {
-                    if (i > 0) goff.push_back((int32_t)i);
-                    gt.push_back(gather[i].v);
+            // pair tiles: per target vector, its partial rows in direction
+            // order. A target's pair tiles were made from its octant's pairs
+            // in increasing direction, so they were met in that order above,
+            // and a stable counting sort by target keeps it.
+            std::vector<int32_t> gt, goff{0}, gidx(gather.size());
+            {
+                const int64_t nvec = nb * nrhs;
+                std::vector<int32_t> gstart(nvec + 1, 0);
+                for (const GatherE &g : gather) ++gstart[g.v + 1];
+                for (int64_t v = 0; v < nvec; ++v) {
+                    if (gstart[v + 1]) {
+                        gt.push_back((int32_t)v);
+                        goff.push_back(gstart[v] + gstart[v + 1]);
+                    }
+                    gstart[v + 1] += gstart[v];
                 }
-                gidx.push_back(gather[i].idx);
+                for (const GatherE &g : gather) gidx[gstart[g.v]++] = g.idx;
             }
-            if (!gather.empty()) goff.push_back((int32_t)gather.size());
+            lap("m2l slots and gather lists");
             P.m2l_ngather = (int)gt.size();
             P.m2l_pair_tiles = (int)std::count(pair_tile.begin(), pair_tile.end(), 1);
             if (P.m2l_ngather > 0) {
@@ -479,15 +555,34 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
                 P.m2l_gidx = upload(gidx, s);
             }
         }
+        lap("m2l uploads");
         P.m2l_ntile = ntile;
         P.m2l_steps = (int64_t)tdir.size();
         P.m2l_ncol = nc;
         P.m2l_toff = upload(toff, s);
         P.m2l_dir = upload(tdir, s);
-        P.m2l_src = upload(tsrc, s);
         P.m2l_cols = upload(cols, s);
+        // the source vector of every (step, column), filled on the device
+        {
+            std::vector<int32_t> item(tdir.size());
+            for (int k = 0; k < ntile; ++k)
+                std::fill(item.begin() + toff[k], item.begin() + toff[k + 1], (int32_t)k);
+            DBuf<int32_t> ditem = upload(item, s);
+            P.m2l_src.alloc(tdir.size() * (size_t)nc);
+            const int64_t n = (int64_t)tdir.size() * nc;
+            if (n > 0) {
+                hipLaunchKernelGGL(k_m2l_sources, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, ditem.p,
+                                   P.m2l_dir.p, (int64_t)tdir.size(), P.m2l_cols.p, nc, t.vdense.p, t.sbeg.p,
+                                   t.send.p, nrhs, P.m2l_src.p);
+                FMM_HIP(hipGetLastError());
+            }
+            FMM_HIP(hipStreamSynchronize(s));
+        }
         P.m2l_zero = upload(std::vector<float>(48, 0.f), s);
+        lap("m2l sources");
     }
+    phase_end(5);
+    wl("M2L schedule");
 
     // P2L (X lists of boxes holding more than n_s targets)
     {
@@ -516,6 +611,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         j.src = upload(cols, s);
     }
 
+    wl("P2L lists");
     // L2L, top-down, float64 tiles grouped by octant (one matrix per tile)
     for (int l = 3; l < t.nlev; ++l) {
         std::vector<int32_t> by_oct[8];
@@ -550,6 +646,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         P.l2l_jobs.push_back(std::move(j));
     }
 
+    wl("L2L lists");
     // check-to-equivalent maps and the leaf evaluation lists
     std::vector<int32_t> down_boxes;
     std::vector<uint8_t> up_needed(nb, 0);
@@ -599,6 +696,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         tbox = t.tsm ? boxes_of(tl, t.tbeg, t.tend, t.tx, t.ty, t.tz) : boxes_of(tl, t.sbeg, t.send, t.sx, t.sy, t.sz);
         sboxes = boxes_of(sl, t.sbeg, t.send, t.sx, t.sy, t.sz);
     }
+    wl("leaf bounding boxes");
     const double delta2 = std::max((double)P.opt.cutoff * P.opt.cutoff, (double)std::numeric_limits<float>::min());
     auto needs_test = [&](int64_t b, int32_t a) {
         if (a == b) return true;
@@ -610,56 +708,75 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         }
         return g2 <= 1.1 * delta2;
     };
-    int64_t tested_pairs = 0;
-    for (int64_t b = 0; b < nb; ++b) {
-        if (!leaf(b) || ntrg(b) == 0) continue;
-        std::vector<int32_t> rt, rf;  // ranges that need the test, ranges that do not
+    // per target leaf, in parallel: its point ranges that need the test and
+    // those that do not (each merged), and its W partners evaluated through
+    // their upward surfaces; then concatenated in leaf order
+    std::vector<int32_t> tleaves;
+    for (int64_t b = 0; b < nb; ++b)
+        if (leaf(b) && ntrg(b) > 0) tleaves.push_back((int32_t)b);
+    struct LeafLists {
+        std::vector<int32_t> rt, rf, wsurf;
+    };
+    std::vector<LeafLists> ll(tleaves.size());
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < (int64_t)tleaves.size(); ++i) {
+        const int32_t b = tleaves[i];
+        LeafLists &o = ll[i];
         auto add_src = [&](int32_t a) {
-            if (nsrc(a) > 0) add_range(needs_test(b, a) ? rt : rf, t.h_sbeg[a], t.h_send[a]);
+            if (nsrc(a) > 0) add_range(needs_test(b, a) ? o.rt : o.rf, t.h_sbeg[a], t.h_send[a]);
         };
-        if (lvl(b) >= 2) {
-            down_boxes.push_back((int32_t)b);
-            if (!P.cheb) {  // the Chebyshev L2P is an interpolation (nodes_to_points), not a kernel sum
-                sbox.push_back((int32_t)b);
-                skind.push_back(0);
-                P.surf_evals += ntrg(b) * ns;
-            }
-        }
-        size_t from = prng.size();
         for (int32_t k = U.h_off[b]; k < U.h_off[b + 1]; ++k) add_src(U.h_idx[k]);
         for (int32_t k = W.h_off[b]; k < W.h_off[b + 1]; ++k) {
-            int32_t a = W.h_idx[k];
+            const int32_t a = W.h_idx[k];
             if (nsrc(a) == 0) continue;
-            if (nsrc(a) <= ns) {
+            if (nsrc(a) <= ns)
                 add_src(a);
-            } else {
-                sbox.push_back(a);
-                skind.push_back(1);
-                up_needed[a] = 1;
-                P.surf_evals += ntrg(b) * ns;
-            }
+            else
+                o.wsurf.push_back(a);
         }
         for (int64_t anc = b; anc >= 0; anc = t.h_parent[anc]) {
             if (ntrg(anc) > ns) continue;
             for (int32_t k = X.h_off[anc]; k < X.h_off[anc + 1]; ++k) add_src(X.h_idx[k]);
         }
-        merge_ranges(rt, 0);
-        merge_ranges(rf, 0);
-        prng.insert(prng.end(), rt.begin(), rt.end());
+        merge_ranges(o.rt, 0);
+        merge_ranges(o.rf, 0);
+    }
+    int64_t tested_pairs = 0;
+    for (size_t i = 0; i < tleaves.size(); ++i) {
+        const int32_t b = tleaves[i];
+        const LeafLists &o = ll[i];
+        if (lvl(b) >= 2) {
+            down_boxes.push_back(b);
+            if (!P.cheb) {  // the Chebyshev L2P is an interpolation (nodes_to_points), not a kernel sum
+                sbox.push_back(b);
+                skind.push_back(0);
+                P.surf_evals += ntrg(b) * ns;
+            }
+        }
+        for (int32_t a : o.wsurf) {
+            sbox.push_back(a);
+            skind.push_back(1);
+            up_needed[a] = 1;
+            P.surf_evals += ntrg(b) * ns;
+        }
+        prng.insert(prng.end(), o.rt.begin(), o.rt.end());
         pmid.push_back((int32_t)(prng.size() / 2));
-        prng.insert(prng.end(), rf.begin(), rf.end());
+        prng.insert(prng.end(), o.rf.begin(), o.rf.end());
         int64_t npts = 0, ntest = 0;
-        for (size_t e = from; e < prng.size(); e += 2) npts += prng[e + 1] - prng[e];
-        for (size_t e = 0; e < rt.size(); e += 2) ntest += rt[e + 1] - rt[e];
+        for (size_t e = 0; e < o.rt.size(); e += 2) ntest += o.rt[e + 1] - o.rt[e];
+        npts = ntest;
+        for (size_t e = 0; e < o.rf.size(); e += 2) npts += o.rf[e + 1] - o.rf[e];
         P.p2p_pairs += npts * ntrg(b);
         tested_pairs += ntest * ntrg(b);
         soff.push_back((int32_t)sbox.size());
         poff.push_back((int32_t)(prng.size() / 2));
         for (int64_t t0 = 0; t0 < ntrg(b); t0 += 64) {
-            wleaf.push_back((int32_t)b);
+            wleaf.push_back(b);
             wt0.push_back((int32_t)t0);
         }
     }
+    ll.clear();
+    wl("evaluation lists");
     // soff/poff are indexed by leaf id: expand to all boxes
     {
         std::vector<int32_t> so(nb + 1, 0), po(nb + 1, 0), pm(nb, 0);
@@ -683,6 +800,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
         P.pmid = upload(pm, s);
         P.p2p_tested = tested_pairs;
     }
+    wl("evaluation offsets");
     P.nwork = (int)wleaf.size();
     P.wleaf = upload(wleaf, s);
     P.wt0 = upload(wt0, s);
@@ -756,7 +874,8 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             j.src = upload(cols, s);
         }
     }
-    FMM_HIP(hipStreamSynchronize(s));
+    wl("evaluation uploads, expansion and Chebyshev lists");
+    phase_end(6);
 }
 
 static void run_gemm(GemmJob &j, const double *mats, int m_pad, int k_pad, const float *in, float *out,

@@ -83,6 +83,8 @@ struct Plan {
     int64_t p2m_evals = 0;
     int64_t p2l_evals = 0;
     double setup_ms = 0;
+    // host wall time of the setup phases (ms), in the order of fmm_info.setup_phase_ms
+    double setup_phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int leaf_from_cache = 0;  // leaf_size = 0 resolved from the tuning cache (1) or the default (0)
 
     // captured apply (fmm_set_graph): replayed while the argument pointers match

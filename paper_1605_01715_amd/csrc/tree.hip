@@ -12,6 +12,7 @@
 #include "tree.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 
 namespace fmm {
@@ -98,15 +99,36 @@ bool bbox(const float *a, int64_t n, hipStream_t s, double lo[3], double hi[3]) 
     return ok;
 }
 
-__global__ void k_keys(const float *trg, const float *src, int64_t n_trg, int64_t n, bool tsm, double x0,
-                       double y0, double z0, double scale, uint64_t *keys, int64_t *idx) {
+// Instance of global index j: the last i with off[i] <= j (instances with no
+// points of this kind have off[i] == off[i + 1] and never match).
+__device__ inline int32_t instance_of(const int64_t *off, int ni, int64_t j) {
+    int lo = 0, hi = ni;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= j) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Morton key of combined point i (targets first when tsm) in the root cube of
+// its instance: roots[5 k .. 5 k + 4] = x0, y0, z0, w, 2^21 / w of instance k.
+// inst (with toff / soff) is NULL for a single tree.
+__global__ void k_keys(const float *trg, const float *src, int64_t n_trg, int64_t n, bool tsm, const double *roots,
+                       int ni, const int64_t *toff, const int64_t *soff, uint64_t *keys, int64_t *idx,
+                       int32_t *inst) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const float *p = (tsm && i < n_trg) ? trg + 3 * i : src + 3 * (tsm ? i - n_trg : i);
-    const double org[3] = {x0, y0, z0};
+    const bool is_trg = tsm && i < n_trg;
+    const float *p = is_trg ? trg + 3 * i : src + 3 * (tsm ? i - n_trg : i);
+    int32_t k = 0;
+    if (inst) {
+        k = is_trg ? instance_of(toff, ni, i) : instance_of(soff, ni, tsm ? i - n_trg : i);
+        inst[i] = k;
+    }
+    const double *r = roots + 5 * (int64_t)k;
     uint32_t q[3];
     for (int c = 0; c < 3; ++c) {
-        double v = floor(((double)p[c] - org[c]) * scale);
+        double v = floor(((double)p[c] - r[c]) * r[4]);
         v = v < 0.0 ? 0.0 : v;
         v = v > 2097151.0 ? 2097151.0 : v;
         q[c] = (uint32_t)v;
@@ -115,11 +137,60 @@ __global__ void k_keys(const float *trg, const float *src, int64_t n_trg, int64_
     idx[i] = i;
 }
 
+// forest: instance of the k-th sorted point as a sort key, and the identity
+__global__ void k_inst_keys(const int64_t *order, const int32_t *inst, int64_t n, uint64_t *ik, int64_t *pos) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    ik[k] = (uint64_t)inst[order[k]];
+    pos[k] = k;
+}
+
+__global__ void k_permute_sorted(const int64_t *pos, const uint64_t *keys, const int64_t *order, const uint64_t *ik,
+                                 int64_t n, uint64_t *keys2, int64_t *order2, int32_t *sinst, int32_t *pbox,
+                                 const int32_t *root_of) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int64_t j = pos[k];
+    keys2[k] = keys[j];
+    order2[k] = order[j];
+    sinst[k] = (int32_t)ik[k];
+    pbox[k] = root_of[ik[k]];
+}
+
+// per-instance bounding boxes: one workgroup per instance,
+// out[6 k .. 6 k + 5] = min x, y, z, max x, y, z over a[off[k] .. off[k + 1])
+__global__ __launch_bounds__(kBlock) void k_inst_bbox(const float *a, const int64_t *off, double *out) {
+    __shared__ float sh[6][kBlock];
+    const int k = blockIdx.x;
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = off[k] + threadIdx.x; i < off[k + 1]; i += kBlock)
+        for (int c = 0; c < 3; ++c) {
+            const float v = a[3 * i + c];
+            mn[c] = fminf(mn[c], v);
+            mx[c] = fmaxf(mx[c], v);
+        }
+    for (int c = 0; c < 3; ++c) {
+        sh[c][threadIdx.x] = mn[c];
+        sh[3 + c][threadIdx.x] = mx[c];
+    }
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int c = 0; c < 3; ++c) {
+                sh[c][threadIdx.x] = fminf(sh[c][threadIdx.x], sh[c][threadIdx.x + o]);
+                sh[3 + c][threadIdx.x] = fmaxf(sh[3 + c][threadIdx.x], sh[3 + c][threadIdx.x + o]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[6 * k + threadIdx.x] = (double)sh[threadIdx.x][0];
+}
+
 // first level at which key[i] differs from key[i-1]; 22 if equal
-__global__ void k_difflevel(const uint64_t *key, int64_t n, uint8_t *dl) {
+// (0 where the instance changes, sinst = instance per sorted point or NULL)
+__global__ void k_difflevel(const uint64_t *key, const int32_t *sinst, int64_t n, uint8_t *dl) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    if (i == 0) { dl[0] = 0; return; }
+    if (i == 0 || (sinst && sinst[i] != sinst[i - 1])) { dl[i] = 0; return; }
     uint64_t x = key[i] ^ key[i - 1];
     if (x == 0) { dl[i] = 22; return; }
     int h = 63 - __clzll((long long)x);
@@ -171,25 +242,29 @@ __global__ void k_strip_flag(int32_t *flag, int64_t n) {
     if (i < n) flag[i] &= 1;
 }
 
-// assemble one level's boxes into the global arrays
+// assemble one level's boxes into the global arrays; a box's root cube is its
+// instance's (sinst: instance per sorted point, NULL for a single tree; binst:
+// instance per box, written when not NULL)
 __global__ void k_assemble(const int64_t *lbeg, const int64_t *lend, const int32_t *lpar, int64_t nl, int lvl,
-                           int64_t off, int64_t poff, const uint64_t *keys, double x0, double y0, double z0,
-                           double w, int32_t *level, int32_t *parent, int32_t *anchor, uint64_t *bkey,
-                           int64_t *begin, int64_t *end, double *centre, double *half, int32_t *child) {
+                           int64_t off, int64_t poff, const uint64_t *keys, const int32_t *sinst, const double *roots,
+                           int32_t *level, int32_t *parent, int32_t *anchor, uint64_t *bkey, int64_t *begin,
+                           int64_t *end, double *centre, double *half, int32_t *child, int32_t *binst) {
     int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= nl) return;
     int64_t g = off + c;
     level[g] = lvl;
     begin[g] = lbeg[c];
     end[g] = lend[c];
+    const int32_t ii = sinst ? sinst[lbeg[c]] : 0;
+    if (binst) binst[g] = ii;
+    const double *r = roots + 5 * (int64_t)ii;
     uint64_t pre = lvl ? (keys[lbeg[c]] >> (3 * (kMaxLevel - lvl))) : 0ull;
     bkey[g] = pre;
     uint32_t a[3] = {compact3(pre >> 2), compact3(pre >> 1), compact3(pre)};
-    double bw = w / (double)(1ll << lvl);
-    const double org[3] = {x0, y0, z0};
+    double bw = r[3] / (double)(1ll << lvl);
     for (int k = 0; k < 3; ++k) {
         anchor[3 * g + k] = (int32_t)a[k];
-        centre[3 * g + k] = org[k] + ((double)a[k] + 0.5) * bw;
+        centre[3 * g + k] = r[k] + ((double)a[k] + 0.5) * bw;
     }
     half[g] = 0.5 * bw;
     int32_t p = lvl ? (int32_t)(poff + lpar[c]) : -1;
@@ -290,9 +365,11 @@ struct BoxView {
     const uint64_t *bkey;
     const int64_t *lvl_off;  // device copy [nlev + 1]
     int nlev;
+    const int32_t *inst;     // forest: instance of each box (boxes of a level ordered by instance, then key)
 };
 
-__device__ inline int32_t find_box(const BoxView &v, int lvl, int32_t ax, int32_t ay, int32_t az) {
+// The box of instance `inst` at level lvl with anchor (ax, ay, az), or -1.
+__device__ inline int32_t find_box(const BoxView &v, int lvl, int32_t ax, int32_t ay, int32_t az, int32_t inst) {
     if (lvl >= v.nlev) return -1;
     int32_t lim = 1 << lvl;
     if (ax < 0 || ay < 0 || az < 0 || ax >= lim || ay >= lim || az >= lim) return -1;
@@ -300,9 +377,10 @@ __device__ inline int32_t find_box(const BoxView &v, int lvl, int32_t ax, int32_
     int64_t lo = v.lvl_off[lvl], hi = v.lvl_off[lvl + 1];
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
-        if (v.bkey[mid] < k) lo = mid + 1; else hi = mid;
+        const bool less = v.inst ? (v.inst[mid] < inst || (v.inst[mid] == inst && v.bkey[mid] < k)) : v.bkey[mid] < k;
+        if (less) lo = mid + 1; else hi = mid;
     }
-    return (lo < v.lvl_off[lvl + 1] && v.bkey[lo] == k) ? (int32_t)lo : -1;
+    return (lo < v.lvl_off[lvl + 1] && v.bkey[lo] == k && (!v.inst || v.inst[lo] == inst)) ? (int32_t)lo : -1;
 }
 
 __device__ inline bool adjacent(const BoxView &v, int32_t a, int32_t b) {
@@ -322,7 +400,8 @@ __global__ void k_colleagues(BoxView v, int64_t nb, int32_t *col) {
     int64_t b = t / 27;
     int k = (int)(t % 27);
     int dx = k / 9 - 1, dy = (k / 3) % 3 - 1, dz = k % 3 - 1;
-    col[t] = find_box(v, v.level[b], v.anchor[3 * b] + dx, v.anchor[3 * b + 1] + dy, v.anchor[3 * b + 2] + dz);
+    col[t] = find_box(v, v.level[b], v.anchor[3 * b] + dx, v.anchor[3 * b + 1] + dy, v.anchor[3 * b + 2] + dz,
+                      v.inst ? v.inst[b] : 0);
 }
 
 __constant__ int8_t c_dirs[kNumDirs][3];
@@ -343,7 +422,7 @@ __global__ void k_vdense(BoxView v, int64_t nb, int32_t *vd) {
             int pd = (na[c] >> 1) - (a[c] >> 1);  // parents must be adjacent
             if (na[c] < 0 || pd < -1 || pd > 1) ok = false;
         }
-        if (ok) r = find_box(v, lvl, na[0], na[1], na[2]);
+        if (ok) r = find_box(v, lvl, na[0], na[1], na[2], v.inst ? v.inst[b] : 0);
     }
     vd[t] = r;
 }
@@ -485,201 +564,40 @@ static void derive_root(const double lo[3], const double hi[3], double x0[3], do
 
 namespace {
 
-__global__ void k_offset_copy(const int64_t *in, int64_t n, int64_t off, int64_t *out) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) out[i] = in[i] + off;
-}
-
-}  // namespace
-
-void merge_forest(std::vector<Tree> &parts, const std::vector<int64_t> &src_off, const std::vector<int64_t> &trg_off,
-                  bool src_normals, bool trg_normals, Tree &t, hipStream_t s) {
-    const size_t ni = parts.size();
-    FMM_REQUIRE(ni > 0 && src_off.size() == ni + 1 && trg_off.size() == ni + 1, "merge_forest: bad offsets");
-    t = Tree();
-    t.tsm = parts[0].tsm;
-    for (int c = 0; c < 3; ++c) t.x0[c] = parts[0].x0[c];
-    t.w = parts[0].w;
-    // point offsets of each part in the merged sorted arrays
-    std::vector<int64_t> noff(ni + 1, 0), toff(ni + 1, 0), soff(ni + 1, 0);
-    for (size_t i = 0; i < ni; ++i) {
-        noff[i + 1] = noff[i] + parts[i].n;
-        toff[i + 1] = toff[i] + parts[i].n_trg;
-        soff[i + 1] = soff[i] + parts[i].n_src;
-    }
-    t.n = noff[ni];
-    t.n_trg = toff[ni];
-    t.n_src = soff[ni];
-    // level-major box order: level l holds part 0's level-l boxes, then part 1's, ...
-    int nlev = 0;
-    for (auto &p : parts) nlev = std::max(nlev, p.nlev);
-    t.nlev = nlev;
-    auto cnt = [&](size_t i, int l) { return l < parts[i].nlev ? parts[i].lvl_off[l + 1] - parts[i].lvl_off[l] : 0; };
-    std::vector<std::vector<int64_t>> base(ni, std::vector<int64_t>(std::max(nlev, 1), 0));
-    t.lvl_off.assign(nlev + 1, 0);
-    for (int l = 0; l < nlev; ++l) {
-        int64_t o = t.lvl_off[l];
-        for (size_t i = 0; i < ni; ++i) {
-            base[i][l] = o;
-            o += cnt(i, l);
-        }
-        t.lvl_off[l + 1] = o;
-    }
-    const int64_t nb = t.nb = t.lvl_off[nlev];
-    auto nid = [&](size_t i, int32_t b) -> int32_t {
-        if (b < 0) return -1;
-        const int l = parts[i].h_level[b];
-        return (int32_t)(base[i][l] + (b - parts[i].lvl_off[l]));
+// One pass over all points for a single tree (so == NULL) or a forest of
+// independent instances (instance i: sources [so[i], so[i + 1]) and targets
+// [to[i], to[i + 1]) of the caller's arrays). A forest's points are sorted by
+// (instance, key), each instance quantised in its own root cube, and level 0
+// holds one root per instance with points; the boxes of a level are then
+// ordered by instance and, within one, exactly as in that instance's own
+// tree, and no list links two instances.
+void build_any(Tree &t, const float *src, const float *src_nrm, int64_t n_src, const float *trg,
+               const float *trg_nrm, int64_t n_trg, const TreeOptions &opt, const std::vector<int64_t> *so,
+               const std::vector<int64_t> *to, hipStream_t s) {
+    auto clock0 = std::chrono::steady_clock::now();
+    auto phase_end = [&](int k) {
+        FMM_HIP(hipStreamSynchronize(s));
+        const auto now = std::chrono::steady_clock::now();
+        t.phase_ms[k] += std::chrono::duration<double, std::milli>(now - clock0).count();
+        clock0 = now;
     };
-    t.h_level.resize(nb);
-    t.h_parent.resize(nb);
-    t.h_child.resize(8 * nb);
-    t.h_anchor.resize(3 * nb);
-    t.h_begin.resize(nb);
-    t.h_end.resize(nb);
-    t.h_tbeg.resize(nb);
-    t.h_tend.resize(nb);
-    t.h_sbeg.resize(nb);
-    t.h_send.resize(nb);
-    t.h_leaf.resize(nb);
-    t.h_centre.resize(3 * nb);
-    t.h_half.resize(nb);
-    std::vector<int32_t> vd((size_t)kNumDirs * nb);
-    std::vector<int32_t> host_vd;
-    std::vector<int32_t> new_of_old;  // per part
-    for (size_t i = 0; i < ni; ++i) {
-        Tree &p = parts[i];
-        if (p.nb == 0) continue;
-        host_vd.resize((size_t)kNumDirs * p.nb);
-        d2h(host_vd.data(), p.vdense.p, host_vd.size(), s);
-        for (int64_t b = 0; b < p.nb; ++b) {
-            const int64_t q = nid(i, (int32_t)b);
-            t.h_level[q] = p.h_level[b];
-            t.h_parent[q] = nid(i, p.h_parent[b]);
-            for (int c = 0; c < 8; ++c) t.h_child[8 * q + c] = nid(i, p.h_child[8 * b + c]);
-            for (int c = 0; c < 3; ++c) {
-                t.h_anchor[3 * q + c] = p.h_anchor[3 * b + c];
-                t.h_centre[3 * q + c] = p.h_centre[3 * b + c];
-            }
-            t.h_begin[q] = p.h_begin[b] + noff[i];
-            t.h_end[q] = p.h_end[b] + noff[i];
-            t.h_tbeg[q] = p.h_tbeg[b] + toff[i];
-            t.h_tend[q] = p.h_tend[b] + toff[i];
-            t.h_sbeg[q] = p.h_sbeg[b] + soff[i];
-            t.h_send[q] = p.h_send[b] + soff[i];
-            t.h_leaf[q] = p.h_leaf[b];
-            t.h_half[q] = p.h_half[b];
-            for (int d = 0; d < kNumDirs; ++d)
-                vd[(size_t)q * kNumDirs + d] = nid(i, host_vd[(size_t)b * kNumDirs + d]);
-        }
-    }
-    // lists, rebuilt in the merged box order
-    auto merge_csr = [&](Csr Tree::*which, Csr &out) {
-        std::vector<int32_t> count(nb, 0);
-        std::vector<std::pair<size_t, int32_t>> owner(nb);  // merged box -> (part, old box)
-        for (size_t i = 0; i < ni; ++i)
-            for (int64_t b = 0; b < parts[i].nb; ++b) owner[nid(i, (int32_t)b)] = {i, (int32_t)b};
-        out.h_off.assign(nb + 1, 0);
-        for (int64_t q = 0; q < nb; ++q) {
-            const Csr &c = parts[owner[q].first].*which;
-            const int32_t b = owner[q].second;
-            out.h_off[q + 1] = out.h_off[q] + (c.h_off[b + 1] - c.h_off[b]);
-        }
-        out.h_idx.resize(out.h_off[nb]);
-        for (int64_t q = 0; q < nb; ++q) {
-            const size_t i = owner[q].first;
-            const Csr &c = parts[i].*which;
-            const int32_t b = owner[q].second;
-            int32_t o = out.h_off[q];
-            for (int32_t k = c.h_off[b]; k < c.h_off[b + 1]; ++k) out.h_idx[o++] = nid(i, c.h_idx[k]);
-            // merged ids keep each part's order within a level; keep lists sorted
-            std::sort(out.h_idx.begin() + out.h_off[q], out.h_idx.begin() + out.h_off[q + 1]);
-        }
-        out.total = out.h_off[nb];
-        out.off = upload(out.h_off, s);
-        out.idx = upload(out.h_idx, s);
-    };
-    merge_csr(&Tree::U, t.U);
-    merge_csr(&Tree::V, t.V);
-    merge_csr(&Tree::W, t.W);
-    merge_csr(&Tree::X, t.X);
-
-    // device box arrays
-    t.level = upload(t.h_level, s);
-    t.parent = upload(t.h_parent, s);
-    t.child = upload(t.h_child, s);
-    t.anchor = upload(t.h_anchor, s);
-    t.begin = upload(t.h_begin, s);
-    t.end = upload(t.h_end, s);
-    t.tbeg = upload(t.h_tbeg, s);
-    t.tend = upload(t.h_tend, s);
-    t.sbeg = upload(t.h_sbeg, s);
-    t.send = upload(t.h_send, s);
-    t.leaf = upload(t.h_leaf, s);
-    t.centre = upload(t.h_centre, s);
-    t.half = upload(t.h_half, s);
-    t.vdense = upload(vd, s);
-
-    // sorted point data, concatenated; permutations shifted to the caller's indices
-    auto cat_f = [&](DBuf<float> Tree::*m, int64_t total, const std::vector<int64_t> &off, DBuf<float> &out) {
-        out.alloc(total);
-        for (size_t i = 0; i < ni; ++i) {
-            const DBuf<float> &b = parts[i].*m;
-            const int64_t n = off[i + 1] - off[i];
-            if (n && b.p) FMM_HIP(hipMemcpyAsync(out.p + off[i], b.p, n * sizeof(float), hipMemcpyDeviceToDevice, s));
-        }
-    };
-    auto cat_perm = [&](DBuf<int64_t> Tree::*m, int64_t total, const std::vector<int64_t> &off,
-                        const std::vector<int64_t> &user_off, DBuf<int64_t> &out) {
-        out.alloc(total);
-        for (size_t i = 0; i < ni; ++i) {
-            const int64_t n = off[i + 1] - off[i];
-            if (!n) continue;
-            hipLaunchKernelGGL(k_offset_copy, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, (parts[i].*m).p, n,
-                               user_off[i], out.p + off[i]);
-            FMM_HIP(hipGetLastError());
-        }
-    };
-    cat_f(&Tree::sx, t.n_src, soff, t.sx);
-    cat_f(&Tree::sy, t.n_src, soff, t.sy);
-    cat_f(&Tree::sz, t.n_src, soff, t.sz);
-    if (src_normals) {
-        cat_f(&Tree::snx, t.n_src, soff, t.snx);
-        cat_f(&Tree::sny, t.n_src, soff, t.sny);
-        cat_f(&Tree::snz, t.n_src, soff, t.snz);
-    }
-    cat_perm(&Tree::src_perm, t.n_src, soff, src_off, t.src_perm);
-    if (t.tsm) {
-        cat_f(&Tree::tx, t.n_trg, toff, t.tx);
-        cat_f(&Tree::ty, t.n_trg, toff, t.ty);
-        cat_f(&Tree::tz, t.n_trg, toff, t.tz);
-        cat_perm(&Tree::trg_perm, t.n_trg, toff, trg_off, t.trg_perm);
-    }
-    if (trg_normals) {
-        cat_f(&Tree::tnx, t.n_trg, toff, t.tnx);
-        cat_f(&Tree::tny, t.n_trg, toff, t.tny);
-        cat_f(&Tree::tnz, t.n_trg, toff, t.tnz);
-    }
-    t.keys.alloc(t.n);
-    for (size_t i = 0; i < ni; ++i)
-        if (parts[i].n)
-            FMM_HIP(hipMemcpyAsync(t.keys.p + noff[i], parts[i].keys.p, parts[i].n * sizeof(uint64_t),
-                                   hipMemcpyDeviceToDevice, s));
-    FMM_HIP(hipStreamSynchronize(s));
-    parts.clear();
-}
-
-void build_tree(Tree &t, const float *src, const float *src_nrm, int64_t n_src, const float *trg,
-                const float *trg_nrm, int64_t n_trg, const TreeOptions &opt, hipStream_t s) {
     t.tsm = trg != nullptr;
     t.n_src = n_src;
     t.n_trg = t.tsm ? n_trg : n_src;
     t.n = t.tsm ? n_trg + n_src : n_src;
     const int64_t n = t.n;
+    const bool forest = so != nullptr;
+    const int ni = forest ? (int)so->size() - 1 : 1;
 
-    // root cube
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    // root cubes, one per instance: [5 k .. 5 k + 4] = x0, y0, z0, w, 2^21 / w
+    std::vector<double> roots(5 * (size_t)ni);
+    auto set_root = [&](int k, const double x0[3], double w) {
+        for (int c = 0; c < 3; ++c) roots[5 * k + c] = x0[c];
+        roots[5 * k + 3] = w;
+        roots[5 * k + 4] = 2097152.0 / w;
+    };
     {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         double l1[3], h1[3];
         FMM_REQUIRE(bbox(src, n_src, s, l1, h1), "fmm_setup: non-finite source coordinates");
         for (int c = 0; c < 3; ++c) { lo[c] = std::min(lo[c], l1[c]); hi[c] = std::max(hi[c], h1[c]); }
@@ -689,46 +607,128 @@ void build_tree(Tree &t, const float *src, const float *src_nrm, int64_t n_src, 
         }
         if (src_nrm) FMM_REQUIRE(all_finite(src_nrm, 3 * n_src, s), "fmm_setup: non-finite source normals");
         if (trg_nrm) FMM_REQUIRE(all_finite(trg_nrm, 3 * t.n_trg, s), "fmm_setup: non-finite target normals");
+        const double unit[3] = {0.0, 0.0, 0.0};
+        if (opt.root[3] > 0.0) {
+            for (int k = 0; k < ni; ++k) set_root(k, opt.root, opt.root[3]);
+        } else if (!forest) {
+            double x0[3], w = 1.0;
+            if (n == 0) {
+                for (int c = 0; c < 3; ++c) x0[c] = 0.0;
+            } else {
+                derive_root(lo, hi, x0, w);
+            }
+            set_root(0, x0, w);
+        } else {
+            // per-instance boxes over the instance's sources and targets
+            std::vector<double> bs(6 * (size_t)ni), bt(6 * (size_t)ni);
+            auto inst_boxes = [&](const float *a, const std::vector<int64_t> &off, std::vector<double> &out) {
+                DBuf<int64_t> doff = upload(off, s);
+                DBuf<double> d(out.size());
+                hipLaunchKernelGGL(k_inst_bbox, dim3(ni), dim3(kBlock), 0, s, a, doff.p, d.p);
+                FMM_HIP(hipGetLastError());
+                d2h(out.data(), d.p, out.size(), s);
+            };
+            inst_boxes(src, *so, bs);
+            if (t.tsm) inst_boxes(trg, *to, bt);
+            for (int k = 0; k < ni; ++k) {
+                const int64_t nk = ((*so)[k + 1] - (*so)[k]) + (t.tsm ? (*to)[k + 1] - (*to)[k] : 0);
+                if (nk == 0) {
+                    set_root(k, unit, 1.0);
+                    continue;
+                }
+                double l2[3], h2[3];
+                for (int c = 0; c < 3; ++c) {
+                    l2[c] = INFINITY;
+                    h2[c] = -INFINITY;
+                    if ((*so)[k + 1] > (*so)[k]) {
+                        l2[c] = std::min(l2[c], bs[6 * k + c]);
+                        h2[c] = std::max(h2[c], bs[6 * k + 3 + c]);
+                    }
+                    if (t.tsm && (*to)[k + 1] > (*to)[k]) {
+                        l2[c] = std::min(l2[c], bt[6 * k + c]);
+                        h2[c] = std::max(h2[c], bt[6 * k + 3 + c]);
+                    }
+                }
+                double x0[3], w = 1.0;
+                derive_root(l2, h2, x0, w);
+                set_root(k, x0, w);
+            }
+        }
     }
-    if (opt.root[3] > 0.0) {
-        for (int c = 0; c < 3; ++c) t.x0[c] = opt.root[c];
-        t.w = opt.root[3];
-    } else if (n == 0) {
-        t.x0[0] = t.x0[1] = t.x0[2] = 0.0;
-        t.w = 1.0;
-    } else {
-        derive_root(lo, hi, t.x0, t.w);
-    }
+    // the root reported is instance 0's
+    for (int c = 0; c < 3; ++c) t.x0[c] = roots[c];
+    t.w = roots[3];
     t.nlev = 0;
     t.nb = 0;
     t.lvl_off.assign(1, 0);
     if (n == 0) return;
 
-    // keys and Morton sort
+    // keys and Morton sort (a forest: then stably by instance)
+    DBuf<double> droots = upload(roots, s);
     t.keys.alloc(n);
     t.order.alloc(n);
-    double scale = 2097152.0 / t.w;
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, trg, src, n_trg, n, t.tsm, t.x0[0],
-                       t.x0[1], t.x0[2], scale, t.keys.p, t.order.p);
+    DBuf<int32_t> pinst, sinst;
+    DBuf<int64_t> dso, dto;
+    if (forest) {
+        pinst.alloc(n);
+        dso = upload(*so, s);
+        dto = upload(*to, s);
+    }
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, trg, src, n_trg, n, t.tsm, droots.p, ni,
+                       dto.p, dso.p, t.keys.p, t.order.p, pinst.p);
     FMM_HIP(hipGetLastError());
     radix_sort_pairs(t.keys.p, t.order.p, n, 63, s);
+    DBuf<int32_t> pbox(n);
+    // level 0: one root per instance with points, over its run of sorted points
+    std::vector<int64_t> b0, e0;
+    if (forest) {
+        std::vector<int32_t> root_of(ni, -1);
+        int64_t at = 0;
+        for (int k = 0; k < ni; ++k) {
+            const int64_t nk = ((*so)[k + 1] - (*so)[k]) + (t.tsm ? (*to)[k + 1] - (*to)[k] : 0);
+            if (nk == 0) continue;
+            root_of[k] = (int32_t)b0.size();
+            b0.push_back(at);
+            e0.push_back(at + nk);
+            at += nk;
+        }
+        int bits = 1;
+        while ((1 << bits) < ni) ++bits;
+        DBuf<uint64_t> ik(n), keys2(n);
+        DBuf<int64_t> pos(n), order2(n);
+        hipLaunchKernelGGL(k_inst_keys, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, t.order.p, pinst.p, n, ik.p,
+                           pos.p);
+        FMM_HIP(hipGetLastError());
+        radix_sort_pairs(ik.p, pos.p, n, bits, s);
+        DBuf<int32_t> droot_of = upload(root_of, s);
+        sinst.alloc(n);
+        hipLaunchKernelGGL(k_permute_sorted, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, pos.p, t.keys.p, t.order.p,
+                           ik.p, n, keys2.p, order2.p, sinst.p, pbox.p, droot_of.p);
+        FMM_HIP(hipGetLastError());
+        std::swap(t.keys, keys2);
+        std::swap(t.order, order2);
+        FMM_HIP(hipStreamSynchronize(s));  // the temporaries are freed on return from this block
+    } else {
+        b0 = {0};
+        e0 = {n};
+        FMM_HIP(hipMemsetAsync(pbox.p, 0, n * sizeof(int32_t), s));  // every point is in the root
+    }
+    phase_end(0);
 
     // level-by-level build
     DBuf<uint8_t> dl(n);
-    hipLaunchKernelGGL(k_difflevel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, t.keys.p, n, dl.p);
+    hipLaunchKernelGGL(k_difflevel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, t.keys.p, sinst.p, n, dl.p);
     FMM_HIP(hipGetLastError());
-    DBuf<int32_t> pbox(n), npbox(n), flag(n), cidx(n);
-    FMM_HIP(hipMemsetAsync(pbox.p, 0, n * sizeof(int32_t), s));  // every point is in the root
+    DBuf<int32_t> npbox(n), flag(n), cidx(n);
     std::vector<DBuf<int64_t>> lbeg, lend;
     std::vector<DBuf<int32_t>> lpar;
     {
-        std::vector<int64_t> b0 = {0}, e0 = {n};
         lbeg.push_back(upload(b0, s));
         lend.push_back(upload(e0, s));
-        lpar.emplace_back(DBuf<int32_t>(1));
-        FMM_HIP(hipMemsetAsync(lpar[0].p, 0xff, sizeof(int32_t), s));
+        lpar.emplace_back(DBuf<int32_t>(b0.size()));
+        FMM_HIP(hipMemsetAsync(lpar[0].p, 0xff, b0.size() * sizeof(int32_t), s));
     }
-    std::vector<int64_t> counts = {1};
+    std::vector<int64_t> counts = {(int64_t)b0.size()};
     for (int lvl = 0; lvl < kMaxLevel; ++lvl) {
         hipLaunchKernelGGL(k_split_flags, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, pbox.p, dl.p,
                            lbeg[lvl].p, lend[lvl].p, n, lvl, opt.uniform_depth, opt.leaf_size, opt.max_depth,
@@ -769,13 +769,14 @@ void build_tree(Tree &t, const float *src, const float *src_nrm, int64_t n_src, 
     t.centre.alloc(3 * nb);
     t.half.alloc(nb);
     t.leaf.alloc(nb);
+    if (forest) t.binst.alloc(nb);
     FMM_HIP(hipMemsetAsync(t.child.p, 0xff, 8 * nb * sizeof(int32_t), s));
     for (int l = 0; l < t.nlev; ++l) {
         int64_t nl = counts[l];
         hipLaunchKernelGGL(k_assemble, dim3(grid_for(nl, kBlock)), dim3(kBlock), 0, s, lbeg[l].p, lend[l].p,
-                           lpar[l].p, nl, l, t.lvl_off[l], l ? t.lvl_off[l - 1] : 0, t.keys.p, t.x0[0], t.x0[1],
-                           t.x0[2], t.w, t.level.p, t.parent.p, t.anchor.p, t.bkey.p, t.begin.p, t.end.p,
-                           t.centre.p, t.half.p, t.child.p);
+                           lpar[l].p, nl, l, t.lvl_off[l], l ? t.lvl_off[l - 1] : 0, t.keys.p, sinst.p, droots.p,
+                           t.level.p, t.parent.p, t.anchor.p, t.bkey.p, t.begin.p, t.end.p, t.centre.p, t.half.p,
+                           t.child.p, t.binst.p);
         FMM_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_leaf, dim3(grid_for(nb, kBlock)), dim3(kBlock), 0, s, t.child.p, nb, t.leaf.p);
@@ -842,10 +843,13 @@ void build_tree(Tree &t, const float *src, const float *src_nrm, int64_t n_src, 
         }
     }
 
+    phase_end(1);
+
     // ---- lists
     DBuf<int64_t> d_lvl_off = upload(t.lvl_off, s);
     t.colleague.alloc(27 * nb);
-    BoxView v{t.level.p, t.anchor.p, t.child.p, t.parent.p, t.colleague.p, t.leaf.p, t.bkey.p, d_lvl_off.p, t.nlev};
+    BoxView v{t.level.p, t.anchor.p,  t.child.p,  t.parent.p, t.colleague.p,
+              t.leaf.p,  t.bkey.p,    d_lvl_off.p, t.nlev,    t.binst.p};
     hipLaunchKernelGGL(k_colleagues, dim3(grid_for(27 * nb, kBlock)), dim3(kBlock), 0, s, v, nb, t.colleague.p);
     FMM_HIP(hipGetLastError());
     {
@@ -926,6 +930,22 @@ void build_tree(Tree &t, const float *src, const float *src_nrm, int64_t n_src, 
     d2h(t.h_centre.data(), t.centre.p, 3 * nb, s);
     t.h_half.resize(nb);
     d2h(t.h_half.data(), t.half.p, nb, s);
+    phase_end(2);
+}
+
+}  // namespace
+
+void build_tree(Tree &t, const float *src, const float *src_nrm, int64_t n_src, const float *trg,
+                const float *trg_nrm, int64_t n_trg, const TreeOptions &opt, hipStream_t s) {
+    build_any(t, src, src_nrm, n_src, trg, trg_nrm, n_trg, opt, nullptr, nullptr, s);
+}
+
+void build_forest(Tree &t, const std::vector<int64_t> &src_off, const std::vector<int64_t> &trg_off,
+                  const float *src, const float *src_nrm, const float *trg, const float *trg_nrm,
+                  const TreeOptions &opt, hipStream_t s) {
+    FMM_REQUIRE(src_off.size() >= 2 && trg_off.size() == src_off.size(), "build_forest: bad offsets");
+    const int64_t n_src = src_off.back(), n_trg = trg ? trg_off.back() : 0;
+    build_any(t, src, src_nrm, n_src, trg, trg_nrm, n_trg, opt, &src_off, &trg_off, s);
 }
 
 }  // namespace fmm

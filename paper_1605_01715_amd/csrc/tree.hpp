@@ -39,6 +39,7 @@ struct Tree {
     DBuf<uint64_t> bkey;                 // Morton prefix of the box at its level
     DBuf<int64_t> begin, end, tbeg, tend, sbeg, send;
     DBuf<uint8_t> leaf;
+    DBuf<int32_t> binst;  // forest: instance of each box (empty for a single tree)
     DBuf<double> centre;  // [nb][3]
     DBuf<double> half;    // [nb]
 
@@ -57,6 +58,10 @@ struct Tree {
     DBuf<int64_t> src_perm, trg_perm;
     DBuf<float> sx, sy, sz, snx, sny, snz;
     DBuf<float> tx, ty, tz, tnx, tny, tnz;
+
+    // host wall time of the three phases of build_tree (ms): keys and sort,
+    // octree levels and sorted point data, lists and host copies
+    double phase_ms[3] = {0, 0, 0};
 };
 
 // Build the tree and lists. Pointers are device [n][3] float arrays; trg may be
@@ -64,15 +69,17 @@ struct Tree {
 void build_tree(Tree &t, const float *src, const float *src_nrm, int64_t n_src, const float *trg,
                 const float *trg_nrm, int64_t n_trg, const TreeOptions &opt, hipStream_t s);
 
-// Forest of independent instances: `parts` are trees built separately on
-// consecutive slices of the caller's arrays (part i's sources start at user
-// index src_off[i], its targets at trg_off[i]). The result is one tree whose
-// boxes are ordered by level, then by instance, with every index (boxes,
-// point ranges, permutations back to the caller's order) shifted so the plan
-// treats the batch as one box set; no list ever links two instances. The
-// root cube reported is part 0's. `parts` is consumed.
-void merge_forest(std::vector<Tree> &parts, const std::vector<int64_t> &src_off, const std::vector<int64_t> &trg_off,
-                  bool src_normals, bool trg_normals, Tree &out, hipStream_t s);
+// Forest of independent instances in one pass: instance i owns the caller's
+// sources [src_off[i], src_off[i + 1]) and targets [trg_off[i], trg_off[i + 1])
+// (trg NULL: targets = sources, trg_off ignored), each with its own root cube.
+// The result is one tree whose boxes are ordered by level, then by instance,
+// each instance's boxes, points and lists exactly those of a tree built on it
+// alone (box and point indices shifted); permutations refer to the caller's
+// whole arrays, and no list links two instances. The root cube reported is
+// instance 0's.
+void build_forest(Tree &t, const std::vector<int64_t> &src_off, const std::vector<int64_t> &trg_off,
+                  const float *src, const float *src_nrm, const float *trg, const float *trg_nrm,
+                  const TreeOptions &opt, hipStream_t s);
 
 // Device check that coordinates (and normals) are finite; returns false if not.
 bool all_finite(const float *a, int64_t n3, hipStream_t s);

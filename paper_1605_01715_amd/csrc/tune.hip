@@ -18,8 +18,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <fstream>
 #include <mutex>
 #include <sstream>
@@ -64,6 +66,23 @@ bool json_number_field(const std::string &line, const std::string &name, double 
 }
 
 }  // namespace
+
+bool log_enabled() {
+    static const bool on = [] {
+        const char *v = std::getenv("FMM_LOG");
+        return v != nullptr && *v != 0 && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+void log_printf(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    std::fputs("[fmm] ", stderr);
+    std::vfprintf(stderr, fmt, ap);
+    va_end(ap);
+    std::fflush(stderr);
+}
 
 std::string tune_cache_path() {
     if (const char *p = std::getenv("FMM_TUNE_CACHE")) return p;
