@@ -366,9 +366,11 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
                     oct2.push_back(tile_oct[tl]);
                     pair2.push_back(0);
                 }
-                // per octant, the (direction, target) pairs ordered by direction,
-                // then target: a counting sort over the directions of the
-                // targets taken in increasing order
+                // per octant (in parallel), the (direction, target) pairs ordered
+                // by direction, then target: a counting sort over the directions
+                // of the targets taken in increasing order
+                std::vector<std::vector<int32_t>> pdir(8), pcols(8);
+#pragma omp parallel for schedule(dynamic, 1)
                 for (int o = 0; o < 8; ++o) {
                     std::vector<int32_t> &sv = sparse[o];
                     std::sort(sv.begin(), sv.end());
@@ -391,12 +393,18 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
                     for (int d = 0; d < kNumDirs; ++d)
                         for (int64_t i = start[d]; i < start[d + 1]; i += nc) {
                             const int64_t j = std::min(start[d + 1], i + nc);
-                            tdir2.push_back(d);
-                            for (int64_t q = i; q < i + nc; ++q) cols2.push_back(q < j ? by_dir[q] : -1);
-                            toff2.push_back((int64_t)tdir2.size());
-                            oct2.push_back(o);
-                            pair2.push_back(1);
+                            pdir[o].push_back(d);
+                            for (int64_t q = i; q < i + nc; ++q) pcols[o].push_back(q < j ? by_dir[q] : -1);
                         }
+                }
+                for (int o = 0; o < 8; ++o) {
+                    for (int32_t d : pdir[o]) {
+                        tdir2.push_back(d);
+                        toff2.push_back((int64_t)tdir2.size());
+                        oct2.push_back(o);
+                        pair2.push_back(1);
+                    }
+                    cols2.insert(cols2.end(), pcols[o].begin(), pcols[o].end());
                 }
                 toff.swap(toff2);
                 tdir.swap(tdir2);
@@ -423,12 +431,14 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             const int slots = 32 * m2l_blocks_per_cu(P.m2l_form, P.r_pad);  // concurrent workgroups per XCD
             auto ndir = [&](int tl) { return (int)(toff[tl + 1] - toff[tl]); };
             // makespan of one XCD in steps, with a cost of 2 directions per piece of a cut tile
+            std::vector<std::vector<int>> tiles_of(8);
+            for (int tl = 0; tl < ntile; ++tl) tiles_of[tile_oct[tl]].push_back(tl);
             auto makespan = [&](int k) {
                 double worst = 0.0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(max : worst)
                 for (int x = 0; x < 8; ++x) {
                     std::vector<double> w;
-                    for (int tl = 0; tl < ntile; ++tl) {
-                        if (tile_oct[tl] != x) continue;
+                    for (int tl : tiles_of[x]) {
                         const int kk = std::min(k, ndir(tl));
                         for (int q = 0; q < kk; ++q) w.push_back((double)ndir(tl) / kk + (kk > 1 ? 2.0 : 0.0));
                     }
@@ -499,22 +509,32 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
                 std::stable_sort(v.begin(), v.end(), [](const Piece &x, const Piece &y) { return x.e1 - x.e0 > y.e1 - y.e0; });
                 len = std::max(len, v.size());
             }
-            std::vector<int64_t> toff2{0};
-            std::vector<int32_t> tdir2, cols2, slot2;
-            for (int x = 0; x < 8; ++x)
+            // work item x * len + k is piece k of octant x (empty past the
+            // octant's last piece); each octant's block is filled in parallel
+            std::vector<int64_t> sbase(9, 0);
+            for (int x = 0; x < 8; ++x) {
+                int64_t n = 0;
+                for (const Piece &pc : per_oct[x]) n += pc.e1 - pc.e0;
+                sbase[x + 1] = sbase[x] + n;
+            }
+            std::vector<int64_t> toff2(8 * len + 1, 0);
+            std::vector<int32_t> tdir2(sbase[8]), cols2(8 * len * (size_t)nc, -1), slot2(8 * len, -1);
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int x = 0; x < 8; ++x) {
+                int64_t e = sbase[x];
                 for (size_t k = 0; k < len; ++k) {
-                    if (k >= per_oct[x].size()) {  // empty work item
-                        toff2.push_back((int64_t)tdir2.size());
-                        cols2.insert(cols2.end(), (size_t)nc, -1);
-                        slot2.push_back(-1);
-                        continue;
+                    const size_t item = (size_t)x * len + k;
+                    if (k < per_oct[x].size()) {
+                        const Piece &pc = per_oct[x][k];
+                        std::copy(tdir.begin() + pc.e0, tdir.begin() + pc.e1, tdir2.begin() + e);
+                        e += pc.e1 - pc.e0;
+                        std::copy(cols.begin() + (size_t)pc.tile * nc, cols.begin() + (size_t)(pc.tile + 1) * nc,
+                                  cols2.begin() + item * nc);
+                        slot2[item] = pc.slot;
                     }
-                    const Piece &pc = per_oct[x][k];
-                    tdir2.insert(tdir2.end(), tdir.begin() + pc.e0, tdir.begin() + pc.e1);
-                    toff2.push_back((int64_t)tdir2.size());
-                    cols2.insert(cols2.end(), cols.begin() + (size_t)pc.tile * nc, cols.begin() + (size_t)(pc.tile + 1) * nc);
-                    slot2.push_back(pc.slot);
+                    toff2[item + 1] = e;
                 }
+            }
             toff.swap(toff2);
             tdir.swap(tdir2);
             cols.swap(cols2);
