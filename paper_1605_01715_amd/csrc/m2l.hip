@@ -188,7 +188,7 @@ __global__ __launch_bounds__(NW * 64, 2) void k_m2l(M2LLaunch a) {
     };
     if (nact > 0) {
         fetch_src(0, cur_sv, cur_own);
-        fetch_src(min(1, nact - 1), nxt_sv, nxt_own);
+        fetch_src(nact > 1 ? 1 : 0, nxt_sv, nxt_own);
     }
     __syncthreads();  // s_dir
 
@@ -227,16 +227,15 @@ __global__ __launch_bounds__(NW * 64, 2) void k_m2l(M2LLaunch a) {
             copy_to_lds(src, &sB[BUF][i * 1024]);
         }
         live_q[BUF] = __ballot(cur_own >= 0) != 0;  // does this wave's column block have any source?
-        if (++st_ld == NGR) {
-            st_ld = 0;
-            ++e_ld;
-#pragma unroll
-            for (int j = 0; j < JB; ++j) cur_sv[j] = nxt_sv[j];
-            cur_own = nxt_own;
-            if (NGR == 1) fetch_src(min(e_ld + 1, nact - 1), nxt_sv, nxt_own);
-        } else if (st_ld == 1) {
-            fetch_src(min(e_ld + 1, nact - 1), nxt_sv, nxt_own);
+        // k-chunk major: every direction of the tile at chunk kc, then chunk kc + 1
+        if (++e_ld == nact) {
+            e_ld = 0;
+            ++st_ld;
         }
+#pragma unroll
+        for (int j = 0; j < JB; ++j) cur_sv[j] = nxt_sv[j];
+        cur_own = nxt_own;
+        fetch_src(e_ld + 1 < nact ? e_ld + 1 : 0, nxt_sv, nxt_own);
     };
 
     // Operand fragments of one step. The two buffers are distinct LDS

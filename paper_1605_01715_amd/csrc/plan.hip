@@ -15,6 +15,7 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <limits>
 #include <queue>
 
@@ -56,6 +57,47 @@ __global__ __launch_bounds__(64) void k_point_boxes(const int32_t *boxes, const 
 }
 
 constexpr int kMaskWords = (kNumDirs + 63) / 64;
+
+// The order in which a tile runs its directions. The targets of a tile share
+// one octant, hence one parity per axis, so the sources of two directions
+// overlap only when the offsets differ by even amounts in every axis. The
+// offsets are therefore grouped by parity class and, within a class, visited
+// in a boustrophedon over (i, j, k) with steps of two, so that consecutive
+// directions mostly differ by 2 along one axis and the kernel's consecutive
+// steps (one k-chunk of every direction, then the next chunk) re-read most
+// of the previous step's source chunks from L2.
+const std::vector<int> &m2l_direction_order() {
+    static const std::vector<int> order = [] {
+        int idx[7][7][7];
+        int k = 0;
+        for (int i = -3; i <= 3; ++i)
+            for (int j = -3; j <= 3; ++j)
+                for (int l = -3; l <= 3; ++l)
+                    idx[i + 3][j + 3][l + 3] =
+                        std::max(std::abs(i), std::max(std::abs(j), std::abs(l))) >= 2 ? k++ : -1;
+        std::vector<int> out;
+        for (int cls = 0; cls < 8; ++cls) {
+            const int pi = cls >> 2, pj = (cls >> 1) & 1, pl = cls & 1;
+            bool flip_j = false, flip_l = false;
+            for (int i = -3; i <= 3; ++i) {
+                if ((i & 1) != pi) continue;
+                for (int jj = 0; jj < 7; ++jj) {
+                    const int j = flip_j ? 3 - jj : jj - 3;
+                    if ((j & 1) != pj) continue;
+                    for (int ll = 0; ll < 7; ++ll) {
+                        const int l = flip_l ? 3 - ll : ll - 3;
+                        if ((l & 1) != pl) continue;
+                        if (idx[i + 3][j + 3][l + 3] >= 0) out.push_back(idx[i + 3][j + 3][l + 3]);
+                    }
+                    flip_l = !flip_l;
+                }
+                flip_j = !flip_j;
+            }
+        }
+        return out;
+    }();
+    return order;
+}
 
 // Host wall time since the previous call (or construction), logged with FMM_LOG.
 struct Lap {
@@ -316,10 +358,14 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             }
         }
         lap("m2l direction counts");
+        // A tile's directions are run in the order of m2l_direction_order():
+        // by parity class, so that the sources of consecutive directions
+        // (the tile's targets shifted by the two offsets) overlap
+        const std::vector<int> &dorder = m2l_direction_order();
         std::vector<int64_t> toff{0};
         std::vector<int32_t> tdir;
         for (int tl = 0; tl < ntile; ++tl) {
-            for (int d = 0; d < kNumDirs; ++d)
+            for (int d : dorder)
                 if (tcnt[(size_t)tl * kNumDirs + d]) tdir.push_back(d);
             toff.push_back((int64_t)tdir.size());
         }
