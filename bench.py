@@ -175,7 +175,86 @@ def roofline(res, precision, n, cfg):
         others["M2L"]["note"] = ("stage time on the caller's stream: the translation kernel, its reduction and "
                                  "gather, which run beside the leaf evaluation on the plan's second stream")
         others["P2L"]["note"] = "runs on the plan's second stream beside P2M and M2M"
+    else:
+        # the surface form's P2L is the first work on the caller's stream after the fork: its stage time is
+        # mostly queueing behind the leaf evaluation's workgroups, not a kernel time
+        others["P2L"].update({"achieved_tflops": None, "frac": None,
+                              "note": "stage time includes queueing behind the leaf evaluation on the second "
+                                      "stream; the kernel time is in the rocprofv3 trace"})
     return out, others
+
+
+def setup_batch(F, W, torch, dev, reps):
+    """Batched setup of the ferromagnet batch against separate setups of its instances."""
+    import numpy as np
+
+    insts = W.ferro_batch(256)
+    so = np.concatenate([[0], np.cumsum([len(i["src"]) for i in insts])])
+    to = np.concatenate([[0], np.cumsum([len(i["trg"]) for i in insts])])
+    src = torch.from_numpy(np.concatenate([i["src"] for i in insts])).to(dev)
+    nrm = torch.from_numpy(np.concatenate([i["normals"] for i in insts])).to(dev)
+    trg = torch.from_numpy(np.concatenate([i["trg"] for i in insts])).to(dev)
+    opts = F.fmm_default_options(order=8, leaf_size=128, src_kernels=F.FMM_SRC_DOUBLE, nrhs=3,
+                                 precision=F.FMM_PREC_SPLIT_BF16X3, basis=F.FMM_BASIS_CHEBYSHEV, pinv_eps=1e-8)
+    F.fmm_destroy(F.fmm_setup(src[:1000], nrm[:1000], options=opts))  # operators built once
+    out = []
+    for rep in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = F.fmm_setup_batch(so, src, nrm, to, trg, options=opts)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        info = F.fmm_plan_info(plan)
+        F.fmm_destroy(plan)
+        phases = {}
+        t0 = time.perf_counter()
+        for i in range(len(insts)):
+            p = F.fmm_setup(src[so[i]:so[i + 1]], nrm[so[i]:so[i + 1]], trg[to[i]:to[i + 1]], options=opts)
+            for k, v in F.fmm_plan_info(p)["setup_phase_ms"].items():
+                phases[k] = phases.get(k, 0.0) + v
+            F.fmm_destroy(p)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        out.append({"batched_s": round(tb, 3), "separate_s": round(ts, 3), "boxes": info["n_boxes"],
+                    "batched_phases_ms": {k: round(v, 1) for k, v in info["setup_phase_ms"].items()},
+                    "separate_phases_ms_sum": {k: round(v, 1) for k, v in phases.items()}})
+        log(f"bench: batched setup {tb:.3f} s, 256 separate setups {ts:.3f} s")
+    # GMRES on single instances of the batch: the interior Dirichlet problem of the double layer on the
+    # instance's surface (centroids with their areas as weights, diagonal -1/2 on the flat faces),
+    # boundary data 1 / |x - r0| from a point r0 outside
+    solves = []
+    for i in (8, 118):
+        xs, ns = src[so[i]:so[i + 1]], nrm[so[i]:so[i + 1]]
+        n = int(xs.shape[0])
+        o1 = F.fmm_default_options(order=8, leaf_size=128, src_kernels=F.FMM_SRC_DOUBLE,
+                                   precision=F.FMM_PREC_SPLIT_BF16X3, basis=F.FMM_BASIS_CHEBYSHEV, pinv_eps=1e-8)
+        plan = F.fmm_setup(xs, ns, options=o1)
+        a = torch.full((n,), -0.5, device=dev)
+        w = torch.from_numpy(insts[i]["weights"]).to(dev)
+        r0 = torch.tensor(insts[i]["centre"] + 4.0, dtype=torch.float64, device=dev)
+        b = 1.0 / torch.linalg.norm(xs.double() - r0, dim=1)
+        mu = torch.ones(n, device=dev)
+        pot = torch.empty(n, device=dev)
+        for _ in range(3):
+            F.fmm_apply(plan, mu=mu, pot=pot)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            F.fmm_apply(plan, mu=mu, pot=pot)
+        torch.cuda.synchronize()
+        t_apply = (time.perf_counter() - t0) / 20
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, it, rr = F.gmres_solve(plan, F.FMM_OP_FK, a, None, w, b, x, rtol=1e-6)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        F.fmm_destroy(plan)
+        solves.append({"instance": i, "kind": insts[i]["kind"], "points": n, "status": rc, "iterations": it,
+                       "rel_residual": rr, "solve_ms": round(t_solve * 1e3, 3),
+                       "ms_per_iteration": round(t_solve * 1e3 / max(it, 1), 4), "apply_ms": round(t_apply * 1e3, 4)})
+        log(f"bench: GMRES on instance {i}: {solves[-1]}")
+    print(json.dumps({"setup_batch": out, "gmres_instances": solves}), flush=True)
 
 
 def main():
@@ -200,6 +279,9 @@ def main():
                     help="M2L arithmetic of the split leg in --no-tune runs (fp32 with --no-fp32: the plain leg only)")
     ap.add_argument("--setup-only", type=int, default=0, metavar="K",
                     help="only set up the --basis/--order/--leaf/--eps plan K times and report the setup times")
+    ap.add_argument("--setup-batch", type=int, default=0, metavar="K",
+                    help="only time K batched setups of the 256-instance ferromagnet workload (Chebyshev, 8 nodes "
+                         "per axis, leaf 128, three right-hand sides) against 256 separate setups of its instances")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -225,6 +307,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}), flush=True)
+        return
+    if args.setup_batch:
+        setup_batch(F, W, torch, dev, args.setup_batch)
         return
     # the tuning cache of this run (the autotuner writes it, the timed plans read it)
     os.environ["FMM_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="fmm_bench_"), "tune.jsonl")
@@ -324,17 +409,31 @@ def main():
                                  "trials": [{"leaf": c["leaf"], "ms": round(c["ms"], 3)} for c in t["tried"]]})
                     log(f"bench: tune {name}: {tune[-1]}")
             ok = [c for c in tune if max(c["err"], c["err_seed7"]) <= args.target]
-            pick = min(ok, key=lambda c: c["ms"]) if ok else min(tune, key=lambda c: max(c["err"], c["err_seed7"]))
-            cfg = (BASES.index(pick["basis"]), pick["order"], pick["leaf"], pick["eps"])
-            prec = PREC_NAMES.index(pick["arith"])
+            # the two fastest candidates that meet the target are timed in full (three tuning applies
+            # do not separate forms within a few per cent), and the faster is the leg's result
+            finalists = sorted(ok, key=lambda c: c["ms"])[:2] if ok else \
+                [min(tune, key=lambda c: max(c["err"], c["err_seed7"]))]
+            cands = [((BASES.index(c["basis"]), c["order"], c["leaf"], c["eps"]), PREC_NAMES.index(c["arith"]))
+                     for c in finalists]
         else:
-            cfg = (basis_arg, args.order, args.leaf, args.eps)
-        log(f"bench: form {name} {PREC_NAMES[prec]} {cfg}: setup + {args.warmup} warmup + {args.steps} timed steps")
-        r = run_form(F, torch, x, nrm, q, mu, prec, cfg[0], cfg[1], cfg[3], cfg[2], args.steps, args.warmup)
-        r["prec"] = prec
+            cands = [((basis_arg, args.order, args.leaf, args.eps), prec)]
+        timed = []
+        for cfg, prec in cands:
+            log(f"bench: form {name} {PREC_NAMES[prec]} {cfg}: setup + {args.warmup} warmup + {args.steps} timed steps")
+            r = run_form(F, torch, x, nrm, q, mu, prec, cfg[0], cfg[1], cfg[3], cfg[2], args.steps, args.warmup)
+            r["prec"], r["cfg"] = prec, cfg
+            timed.append(r)
+            log(f"bench: form {name} {PREC_NAMES[prec]} {cfg}: {r['ms']:.3f} ms/step")
+        r = min(timed, key=lambda x: x["ms"])
+        runner = [x for x in timed if x is not r]
+        r["runner_up"] = {"arith": PREC_NAMES[runner[0]["prec"]], "basis": BASES[runner[0]["cfg"][0]],
+                          "order_leaf_eps": list(runner[0]["cfg"][1:]), "ms_per_step": round(runner[0]["ms"], 4),
+                          "value": round(runner[0]["info"]["n_points"] / (runner[0]["ms"] * 1e-3) / 1e6, 3)} \
+            if runner else None
+        prec, cfg = r["prec"], r["cfg"]
         err = errors_of(r)
         r["err"], r["err_seed7"] = err.get(1), err.get(7)
-        r["cfg"], r["tune"] = cfg, tune
+        r["tune"] = tune
         r["roofline"], r["kernels"] = roofline(r, prec, args.n, cfg)
         results[name] = r
         log(f"bench: form {name}: {r['ms']:.3f} ms/step, setup {r['setup_s']:.2f} s, err {r.get('err')} / "
@@ -382,6 +481,8 @@ def main():
         "timing": "ordinary applies with the library's stage events on (one host synchronisation per step)",
         "selection": {"target_rel_l2": args.target, "error_sets": "10,000 targets each, seeds 1 and 7; the target "
                       "must hold on both", "leaf_from": "fmm_autotune trial runs, read back from its cache",
+                      "finalists": "the two fastest candidates meeting the target, each timed in full; the faster "
+                                   "is the result", "runner_up": main_r.get("runner_up"),
                       "split_bf16": main_r["tune"] if main_name == "split_bf16" else None,
                       "fp32": results["fp32"]["tune"] if "fp32" in results else None},
         "rel_l2_error": main_r.get("err"),
