@@ -184,6 +184,51 @@ def roofline(res, precision, n, cfg):
     return out, others
 
 
+def paper_workloads(F, W, torch, dev):
+    """Apply times of the paper's two model problems at their full sizes (errors: tests/test_gpu_workloads.py)."""
+    import numpy as np
+
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    out = []
+
+    def timeit(name, x, nrm, opts, q=None, mu=None, field=False):
+        plan = F.fmm_setup(t(x), t(nrm), options=opts)
+        info = F.fmm_plan_info(plan)
+        n = info["n_trg"]
+        pot = None if field else torch.zeros(n, device=dev)
+        fld = torch.zeros(3 * n, device=dev) if field else None
+        for _ in range(3):
+            F.fmm_apply(plan, q=q, mu=mu, pot=pot, field=fld)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            F.fmm_apply(plan, q=q, mu=mu, pot=pot, field=fld)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 20 * 1e3
+        out.append({"workload": name, "points": n, "basis": BASES[opts.basis], "order": opts.order,
+                    "arith": PREC_NAMES[opts.precision], "leaf": opts.leaf_size, "eps": opts.pinv_eps,
+                    "apply_ms": round(ms, 3), "m2l_fill": round(info["m2l_pairs"] / max(info["m2l_columns"], 1), 3)})
+        log(f"bench: {out[-1]}")
+        F.fmm_destroy(plan)
+
+    forms = [(0, 8, 1e-8), (1, 8, 1e-8), (1, 5, 1e-6)]
+    s8 = W.spheres_8(freq=35)
+    mu = t(s8["mu"] * s8["weights"])
+    for basis, order, eps in forms:
+        for prec in (F.FMM_PREC_SPLIT_BF16X3, F.FMM_PREC_FP32):
+            o = F.fmm_default_options(order=order, leaf_size=192, src_kernels=F.FMM_SRC_DOUBLE, precision=prec,
+                                      basis=basis, pinv_eps=eps)
+            timeit("eight spheres, double layer", s8["xyz"], s8["normals"], o, mu=mu)
+    d = W.dielectric(1000, 7)
+    q = t(d["areas"])
+    for basis, order, eps in forms:
+        for prec in (F.FMM_PREC_SPLIT_BF16X3, F.FMM_PREC_FP32):
+            o = F.fmm_default_options(order=order, leaf_size=192, src_kernels=F.FMM_SRC_SINGLE,
+                                      outputs=F.FMM_OUT_FIELD, precision=prec, basis=basis, pinv_eps=eps)
+            timeit("dielectric spheres, single-layer field", d["xyz"], d["normals"], o, q=q, field=True)
+    print(json.dumps({"paper_workloads": out}), flush=True)
+
+
 def setup_batch(F, W, torch, dev, reps):
     """Batched setup of the ferromagnet batch against separate setups of its instances."""
     import numpy as np
@@ -219,6 +264,44 @@ def setup_batch(F, W, torch, dev, reps):
                     "batched_phases_ms": {k: round(v, 1) for k, v in info["setup_phase_ms"].items()},
                     "separate_phases_ms_sum": {k: round(v, 1) for k, v in phases.items()}})
         log(f"bench: batched setup {tb:.3f} s, 256 separate setups {ts:.3f} s")
+    # the batched apply (one plan, every stage one launch over all instances, replayed as one HIP graph)
+    # against 256 plans applied one after another, three right-hand sides (the magnetisation components)
+    rng = np.random.default_rng(5)
+    mu = torch.from_numpy(rng.standard_normal(3 * int(so[-1])).astype(np.float32)).to(dev)
+    plan = F.fmm_setup_batch(so, src, nrm, to, trg, options=opts)
+    pot = torch.empty(3 * int(to[-1]), device=dev)
+    F.fmm_set_graph(plan, True)
+    for _ in range(3):
+        F.fmm_apply(plan, mu=mu, pot=pot)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        F.fmm_apply(plan, mu=mu, pot=pot)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / 10
+    F.fmm_destroy(plan)
+    plans, mus, pots = [], [], []
+    for i in range(len(insts)):
+        plans.append(F.fmm_setup(src[so[i]:so[i + 1]], nrm[so[i]:so[i + 1]], trg[to[i]:to[i + 1]], options=opts))
+        ns, nt = int(so[i + 1] - so[i]), int(to[i + 1] - to[i])
+        mus.append(torch.from_numpy(rng.standard_normal(3 * ns).astype(np.float32)).to(dev))
+        pots.append(torch.empty(3 * nt, device=dev))
+    for p, m, o in zip(plans, mus, pots):
+        F.fmm_apply(p, mu=m, pot=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        for p, m, o in zip(plans, mus, pots):
+            F.fmm_apply(p, mu=m, pot=o)
+    torch.cuda.synchronize()
+    t_sep = (time.perf_counter() - t0) / 3
+    for p in plans:
+        F.fmm_destroy(p)
+    npts = int(so[-1] + to[-1])
+    applies = {"batched_apply_ms": round(t_batch * 1e3, 3), "separate_applies_ms": round(t_sep * 1e3, 3),
+               "points": npts, "batched_mpoints_s": round(npts / t_batch / 1e6, 3),
+               "form": "Chebyshev, 8 nodes per axis, threshold 1e-8, leaf 128, bf16x3, double layer, 3 rhs"}
+    log(f"bench: batched apply {applies}")
     # GMRES on single instances of the batch: the interior Dirichlet problem of the double layer on the
     # instance's surface (centroids with their areas as weights, diagonal -1/2 on the flat faces),
     # boundary data 1 / |x - r0| from a point r0 outside
@@ -254,7 +337,7 @@ def setup_batch(F, W, torch, dev, reps):
                        "rel_residual": rr, "solve_ms": round(t_solve * 1e3, 3),
                        "ms_per_iteration": round(t_solve * 1e3 / max(it, 1), 4), "apply_ms": round(t_apply * 1e3, 4)})
         log(f"bench: GMRES on instance {i}: {solves[-1]}")
-    print(json.dumps({"setup_batch": out, "gmres_instances": solves}), flush=True)
+    print(json.dumps({"setup_batch": out, "applies": applies, "gmres_instances": solves}), flush=True)
 
 
 def main():
@@ -282,6 +365,9 @@ def main():
     ap.add_argument("--setup-batch", type=int, default=0, metavar="K",
                     help="only time K batched setups of the 256-instance ferromagnet workload (Chebyshev, 8 nodes "
                          "per axis, leaf 128, three right-hand sides) against 256 separate setups of its instances")
+    ap.add_argument("--paper-workloads", action="store_true",
+                    help="only time applies of the eight-sphere (double layer) and dielectric-sphere (single-layer "
+                         "field) workloads in the surface form (order 8) and the Chebyshev form (n = 8 and 5)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -310,6 +396,9 @@ def main():
         return
     if args.setup_batch:
         setup_batch(F, W, torch, dev, args.setup_batch)
+        return
+    if args.paper_workloads:
+        paper_workloads(F, W, torch, dev)
         return
     # the tuning cache of this run (the autotuner writes it, the timed plans read it)
     os.environ["FMM_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="fmm_bench_"), "tune.jsonl")
