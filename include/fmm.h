@@ -102,7 +102,8 @@ typedef struct {
     float cutoff;       /* tolerance radius (Sec. III.A.1), e.g. 1e-5; r < cutoff excluded, r == 0 always */
     double root[4];     /* root cube x0, y0, z0, width; width <= 0: derived from the points */
     double pinv_eps;    /* relative SVD truncation (SURFACE: of the check-to-equivalent maps;
-                           CHEBYSHEV: of the shared M2L basis); <= 0: default */
+                           CHEBYSHEV: of the shared M2L basis, the count kept then rounded up
+                           to a multiple of 32, the size M2L is padded to); <= 0: default */
     int m2l_pieces;     /* M2L work items per tile of target boxes, 1..8; 0: chosen at setup by
                            simulating the dispatch on the GPU's compute units (the default) */
     int basis;          /* FMM_BASIS_*: far-field representation (default SURFACE) */
@@ -319,8 +320,9 @@ typedef struct {
     int64_t m2l_columns;                 /* matrix-vector products the M2L kernel computes, padding
                                             included (m2l_pairs / m2l_columns is its fill) */
     int64_t rank;                        /* r: singular values kept (SURFACE: of the check-from-
-                                            equivalent map; CHEBYSHEV: of the shared M2L basis);
-                                            M2L acts on r values per box and rhs */
+                                            equivalent map; CHEBYSHEV: of the shared M2L basis, a
+                                            multiple of 32 or n^3); M2L acts on r values per box
+                                            and rhs */
     int64_t m2l_pieces;                  /* M2L work items per tile of 128 target boxes (load
                                             balance across CUs; pieces add up in a fixed order) */
     int64_t m2l_pair_tiles;              /* M2L work items of one direction whose columns are

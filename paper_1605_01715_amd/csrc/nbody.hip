@@ -272,12 +272,38 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
     // poff + 1) the setup has shown that the points' bounding boxes are
     // farther apart than delta, and the test is skipped.
     const float delta2 = a.delta2;
-    auto range = [&](auto test_tag, int e) {
+    // The ranges e0 .. e1 - 1 as one sequence of sources, staged 64 at a
+    // time: a tile runs across range boundaries, so only the sequence's last
+    // tile is padded (per-range tiles left a quarter of the slots padding on
+    // the clustered cloud, whose leaves have about ten merged ranges each).
+    // (e, off) is the wave-uniform position of the tile's first source.
+    auto stream = [&](auto test_tag, int e0, int e1) {
         constexpr bool TEST = decltype(test_tag)::value;
-        const int s0 = a.prng[2 * e], s1 = a.prng[2 * e + 1];
-        for (int j0 = s0; j0 < s1; j0 += 64) {
-            const int j = j0 + lane;
-            if (j < s1) {
+        int e = e0, off = 0;
+        while (e < e1) {
+            // this lane's source: the tile covers the rest of range e and,
+            // past its end, the next ranges; their bounds are wave-uniform
+            // loads issued together (a tile rarely spans more than four)
+            int j = -1;
+            {
+                int base = 0, k = e;  // base: tile position where range k starts
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (k < e1 && base < 64) {
+                        const int r0 = a.prng[2 * k] + (k == e ? off : 0), len = a.prng[2 * k + 1] - r0;
+                        if (lane >= base && lane < base + len) j = r0 + (lane - base);
+                        base += len;
+                        ++k;
+                    }
+                }
+                while (k < e1 && base < 64) {
+                    const int r0 = a.prng[2 * k], len = a.prng[2 * k + 1] - r0;
+                    if (lane >= base && lane < base + len) j = r0 + (lane - base);
+                    base += len;
+                    ++k;
+                }
+            }
+            if (j >= 0) {
                 float *p = sh + lane * W;
                 p[0] = src.x[j];
                 p[1] = src.y[j];
@@ -348,12 +374,24 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
                 for (int r = 0; r < NRHS; ++r)
                     for (int o = 0; o < NOUT; ++o) two_sum_into(hi[u][r][o], lo[u][r][o], part[u][r][o]);
             __syncthreads();
+            // advance the position by 64 sources
+            int adv = 64;
+            while (e < e1) {
+                const int rest = a.prng[2 * e + 1] - a.prng[2 * e] - off;
+                if (adv < rest) {
+                    off += adv;
+                    break;
+                }
+                adv -= rest;
+                ++e;
+                off = 0;
+            }
         }
     };
     if (a.points) {
         const int pmid = a.pmid ? a.pmid[leaf] : a.poff[leaf + 1];
-        for (int e = a.poff[leaf]; e < pmid; ++e) range(std::true_type{}, e);
-        for (int e = pmid; e < a.poff[leaf + 1]; ++e) range(std::false_type{}, e);
+        stream(std::true_type{}, a.poff[leaf], pmid);
+        stream(std::false_type{}, pmid, a.poff[leaf + 1]);
     }
 
     // sum the slices of each target through LDS, then slice 0 writes

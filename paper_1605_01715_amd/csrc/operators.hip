@@ -356,6 +356,12 @@ std::shared_ptr<Operators> build_chebyshev(int n, double eps, hipStream_t s) {
     while (r < nn && lam[r] > thr) ++r;
     r = std::max(r, 1);
     const int rp = ((r + 31) / 32) * 32;
+    // M2L runs on r_pad values whatever r is, so the basis keeps r_pad
+    // vectors when there are that many: the padded rows then carry the next
+    // singular directions instead of zeros, at no cost in M2L. (No inverse is
+    // taken here, unlike the surface form's pseudo-inverse, so more vectors
+    // only bring the compressed operator closer to the dense one.)
+    r = std::min(rp, nn);
     op->r = r;
     op->r_pad = rp;
     std::vector<double> Q((size_t)nn * r), QT((size_t)r * nn);

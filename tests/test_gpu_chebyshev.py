@@ -49,8 +49,10 @@ def test_chebyshev_matches_oracle_and_its_stages(precision):
     t = T.build_tree(x, leaf_size=30)
     L = T.all_lists(t)
     ops = C.ChebOperators(5, rank=info["rank"])
-    # the GPU's rank comes from the same threshold on the same singular values
-    assert info["rank"] == int(np.sum(ops.sigma > 1e-6 * ops.sigma[0]))
+    # the GPU's rank comes from the same threshold on the same singular values,
+    # the count rounded up to the 32 the M2L kernel pads it to anyway
+    kept = int(np.sum(ops.sigma > 1e-6 * ops.sigma[0]))
+    assert info["rank"] == min((kept + 31) // 32 * 32, 125)
     pot, _, st = C.cheb_apply(t, L, ops, x, q=q, mu=mu, normals=nrm, return_stages=True)
     err = D.rel_l2(r["pot"][0], pot)
     say(f"  GPU vs oracle Chebyshev FMM rel L2 = {err:.3e} (rank {info['rank']})")
@@ -83,7 +85,7 @@ def test_chebyshev_field_with_separate_targets():
     import paper_1605_01715_amd as F  # noqa: F401
 
     t = T.build_tree(x, trg=trg, leaf_size=40)
-    ops = C.ChebOperators(6, eps=1e-7)
+    ops = C.ChebOperators(6, rank=r["info"]["rank"])
     _, fld, _ = C.cheb_apply(t, T.all_lists(t), ops, x, q=q, trg_xyz=trg, field=True, return_stages=True)
     err = D.rel_l2(r["field"][0], fld)
     ref_p, ref_f = D.direct_sum(trg, x, q, None, field=True)
