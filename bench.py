@@ -489,13 +489,26 @@ def main():
                 for basis, order, eps in FORMS:
                     t = F.fmm_autotune(x, nrm, options=options(F, cprec, basis, order, eps, 0), leaf_sizes=LEAVES,
                                        reps=3)
-                    r = run_form(F, torch, x, nrm, q, mu, cprec, basis, order, eps, 0, 3, 1)
-                    assert r["info"]["leaf_from_cache"] == 1 and r["info"]["leaf_size"] == t["leaf_size"]
-                    err = errors_of(r)
-                    tune.append({"arith": PREC_NAMES[cprec], "basis": BASES[basis], "order": order, "eps": eps,
-                                 "leaf": t["leaf_size"], "m2l_pieces": t["m2l_pieces"], "ms": round(r["ms"], 3),
-                                 "err": err[1], "err_seed7": err[7],
-                                 "trials": [{"leaf": c["leaf"], "ms": round(c["ms"], 3)} for c in t["tried"]]})
+                    # the error depends on the leaf too (more boxes, more far field): the autotuner's leaf
+                    # first, then the next fastest of its trials while the target is missed (at most three)
+                    best = {}
+                    for c in t["tried"]:
+                        best[c["leaf"]] = min(best.get(c["leaf"], float("inf")), c["ms"])
+                    leaves = [t["leaf_size"]] + [lf for lf in sorted(best, key=best.get) if lf != t["leaf_size"]]
+                    for k, leaf in enumerate(leaves[:3]):
+                        r = run_form(F, torch, x, nrm, q, mu, cprec, basis, order, eps, 0 if k == 0 else leaf, 3, 1)
+                        if k == 0:
+                            assert r["info"]["leaf_from_cache"] == 1 and r["info"]["leaf_size"] == t["leaf_size"]
+                        err = errors_of(r)
+                        entry = {"arith": PREC_NAMES[cprec], "basis": BASES[basis], "order": order, "eps": eps,
+                                 "leaf": leaf, "m2l_pieces": r["info"]["m2l_pieces"], "ms": round(r["ms"], 3),
+                                 "err": err[1], "err_seed7": err[7], "leaf_rank_in_trials": k,
+                                 "trials": [{"leaf": c["leaf"], "ms": round(c["ms"], 3)} for c in t["tried"]]}
+                        if max(err[1], err[7]) <= args.target or k == min(len(leaves), 3) - 1:
+                            break
+                        log(f"bench: tune {name}: leaf {leaf} misses the target ({max(err[1], err[7]):.3e}); "
+                            f"trying the next fastest leaf")
+                    tune.append(entry)
                     log(f"bench: tune {name}: {tune[-1]}")
             ok = [c for c in tune if max(c["err"], c["err_seed7"]) <= args.target]
             # the two fastest candidates that meet the target are timed in full (three tuning applies
