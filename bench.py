@@ -56,7 +56,7 @@ def options(F, precision, basis, order, eps, leaf):
                                  root=(0.0, 0.0, 0.0, 1.0), pinv_eps=eps, basis=basis)
 
 
-def run_form(F, torch, x, nrm, q, mu, precision, basis, order, eps, leaf, steps, warmup):
+def run_form(F, torch, x, nrm, q, mu, precision, basis, order, eps, leaf, steps, warmup, graph_steps=0):
     """Set up a plan (leaf 0: the tuned leaf from the cache), apply it warmup
     times, then time `steps` applies with the library's stage events on
     (each apply then waits for its events: one host synchronisation per step)."""
@@ -83,9 +83,28 @@ def run_form(F, torch, x, nrm, q, mu, precision, basis, order, eps, leaf, steps,
     end.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(end) / steps
+    graph = None
+    if graph_steps:
+        # the same apply replayed as one captured HIP graph, stage events off: the median of
+        # individually timed replays
+        F.fmm_set_timing(plan, False)
+        F.fmm_set_graph(plan, True)
+        for _ in range(3):
+            F.fmm_apply(plan, q=q, mu=mu, pot=pot)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(graph_steps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record()
+            F.fmm_apply(plan, q=q, mu=mu, pot=pot)
+            b.record()
+        torch.cuda.synchronize()
+        times = sorted(a.elapsed_time(b) for a, b in ev)
+        graph = {"replays": graph_steps, "median_ms": round(times[len(times) // 2], 4),
+                 "min_ms": round(times[0], 4), "max_ms": round(times[-1], 4),
+                 "mpoints_s": round(info["n_points"] / (times[len(times) // 2] * 1e-3) / 1e6, 3)}
     F.fmm_destroy(plan)
     stages = {k: v / steps for k, v in stage_sum.items()}
-    return {"ms": ms, "setup_s": setup_s, "info": info, "stages": stages, "pot": pot}
+    return {"ms": ms, "setup_s": setup_s, "info": info, "stages": stages, "pot": pot, "graph": graph}
 
 
 def form_tag(cfg):
@@ -522,7 +541,8 @@ def main():
         timed = []
         for cfg, prec in cands:
             log(f"bench: form {name} {PREC_NAMES[prec]} {cfg}: setup + {args.warmup} warmup + {args.steps} timed steps")
-            r = run_form(F, torch, x, nrm, q, mu, prec, cfg[0], cfg[1], cfg[3], cfg[2], args.steps, args.warmup)
+            r = run_form(F, torch, x, nrm, q, mu, prec, cfg[0], cfg[1], cfg[3], cfg[2], args.steps, args.warmup,
+                         graph_steps=20)
             r["prec"], r["cfg"] = prec, cfg
             timed.append(r)
             log(f"bench: form {name} {PREC_NAMES[prec]} {cfg}: {r['ms']:.3f} ms/step")
@@ -581,6 +601,7 @@ def main():
                    "svd_eps": eps, "rank": info["rank"], "boxes": info["n_boxes"], "levels": info["n_levels"],
                    "m2l_pieces_per_tile": info["m2l_pieces"]},
         "timing": "ordinary applies with the library's stage events on (one host synchronisation per step)",
+        "graph_replay": main_r.get("graph"),
         "selection": {"target_rel_l2": args.target, "error_sets": "10,000 targets each, seeds 1 and 7; the target "
                       "must hold on both", "leaf_from": "fmm_autotune trial runs, read back from its cache",
                       "finalists": "the two fastest candidates meeting the target, each timed in full; the faster "
