@@ -57,3 +57,26 @@ def test_destroyed_plan_returns_state_error():
     torch.cuda.synchronize()
     assert np.all(np.isfinite(pot.cpu().numpy()))
     F.fmm_destroy(plan2)
+
+
+def test_setup_phase_times_add_up():
+    """fmm_info.setup_phase_ms: every phase timed, none negative, their sum
+    within the setup's wall time; a second plan of the same form finds its
+    operators cached (phase 3 near zero), a batch merges nothing (phase 7)."""
+    import paper_1605_01715_amd as F
+
+    d = W.clustered(60_000, seed=21)
+    opts = F.fmm_default_options(order=6, leaf_size=64, basis=F.FMM_BASIS_CHEBYSHEV)
+    infos = []
+    for _ in range(2):
+        plan = F.fmm_setup(dev(d["xyz"]), options=opts)
+        infos.append(F.fmm_plan_info(plan))
+        F.fmm_destroy(plan)
+    for info in infos:
+        ph = info["setup_phase_ms"]
+        say(f"  setup {info['setup_ms']:.1f} ms, phases {ph}")
+        assert all(v >= 0.0 for v in ph.values())
+        assert sum(ph.values()) <= info["setup_ms"] * 1.001 + 0.1
+        assert ph["sort"] > 0 and ph["lists"] > 0 and ph["m2l_schedule"] > 0 and ph["worklists"] > 0
+        assert ph["unused"] == 0.0
+    assert infos[1]["setup_phase_ms"]["operators"] < 1.0

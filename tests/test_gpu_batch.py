@@ -115,3 +115,73 @@ def test_batch_argument_errors():
         F.fmm_setup_batch([5, 100], x, options=opts)  # does not start at 0
     with pytest.raises(F.FmmError):
         F.fmm_setup_batch([0, 100], x, trg_off=[0, 10], options=opts)  # trg_off without targets
+
+
+def test_batch_forest_equals_the_instance_trees():
+    """The batch builds every instance tree in one sorted pass: each instance's
+    boxes (levels, anchors, point ranges, parents), lists and permutations must
+    equal those of a plan built on that instance alone, shifted into the batch's
+    box and point numbering; an instance with no points contributes nothing."""
+    import paper_1605_01715_amd as F
+
+    insts = W.ferro_batch(n_inst=5, seed=13, nmin=500, nmax=3000)
+    say(f"test_batch_forest_equals_the_instance_trees: {len(insts)} instances and an empty one")
+    srcs = [d["src"] for d in insts]
+    nrms = [d["normals"] for d in insts]
+    trgs = [d["trg"] for d in insts]
+    # an empty instance in the middle
+    srcs.insert(2, np.zeros((0, 3), np.float32))
+    nrms.insert(2, np.zeros((0, 3), np.float32))
+    trgs.insert(2, np.zeros((0, 3), np.float32))
+    so = np.concatenate([[0], np.cumsum([len(a) for a in srcs])])
+    to = np.concatenate([[0], np.cumsum([len(a) for a in trgs])])
+    opts = F.fmm_default_options(order=6, leaf_size=40, src_kernels=F.FMM_SRC_DOUBLE)
+    plan = F.fmm_setup_batch(so, dev(np.concatenate(srcs)), dev(np.concatenate(nrms)), to,
+                             dev(np.concatenate(trgs)), options=opts)
+    bt = F.fmm_export_tree(plan)
+    F.fmm_destroy(plan)
+    parts = []
+    for i in range(len(srcs)):
+        if len(srcs[i]) == 0:
+            parts.append(None)
+            continue
+        p = F.fmm_setup(dev(srcs[i]), dev(nrms[i]), dev(trgs[i]), options=opts)
+        parts.append(F.fmm_export_tree(p))
+        F.fmm_destroy(p)
+    nlev = int(bt["level"].max()) + 1
+    # batch numbering: level-major, instances in order within a level
+    base, lvl_start = {}, np.searchsorted(bt["level"], np.arange(nlev + 1))
+    for lvl in range(nlev):
+        o = lvl_start[lvl]
+        for i, t in enumerate(parts):
+            if t is None:
+                continue
+            base[i, lvl] = o
+            o += int(np.sum(t["level"] == lvl))
+        assert o == lvl_start[lvl + 1]
+    noff = np.concatenate([[0], np.cumsum([len(s) + len(t) for s, t in zip(srcs, trgs)])])
+    for i, t in enumerate(parts):
+        if t is None:
+            continue
+        lo = np.searchsorted(t["level"], np.arange(int(t["level"].max()) + 2))
+        ids = np.array([base[i, l] + (b - lo[l]) for b, l in enumerate(t["level"])])
+        def remap(v):
+            v = np.asarray(v)
+            return np.where(v >= 0, ids[np.maximum(v, 0)], -1)
+        assert np.array_equal(bt["level"][ids], t["level"])
+        assert np.array_equal(bt["anchor"][ids], t["anchor"])
+        assert np.array_equal(bt["parent"][ids], remap(t["parent"]))
+        assert np.array_equal(bt["begin"][ids], t["begin"] + noff[i])
+        assert np.array_equal(bt["sbeg"][ids], t["sbeg"] + so[i])
+        assert np.array_equal(bt["send"][ids], t["send"] + so[i])
+        assert np.array_equal(bt["tbeg"][ids], t["tbeg"] + to[i])
+        assert np.array_equal(bt["tend"][ids], t["tend"] + to[i])
+        for k in "uvwx":
+            for b in range(len(ids)):
+                a = t[k + "_idx"][t[k + "_off"][b]:t[k + "_off"][b + 1]]
+                q = ids[b]
+                got = bt[k + "_idx"][bt[k + "_off"][q]:bt[k + "_off"][q + 1]]
+                assert np.array_equal(got, ids[a]), (i, k, b)
+        assert np.array_equal(bt["src_perm"][so[i]:so[i + 1]], t["src_perm"] + so[i])
+        assert np.array_equal(bt["trg_perm"][to[i]:to[i + 1]], t["trg_perm"] + to[i])
+        say(f"  instance {i}: {len(ids)} boxes, {len(t['u_idx'])} U / {len(t['v_idx'])} V entries identical")
