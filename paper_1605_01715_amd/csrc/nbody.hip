@@ -145,9 +145,12 @@ __global__ __launch_bounds__(64) void k_points_to_surface(const int32_t *items, 
 // ------------------------------------------------------------ leaf evaluation
 //
 // One wave per work item (up to 64 targets of a leaf). Lanes are laid out as
-// S source slices x L lane-targets, each lane holding TPL targets (1 or 2,
-// chosen per item to keep most lanes busy: a 39-target item runs as 20 lanes
-// x 2 targets x 3 slices instead of 39 of 64 lanes). Sources are staged in
+// S source slices x L lane-targets, each lane holding TPL targets (1 to 4
+// with one output and one right-hand side, else 1 or 2), chosen per item to
+// keep most lane-slots busy: a 45-target item runs as 15 lanes x 3 targets x
+// 4 slices (94% of the slots) instead of 45 of 64 lanes, or 23 x 2 x 2 (70%).
+// More targets per lane also read each staged source once for more pairs.
+// Sources are staged in
 // LDS 64 at a time (records padded to 16 bytes, the tail of a tile filled
 // with zero-density sources far away), so the loop over a tile has the same
 // trip count in every lane and no per-pair validity test. Slices are summed
@@ -447,17 +450,36 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
 template <int NRHS, bool SL, bool DL, bool FIELD>
 __global__ __launch_bounds__(64) void k_eval(EvalArgs a, SurfaceGeom g, PointSrc src) {
     using E = EvalShape<NRHS, SL, DL, FIELD>;
-    __shared__ __align__(16) float sh[E::NREC * E::W];
-    __shared__ float red[64 * 2 * NRHS * E::NOUT * 2];
+    // up to 4 targets per lane where one output and one right-hand side
+    // keep the accumulators few; 2 otherwise
+    constexpr int MAXTPL = (E::NOUT == 1 && NRHS == 1) ? 4 : 2;
+    constexpr int NSH = E::NREC * E::W, NRED = 64 * MAXTPL * NRHS * E::NOUT * 2;
+    // the slice sums of the end reuse the source records' LDS
+    __shared__ __align__(16) float sh[NSH > NRED ? NSH : NRED];
     const int leaf = a.wleaf[blockIdx.x];
     const int64_t t_first = a.tbeg[leaf] + a.wt0[blockIdx.x];
     const int nt = (int)min((int64_t)64, a.tend[leaf] - t_first);
-    // targets per lane: 2 when that keeps more lanes busy (nt * S / (64 TPL))
-    const int s1 = 64 / nt, s2 = 64 / ((nt + 1) / 2);
-    if (nt * s2 >= 2 * nt * s1)
-        eval_item<2, NRHS, SL, DL, FIELD>(a, g, src, leaf, t_first, nt, sh, red);
+    // targets per lane (TPL): the count that keeps the most lane-slots busy,
+    // nt * S / (64 TPL) with S = 64 / ceil(nt / TPL) slices; ties to the larger
+    // (fewer LDS reads per pair)
+    int best = 1, bnum = nt * (64 / nt), bden = 64;
+#pragma unroll
+    for (int tpl = 2; tpl <= MAXTPL; ++tpl) {
+        const int num = nt * (64 / ((nt + tpl - 1) / tpl)), den = 64 * tpl;
+        if (num * bden >= bnum * den) {
+            best = tpl;
+            bnum = num;
+            bden = den;
+        }
+    }
+    if constexpr (MAXTPL == 4) {
+        if (best == 4) return eval_item<4, NRHS, SL, DL, FIELD>(a, g, src, leaf, t_first, nt, sh, sh);
+        if (best == 3) return eval_item<3, NRHS, SL, DL, FIELD>(a, g, src, leaf, t_first, nt, sh, sh);
+    }
+    if (best >= 2)
+        eval_item<2, NRHS, SL, DL, FIELD>(a, g, src, leaf, t_first, nt, sh, sh);
     else
-        eval_item<1, NRHS, SL, DL, FIELD>(a, g, src, leaf, t_first, nt, sh, red);
+        eval_item<1, NRHS, SL, DL, FIELD>(a, g, src, leaf, t_first, nt, sh, sh);
 }
 
 // ------------------------------------------------------------ all pairs
