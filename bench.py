@@ -351,10 +351,21 @@ def setup_batch(F, W, torch, dev, reps):
         rc, it, rr = F.gmres_solve(plan, F.FMM_OP_FK, a, None, w, b, x, rtol=1e-6)
         torch.cuda.synchronize()
         t_solve = time.perf_counter() - t0
+        # the same solve with its matvecs replayed as one HIP graph (recorded on the first matvec)
+        F.fmm_set_graph(plan, True)
+        xg = torch.zeros(n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rcg, itg, _ = F.gmres_solve(plan, F.FMM_OP_FK, a, None, w, b, xg, rtol=1e-6)
+        torch.cuda.synchronize()
+        t_graph = time.perf_counter() - t0
         F.fmm_destroy(plan)
         solves.append({"instance": i, "kind": insts[i]["kind"], "points": n, "status": rc, "iterations": it,
                        "rel_residual": rr, "solve_ms": round(t_solve * 1e3, 3),
-                       "ms_per_iteration": round(t_solve * 1e3 / max(it, 1), 4), "apply_ms": round(t_apply * 1e3, 4)})
+                       "ms_per_iteration": round(t_solve * 1e3 / max(it, 1), 4), "apply_ms": round(t_apply * 1e3, 4),
+                       "graph": {"status": rcg, "iterations": itg, "solve_ms": round(t_graph * 1e3, 3),
+                                 "ms_per_iteration": round(t_graph * 1e3 / max(itg, 1), 4),
+                                 "same_solution": bool(torch.equal(x, xg))}})
         log(f"bench: GMRES on instance {i}: {solves[-1]}")
     print(json.dumps({"setup_batch": out, "applies": applies, "gmres_instances": solves}), flush=True)
 

@@ -280,27 +280,34 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
     // tile is padded (per-range tiles left a quarter of the slots padding on
     // the clustered cloud, whose leaves have about ten merged ranges each).
     // (e, off) is the wave-uniform position of the tile's first source.
+    // Range bounds are wave-uniform: read through the constant address space
+    // they become scalar loads, and the four bounds pairs a tile looks at
+    // first are read together (the array is padded by 8 entries, so reads
+    // past the last range stay inside it).
+    const int32_t __attribute__((address_space(4))) *rng =
+        (const int32_t __attribute__((address_space(4))) *)a.prng;
     auto stream = [&](auto test_tag, int e0, int e1) {
         constexpr bool TEST = decltype(test_tag)::value;
         int e = e0, off = 0;
         while (e < e1) {
             // this lane's source: the tile covers the rest of range e and,
-            // past its end, the next ranges; their bounds are wave-uniform
-            // loads issued together (a tile rarely spans more than four)
+            // past its end, the next ranges (a tile rarely spans more than four)
             int j = -1;
             {
+                int bnd[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) bnd[u] = rng[2 * e + u];
                 int base = 0, k = e;  // base: tile position where range k starts
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    if (k < e1 && base < 64) {
-                        const int r0 = a.prng[2 * k] + (k == e ? off : 0), len = a.prng[2 * k + 1] - r0;
-                        if (lane >= base && lane < base + len) j = r0 + (lane - base);
-                        base += len;
-                        ++k;
-                    }
+                    const int r0 = bnd[2 * u] + (u == 0 ? off : 0);
+                    const int len = (k < e1) ? bnd[2 * u + 1] - r0 : 0;
+                    if (lane >= base && lane < base + len) j = r0 + (lane - base);
+                    base += len;
+                    k += k < e1 ? 1 : 0;
                 }
                 while (k < e1 && base < 64) {
-                    const int r0 = a.prng[2 * k], len = a.prng[2 * k + 1] - r0;
+                    const int r0 = rng[2 * k], len = rng[2 * k + 1] - r0;
                     if (lane >= base && lane < base + len) j = r0 + (lane - base);
                     base += len;
                     ++k;
@@ -380,7 +387,7 @@ __device__ void eval_item(const EvalArgs &a, const SurfaceGeom &g, const PointSr
             // advance the position by 64 sources
             int adv = 64;
             while (e < e1) {
-                const int rest = a.prng[2 * e + 1] - a.prng[2 * e] - off;
+                const int rest = rng[2 * e + 1] - rng[2 * e] - off;
                 if (adv < rest) {
                     off += adv;
                     break;

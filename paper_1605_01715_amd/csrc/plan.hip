@@ -875,6 +875,7 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
     P.wt0 = upload(wt0, s);
     P.sbox = upload(sbox, s);
     P.skind = upload(skind, s);
+    prng.insert(prng.end(), 8, 0);  // the evaluation reads bounds up to 8 entries ahead
     P.prng = upload(prng, s);
     {
         GemmJob &j = P.c2e_down;
