@@ -319,11 +319,6 @@ int fmm_apply(fmm_plan plan, const float *q, const float *mu, float *pot, float 
             if (field && nt) FMM_HIP(hipMemsetAsync(field, 0, sizeof(float) * 3 * P.nrhs * nt, s));
             return;
         }
-        if (P.timing && !P.ev[0]) {
-            for (auto &e : P.ev) FMM_HIP(hipEventCreate(&e));
-            for (auto &e : P.ev_side) FMM_HIP(hipEventCreate(&e));
-            FMM_HIP(hipEventCreate(&P.ev_l2l_end));
-        }
         if (P.graph.enabled && !P.timing)  // stage timing needs the ordinary apply
             plan_apply_graph(P, q, mu, pot, field, s);
         else

@@ -972,6 +972,11 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
     Tree &t = P.t;
     const int nrhs = P.nrhs;
     const Operators &op = *P.ops;
+    if (P.timing && !P.ev[0]) {  // the stage events, on the first timed apply from any entry point
+        for (auto &e : P.ev) FMM_HIP(hipEventCreate(&e));
+        for (auto &e : P.ev_side) FMM_HIP(hipEventCreate(&e));
+        FMM_HIP(hipEventCreate(&P.ev_l2l_end));
+    }
     auto mark = [&](int k) {
         if (P.timing) FMM_HIP(hipEventRecord(P.ev[k], s));
     };

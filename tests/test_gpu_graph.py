@@ -101,4 +101,60 @@ def test_gmres_with_graph_replay_matches():
     say(f"  eager {r1}, graph {r2}")
     assert r1[0] == F.FMM_OK and r2[0] == F.FMM_OK and r1[1] == r2[1]
     assert torch.equal(x1, x2)
+    # short restarts: the recorded matvec is replayed across restarts (the
+    # restart's residual and every Arnoldi step), with eager work and
+    # synchronisations between solves; every solve must equal the ordinary one
+    # bit for bit
+    F.fmm_set_graph(plan, False)
+    x3 = dev(np.zeros(n))
+    r3 = F.gmres_solve(plan, F.FMM_OP_FK, a, None, wd, bd, x3, rtol=1e-7, restart=4)
+    F.fmm_set_graph(plan, True)
+    for k in range(2):
+        x4 = dev(np.zeros(n))
+        r4 = F.gmres_solve(plan, F.FMM_OP_FK, a, None, wd, bd, x4, rtol=1e-7, restart=4)
+        junk = (x4 * 2.0).sum()
+        torch.cuda.synchronize()
+        say(f"  restart 4: eager {r3}, graph {r4}")
+        assert torch.isfinite(junk)
+        assert r4[0] == r3[0] and r4[1] == r3[1] and r4[1] > 4
+        assert torch.equal(x3, x4), f"solve {k} differs"
+    # stage timing on (its events are created by the solve's first apply): the
+    # ordinary path, same result
+    F.fmm_set_timing(plan, True)
+    x5 = dev(np.zeros(n))
+    r5 = F.gmres_solve(plan, F.FMM_OP_FK, a, None, wd, bd, x5, rtol=1e-7, restart=4)
+    F.fmm_set_timing(plan, False)
+    torch.cuda.synchronize()
+    assert r5[1] == r3[1] and torch.equal(x3, x5)
+    F.fmm_destroy(plan)
+
+
+def test_gmres_dielectric_with_graph_replay_matches():
+    """Graph-replayed matvecs with the dielectric operator (field output,
+    single layer) and short restarts: the same iterates as the ordinary solve."""
+    import torch
+
+    import paper_1605_01715_amd as F
+
+    d = W.dielectric(12, 4)
+    n = len(d["areas"])
+    say(f"test_gmres_dielectric_with_graph_replay_matches: n={n}")
+    opts = F.fmm_default_options(order=6, leaf_size=48, src_kernels=F.FMM_SRC_SINGLE, outputs=F.FMM_OUT_FIELD)
+    nrm = dev(d["normals"])
+    plan = F.fmm_setup(dev(d["xyz"]), nrm, None, nrm, options=opts)
+    eps_i = np.asarray(d["eps_i"], np.float64)
+    lam = (eps_i - 1.0) / (eps_i + 1.0)
+    a = dev(np.ones(n, np.float32))
+    c = dev((-2.0 * lam).astype(np.float32))
+    w = dev(d["areas"])
+    b = dev((2.0 * lam * d["normals"][:, 2]).astype(np.float64))
+    x1 = dev(np.zeros(n))
+    r1 = F.gmres_solve(plan, F.FMM_OP_DIELECTRIC, a, c, w, b, x1, rtol=1e-7, restart=4)
+    F.fmm_set_graph(plan, True)
+    x2 = dev(np.zeros(n))
+    r2 = F.gmres_solve(plan, F.FMM_OP_DIELECTRIC, a, c, w, b, x2, rtol=1e-7, restart=4)
+    torch.cuda.synchronize()
+    say(f"  eager {r1}, graph {r2}")
+    assert r1[0] == F.FMM_OK and r2[0] == F.FMM_OK and r1[1] == r2[1] and r1[1] > 4
+    assert torch.equal(x1, x2)
     F.fmm_destroy(plan)
