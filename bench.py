@@ -375,6 +375,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--graph-steps", type=int, default=20,
+                    help="graph replays timed after the ordinary steps (0: none, e.g. under a profiler)")
     ap.add_argument("--n", type=int, default=4_000_000)
     ap.add_argument("--order", type=int, default=8)
     ap.add_argument("--leaf", type=int, default=192, help="leaf size for --no-tune runs")
@@ -553,7 +555,7 @@ def main():
         for cfg, prec in cands:
             log(f"bench: form {name} {PREC_NAMES[prec]} {cfg}: setup + {args.warmup} warmup + {args.steps} timed steps")
             r = run_form(F, torch, x, nrm, q, mu, prec, cfg[0], cfg[1], cfg[3], cfg[2], args.steps, args.warmup,
-                         graph_steps=20)
+                         graph_steps=args.graph_steps)
             r["prec"], r["cfg"] = prec, cfg
             timed.append(r)
             log(f"bench: form {name} {PREC_NAMES[prec]} {cfg}: {r['ms']:.3f} ms/step")
