@@ -391,7 +391,10 @@ int fmm_pinv(const double *K, int n, double eps, double *out);
 int fmm_unit_surface(int p, double *out, int *ns);
 
 /* Turn per-stage device timing on or off for later applies of this plan
- * (hipEvents recorded on the apply's stream; the apply then waits for them). */
+ * (hipEvents recorded on the streams the stages run on). A timed apply does
+ * not wait for its events: they are read by fmm_stage_times. The plan keeps
+ * the events of up to 16 timed applies; an apply that would reuse the events
+ * of one not yet read waits for those and adds them to the next report. */
 int fmm_set_timing(fmm_plan plan, int enable);
 
 /* Turn graph replay on or off for later applies of this plan. When on, the
@@ -422,8 +425,10 @@ int fmm_set_graph(fmm_plan plan, int enable);
  */
 int fmm_export_stage(fmm_plan plan, int which, float *host_out);
 
-/* Device time (ms) of each stage of the last apply made with timing on
- * (fmm_set_timing); -1 when none was. Order: P2M, M2M, P2L, M2L, L2L, C2E, EVAL.
+/* Device time (ms) of each stage: the mean over the applies made with
+ * timing on (fmm_set_timing) since the previous call, which this call waits
+ * for; when there were none since, the previous means again; -1 when no apply
+ * was ever timed. Order: P2M, M2M, P2L, M2L, L2L, C2E, EVAL.
  * Both forms run the leaf evaluation's near field on a second stream beside
  * M2L (its time is taken there). CHEBYSHEV plans also run P2L there, C2E is
  * their L2P, and their M2L stage times the translation kernel, the reduction

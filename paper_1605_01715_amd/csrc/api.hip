@@ -680,6 +680,7 @@ int fmm_stage_times(fmm_plan plan, double *ms) {
         using namespace fmm;
         Plan &P = live(plan);
         FMM_REQUIRE(ms != nullptr, "fmm_stage_times: out is NULL");
+        plan_report_times(P);
         for (int k = 0; k < ST_COUNT; ++k) ms[k] = P.have_times ? P.stage_ms[k] : -1.0;
     });
 }

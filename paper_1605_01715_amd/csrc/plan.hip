@@ -968,17 +968,53 @@ static void run_gemm(GemmJob &j, const double *mats, int m_pad, int k_pad, const
     box_gemm_f64(a, s);
 }
 
+// adds one timed apply's stage times (its events, once they have completed) to the sums
+static void collect_slot(Plan &P, Plan::TimeSlot &ts) {
+    FMM_HIP(hipEventSynchronize(ts.ev[ST_COUNT]));
+    double ms_k[ST_COUNT];
+    for (int k = 0; k < ST_COUNT; ++k) {
+        float ms = 0.f;
+        FMM_HIP(hipEventElapsedTime(&ms, ts.ev[k], ts.ev[k + 1]));
+        ms_k[k] = ms;
+    }
+    float ms = 0.f;
+    if (P.cheb) {
+        // L2L ends before the join; P2L and the evaluation ran on the side stream
+        FMM_HIP(hipEventElapsedTime(&ms, ts.ev[ST_L2L], ts.l2l_end));
+        ms_k[ST_L2L] = ms;
+        FMM_HIP(hipEventElapsedTime(&ms, ts.side[0], ts.side[1]));
+        ms_k[ST_P2L] = ms;
+        FMM_HIP(hipEventElapsedTime(&ms, ts.side[2], ts.side[3]));
+        ms_k[ST_EVAL] = ms;
+    } else {
+        // the near field ran on the side stream; EVAL is it plus the L2P pass
+        FMM_HIP(hipEventElapsedTime(&ms, ts.side[2], ts.side[3]));
+        ms_k[ST_EVAL] += ms;
+    }
+    for (int k = 0; k < ST_COUNT; ++k) P.stage_sum[k] += ms_k[k];
+    ++P.stage_n;
+    ts.pending = false;
+}
+
 void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s, bool capturing) {
     Tree &t = P.t;
     const int nrhs = P.nrhs;
     const Operators &op = *P.ops;
-    if (P.timing && !P.ev[0]) {  // the stage events, on the first timed apply from any entry point
-        for (auto &e : P.ev) FMM_HIP(hipEventCreate(&e));
-        for (auto &e : P.ev_side) FMM_HIP(hipEventCreate(&e));
-        FMM_HIP(hipEventCreate(&P.ev_l2l_end));
+    // a timed apply records its stage events in the next slot (created on
+    // first use, from whichever entry point applies)
+    Plan::TimeSlot *ts = nullptr;
+    if (P.timing && !capturing) {
+        ts = &P.tslot[P.tnext];
+        if (!ts->ev[0]) {
+            for (auto &e : ts->ev) FMM_HIP(hipEventCreate(&e));
+            for (auto &e : ts->side) FMM_HIP(hipEventCreate(&e));
+            FMM_HIP(hipEventCreate(&ts->l2l_end));
+        }
+        if (ts->pending) collect_slot(P, *ts);
+        P.tnext = (P.tnext + 1) % Plan::kTimeSlots;
     }
     auto mark = [&](int k) {
-        if (P.timing) FMM_HIP(hipEventRecord(P.ev[k], s));
+        if (ts) FMM_HIP(hipEventRecord(ts->ev[k], s));
     };
     const bool sl = q != nullptr, dl = mu != nullptr;
     hipLaunchKernelGGL(k_sort_densities, dim3(grid_for(t.n_src, kBlock)), dim3(kBlock), 0, s, t.src_perm.p, t.n_src,
@@ -1078,10 +1114,10 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         // side stream, first: P2L at the nodes, beside P2M and M2M
         FMM_HIP(hipEventRecord(P.fork0, s));
         FMM_HIP(hipStreamWaitEvent(P.side, P.fork0, 0));
-        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[0], P.side));
+        if (ts) FMM_HIP(hipEventRecord(ts->side[0], P.side));
         points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, 1.0, g, src, P.phi_d.p,
                           false, P.side);
-        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[1], P.side));
+        if (ts) FMM_HIP(hipEventRecord(ts->side[1], P.side));
         FMM_HIP(hipEventRecord(P.p2l_done, P.side));
         mark(ST_P2M);
         points_to_nodes(nrhs, sl, dl, op.p, op.cheb_coef.p, P.p2m_items.p, P.n_p2m, P.p2m_roff.p, P.p2m_rng.p, g, src,
@@ -1095,9 +1131,9 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         // side stream, second: the leaf evaluation, beside M2L and L2L
         FMM_HIP(hipEventRecord(P.fork, s));
         FMM_HIP(hipStreamWaitEvent(P.side, P.fork, 0));
-        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[2], P.side));
+        if (ts) FMM_HIP(hipEventRecord(ts->side[2], P.side));
         eval_leaves(nrhs, sl, dl, e, g, src, P.side);
-        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[3], P.side));
+        if (ts) FMM_HIP(hipEventRecord(ts->side[3], P.side));
         FMM_HIP(hipEventRecord(P.join, P.side));
         mark(ST_P2L);  // (P2L runs on the side stream; timed there)
         // the split of the M2L input queues behind the evaluation's
@@ -1114,7 +1150,7 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
                        P.col_iscale.p, 1, s);
         for (auto &j : P.cheb_l2l)
             cheb_tensor(nrhs, op.p, true, op.cheb_s1.p, j.n, j.dst.p, j.src.p, j.oct.p, P.phi_d.p, P.phi_d.p, np, s);
-        if (P.timing) FMM_HIP(hipEventRecord(P.ev_l2l_end, s));
+        if (ts) FMM_HIP(hipEventRecord(ts->l2l_end, s));
         FMM_HIP(hipStreamWaitEvent(s, P.join, 0));
         mark(ST_C2E);  // the Chebyshev L2P takes the slot of the surface form's check-to-equivalent maps
         EvalArgs el = e;
@@ -1135,11 +1171,11 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         run_gemm(P.c2e_up, op.cu_f64.p, np, rp, P.ut.p, P.phi_u.p, P.col_scale.p, false, s);
         FMM_HIP(hipEventRecord(P.fork, s));
         FMM_HIP(hipStreamWaitEvent(P.side, P.fork, 0));
-        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[2], P.side));
+        if (ts) FMM_HIP(hipEventRecord(ts->side[2], P.side));
         EvalArgs en = e;
         en.surf_mask = 2;  // M2P surfaces and the point ranges
         eval_leaves(nrhs, sl, dl, en, g, src, P.side);
-        if (P.timing) FMM_HIP(hipEventRecord(P.ev_side[3], P.side));
+        if (ts) FMM_HIP(hipEventRecord(ts->side[3], P.side));
         FMM_HIP(hipEventRecord(P.join, P.side));
         mark(ST_P2L);
         points_to_surface(nrhs, sl, dl, P.p2l_items.p, P.n_p2l, P.p2l_roff.p, P.p2l_rng.p, kRadIn, g, src, P.chk.p,
@@ -1161,31 +1197,20 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         eval_leaves(nrhs, sl, dl, ef, g, src, s);
     }
     mark(ST_COUNT);
-    if (P.timing && !capturing) plan_collect_times(P);
+    if (ts) ts->pending = true;
 }
 
-void plan_collect_times(Plan &P) {
-    FMM_HIP(hipEventSynchronize(P.ev[ST_COUNT]));
+void plan_report_times(Plan &P) {
+    for (int i = 0; i < Plan::kTimeSlots; ++i) {
+        Plan::TimeSlot &ts = P.tslot[(P.tnext + i) % Plan::kTimeSlots];  // oldest first
+        if (ts.pending) collect_slot(P, ts);
+    }
+    if (P.stage_n == 0) return;
     for (int k = 0; k < ST_COUNT; ++k) {
-        float ms = 0.f;
-        FMM_HIP(hipEventElapsedTime(&ms, P.ev[k], P.ev[k + 1]));
-        P.stage_ms[k] = ms;
+        P.stage_ms[k] = P.stage_sum[k] / P.stage_n;
+        P.stage_sum[k] = 0.0;
     }
-    if (P.cheb) {
-        // L2L ends before the join; P2L and the evaluation ran on the side stream
-        float ms = 0.f;
-        FMM_HIP(hipEventElapsedTime(&ms, P.ev[ST_L2L], P.ev_l2l_end));
-        P.stage_ms[ST_L2L] = ms;
-        FMM_HIP(hipEventElapsedTime(&ms, P.ev_side[0], P.ev_side[1]));
-        P.stage_ms[ST_P2L] = ms;
-        FMM_HIP(hipEventElapsedTime(&ms, P.ev_side[2], P.ev_side[3]));
-        P.stage_ms[ST_EVAL] = ms;
-    } else {
-        // the near field ran on the side stream; EVAL is it plus the L2P pass
-        float ms = 0.f;
-        FMM_HIP(hipEventElapsedTime(&ms, P.ev_side[2], P.ev_side[3]));
-        P.stage_ms[ST_EVAL] += ms;
-    }
+    P.stage_n = 0;
     P.have_times = true;
 }
 
@@ -1202,17 +1227,19 @@ void plan_release_events(Plan &P) {
         (void)hipStreamDestroy(P.side);
         P.side = nullptr;
     }
-    for (hipEvent_t *e : {&P.fork0, &P.p2l_done, &P.fork, &P.join, &P.ev_side[0], &P.ev_side[1], &P.ev_side[2],
-                          &P.ev_side[3], &P.ev_l2l_end})
+    for (hipEvent_t *e : {&P.fork0, &P.p2l_done, &P.fork, &P.join})
         if (*e) {
             (void)hipEventDestroy(*e);
             *e = nullptr;
         }
-    for (auto &e : P.ev)
-        if (e) {
-            (void)hipEventDestroy(e);
-            e = nullptr;
-        }
+    for (auto &ts : P.tslot) {
+        for (auto &e : ts.ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto &e : ts.side)
+            if (e) (void)hipEventDestroy(e);
+        if (ts.l2l_end) (void)hipEventDestroy(ts.l2l_end);
+        ts = Plan::TimeSlot{};
+    }
 }
 
 void plan_apply_graph(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s) {

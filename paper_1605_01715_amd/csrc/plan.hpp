@@ -103,9 +103,20 @@ struct Plan {
     hipEvent_t fork0 = nullptr, p2l_done = nullptr, fork = nullptr, join = nullptr;
 
     bool timing = false;
-    hipEvent_t ev[ST_COUNT + 1] = {};
-    hipEvent_t ev_side[4] = {};      // P2L start / end, evaluation start / end on the side stream (timing)
-    hipEvent_t ev_l2l_end = nullptr;  // end of L2L before the join (timing)
+    // Stage events of timed applies, one set per slot. Applies take the slots
+    // in turn and do not wait for their events; fmm_stage_times collects them
+    // (an apply that finds its slot still uncollected collects it first).
+    struct TimeSlot {
+        hipEvent_t ev[ST_COUNT + 1] = {};
+        hipEvent_t side[4] = {};       // P2L start / end, evaluation start / end on the side stream
+        hipEvent_t l2l_end = nullptr;  // end of L2L before the join
+        bool pending = false;
+    };
+    static constexpr int kTimeSlots = 16;
+    TimeSlot tslot[kTimeSlots];
+    int tnext = 0;                       // the slot the next timed apply takes
+    double stage_sum[ST_COUNT] = {};     // over the applies collected since the last report
+    int stage_n = 0;
     double stage_ms[ST_COUNT] = {-1, -1, -1, -1, -1, -1, -1};
     bool have_times = false;
 };
@@ -117,7 +128,9 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
 // the same pointers (re-captured otherwise). Runs on a plan-owned stream
 // ordered after and before the caller's stream s.
 void plan_apply_graph(Plan &P, const float *q, const float *mu, float *pot, float *field, hipStream_t s);
-void plan_collect_times(Plan &P);
+// Stage times: the mean over the timed applies since the last report (every
+// pending slot collected first); kept for later calls when there were none.
+void plan_report_times(Plan &P);
 void plan_release_graph(Plan &P);
 // Streams and events the plan owns (side stream, fork/join, timing events).
 void plan_create_side(Plan &P);

@@ -80,3 +80,45 @@ def test_setup_phase_times_add_up():
         assert ph["sort"] > 0 and ph["lists"] > 0 and ph["m2l_schedule"] > 0 and ph["worklists"] > 0
         assert ph["unused"] == 0.0
     assert infos[1]["setup_phase_ms"]["operators"] < 1.0
+
+
+@pytest.mark.parametrize("basis", [0, 1])
+def test_stage_times_are_means_over_timed_applies(basis):
+    """fmm_stage_times reads the events of the timed applies made since the
+    previous call (the applies do not wait for them): -1 before any timed
+    apply, the means after, the same means again when nothing new was timed,
+    and more timed applies than the plan keeps event sets for (16) are still
+    all counted. Timed applies give the same potentials as untimed ones."""
+    import torch
+
+    import paper_1605_01715_amd as F
+
+    d = W.clustered(40_000, seed=22)
+    say(f"test_stage_times_are_means_over_timed_applies: n=40000 basis={basis}")
+    opts = F.fmm_default_options(order=6, leaf_size=64, basis=basis,
+                                 src_kernels=F.FMM_SRC_SINGLE | F.FMM_SRC_DOUBLE)
+    x, q, mu = dev(d["xyz"]), dev(d["q"]), dev(d["mu"])
+    plan = F.fmm_setup(x, dev(d["normals"]), options=opts)
+    ref = torch.empty(len(d["q"]), device="cuda:0")
+    F.fmm_apply(plan, q=q, mu=mu, pot=ref)
+    st0 = F.fmm_stage_times(plan)
+    assert all(v == -1.0 for v in st0.values())
+    F.fmm_set_timing(plan, True)
+    pot = torch.empty_like(ref)
+    for _ in range(3):
+        F.fmm_apply(plan, q=q, mu=mu, pot=pot)
+    st1 = F.fmm_stage_times(plan)
+    say(f"  3 timed applies: {st1}")
+    assert all(v >= 0.0 for v in st1.values()) and st1["EVAL"] > 0.0 and st1["M2L"] > 0.0
+    assert F.fmm_stage_times(plan) == st1
+    for _ in range(20):
+        F.fmm_apply(plan, q=q, mu=mu, pot=pot)
+    st2 = F.fmm_stage_times(plan)
+    say(f"  20 timed applies: {st2}")
+    assert all(v >= 0.0 for v in st2.values())
+    # the same work: the means agree to within the run-to-run spread
+    assert 0.3 < st2["EVAL"] / st1["EVAL"] < 3.0
+    torch.cuda.synchronize()
+    assert torch.equal(pot, ref)
+    F.fmm_set_timing(plan, False)
+    F.fmm_destroy(plan)
