@@ -34,6 +34,15 @@
  *     ABI. On failure, fmm_last_error() returns a message describing it
  *     (thread-local, valid until the next call on the same thread).
  *   - Point arrays are float32, array-of-structures [n][3] (x, y, z).
+ *
+ * Environment variables read by the library:
+ *   FMM_LOG            set (and not "0"): diagnostics on stderr
+ *   FMM_TUNE_CACHE     the autotuner's cache file (fmm_autotune)
+ *   FMM_FAULT_INJECT   "alloc:<k>": the k-th device allocation counted from
+ *                      when the variable took this value fails with
+ *                      FMM_ERR_NOMEM, as if the device were out of memory
+ *                      (for tests of the error paths; every buffer the failing
+ *                      call had allocated is released)
  */
 #ifndef FMM_MI355X_H
 #define FMM_MI355X_H

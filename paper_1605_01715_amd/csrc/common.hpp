@@ -39,6 +39,12 @@ struct Error : std::runtime_error {
         if (!(c)) throw ::fmm::Error(FMM_ERR_ARG, (msg));    \
     } while (0)
 
+// Failure injection for tests of the error paths: with the environment
+// variable FMM_FAULT_INJECT=alloc:<k> the k-th device allocation counted from
+// when the variable took its current value fails as if the device were out
+// of memory (FMM_ERR_NOMEM). Returns true for the allocation that must fail.
+bool inject_alloc_failure();
+
 // Owning device buffer (hipMalloc'd; freed on destruction).
 template <class T>
 struct DBuf {
@@ -56,8 +62,20 @@ struct DBuf {
     ~DBuf() { release(); }
     void alloc(size_t count) {
         release();
+        if (!count) return;
+        // on failure, the work already queued finishes before the buffers the
+        // failing call had allocated are released on the way out
+        if (inject_alloc_failure()) {
+            (void)hipDeviceSynchronize();
+            throw Error(FMM_ERR_NOMEM, "device allocation failed (injected by FMM_FAULT_INJECT)");
+        }
+        const hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipDeviceSynchronize();
+            FMM_HIP(e);
+        }
         n = count;
-        if (count) FMM_HIP(hipMalloc(&p, count * sizeof(T)));
     }
     void release() {
         if (p) (void)hipFree(p);

@@ -10,16 +10,17 @@
 //
 // Blocking. A workgroup owns a tile of 128 target boxes of one octant. With
 // 8 waves each takes one 32-column block and one half of the rows; with 4
-// (split-BF16 up to r_pad 192, two workgroups per CU) each takes one column
+// (split-BF16 up to r_pad 192, two or three workgroups per CU) each takes one column
 // block and all rows. The workgroup keeps the r_pad x 128 accumulator in
 // registers across all directions, so every output is written once. Each step of the tile is one
 // (direction, 32-wide k-chunk): the chunk of M_d and the tile's 128 source
 // chunks are copied from global memory straight into LDS (global_load_lds,
 // 16 bytes per lane, no registers on the way) and every wave multiplies
 // them. With 32x32 MFMA tiles each staged matrix element is read from LDS once
-// per 32 columns. With two LDS buffers (split-BF16) the copies of step s + 1
+// per 32 columns. With two LDS buffers (8-wave split-BF16) the copies of step s + 1
 // are issued at the start of step s and run under its MFMAs; with one
-// (float32, and the 4-wave split-BF16 form), two workgroups share each CU.
+// (float32, and the 4-wave split-BF16 form), two or three workgroups share
+// each CU.
 // The tiles of one octant run on one XCD (they share most directions, so
 // concurrently running tiles reuse the matrices in that XCD's L2).
 //
@@ -110,7 +111,7 @@ __device__ inline void copy_to_lds(const void *src, void *dst) {
 
 // NW = 8 waves: 4 column blocks x 2 row halves, two LDS buffers when they
 // fit. NW = 4 waves: one column block each with every row block, one buffer,
-// so that two workgroups share a CU and cover each other's copies and
+// so that two or three workgroups share a CU and cover each other's copies and
 // barriers. Either way every wave reads the matrix chunk rows it multiplies
 // (4 reads of the chunk per step); with 4 waves the source chunk is read
 // once per column block instead of twice (one row half each).

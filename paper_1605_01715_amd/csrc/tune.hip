@@ -75,6 +75,21 @@ bool log_enabled() {
     return on;
 }
 
+bool inject_alloc_failure() {
+    static std::mutex mu;
+    static std::string value;  // the variable's value the count belongs to
+    static long count = 0;
+    const char *v = std::getenv("FMM_FAULT_INJECT");
+    if (v == nullptr || std::strncmp(v, "alloc:", 6) != 0) return false;
+    std::lock_guard<std::mutex> lock(mu);
+    if (value != v) {
+        value = v;
+        count = 0;
+    }
+    const long k = std::strtol(v + 6, nullptr, 10);
+    return ++count == k;
+}
+
 void log_printf(const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);

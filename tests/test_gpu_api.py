@@ -122,3 +122,58 @@ def test_stage_times_are_means_over_timed_applies(basis):
     assert torch.equal(pot, ref)
     F.fmm_set_timing(plan, False)
     F.fmm_destroy(plan)
+
+
+def test_injected_allocation_failure_is_reported_and_recovered():
+    """FMM_FAULT_INJECT=alloc:<k> makes the k-th device allocation fail: setup,
+    apply and gmres_solve return FMM_ERR_NOMEM with a message, release what
+    they had allocated, and work again once the variable is unset (the
+    results equal those of a run without injection)."""
+    import os
+
+    import torch
+
+    import paper_1605_01715_amd as F
+
+    d = W.clustered(20_000, seed=23)
+    say("test_injected_allocation_failure_is_reported_and_recovered: n=20000")
+    x, q = dev(d["xyz"]), dev(d["q"])
+    opts = F.fmm_default_options(order=6, leaf_size=64)
+    plan = F.fmm_setup(x, options=opts)
+    ref = torch.empty(len(d["q"]), device="cuda:0")
+    F.fmm_apply(plan, q=q, pot=ref)
+    plan_dl = F.fmm_setup(x, dev(d["normals"]),
+                          options=F.fmm_default_options(order=6, leaf_size=64, src_kernels=F.FMM_SRC_DOUBLE))
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    try:
+        for k in (1, 3, 17):
+            os.environ["FMM_FAULT_INJECT"] = f"alloc:{k}"
+            with pytest.raises(F.FmmError) as e:
+                F.fmm_setup(x, options=opts)
+            say(f"  setup, allocation {k}: {e.value}")
+            assert e.value.code == F.FMM_ERR_NOMEM and "FMM_FAULT_INJECT" in str(e.value)
+        # a solve allocates its work vectors: the first of its allocations fails
+        n = len(d["q"])
+        os.environ["FMM_FAULT_INJECT"] = "alloc:1"
+        a, w = dev(np.ones(n, np.float32)), dev(np.full(n, 1e-3, np.float32))
+        b, xs = dev(np.ones(n)), dev(np.zeros(n))
+        with pytest.raises(F.FmmError) as e:
+            F.gmres_solve(plan_dl, F.FMM_OP_FK, a, None, w, b, xs, rtol=1e-6, max_iter=3)
+        assert e.value.code == F.FMM_ERR_NOMEM
+    finally:
+        del os.environ["FMM_FAULT_INJECT"]
+    rc = F.gmres_solve(plan_dl, F.FMM_OP_FK, a, None, w, b, xs, rtol=1e-6, max_iter=3)
+    assert rc[0] in (F.FMM_OK, F.FMM_ERR_NOT_CONVERGED)
+    F.fmm_destroy(plan_dl)
+    torch.cuda.synchronize()
+    # nothing leaked by the failed calls (the torch allocations above are small)
+    assert torch.cuda.mem_get_info()[0] >= free0 - (64 << 20)
+    plan2 = F.fmm_setup(x, options=opts)
+    pot = torch.empty_like(ref)
+    F.fmm_apply(plan2, q=q, pot=pot)
+    F.fmm_apply(plan, q=q, pot=ref.clone())
+    torch.cuda.synchronize()
+    assert torch.equal(pot, ref)
+    F.fmm_destroy(plan2)
+    F.fmm_destroy(plan)
