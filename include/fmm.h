@@ -38,6 +38,10 @@
  * Environment variables read by the library:
  *   FMM_LOG            set (and not "0"): diagnostics on stderr
  *   FMM_TUNE_CACHE     the autotuner's cache file (fmm_autotune)
+ *   FMM_OP_CACHE       directory of the cached float64 factorisations the
+ *                      operators are built from (default ~/.cache/fmm_mi355x_ops;
+ *                      "0" turns the cache off). A file that does not match its
+ *                      header or checksum is ignored and rewritten.
  *   FMM_FAULT_INJECT   "alloc:<k>": the k-th device allocation counted from
  *                      when the variable took this value fails with
  *                      FMM_ERR_NOMEM, as if the device were out of memory

@@ -16,8 +16,13 @@
 // evaluation at the targets).
 #include "operators.hpp"
 
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 
@@ -185,6 +190,103 @@ std::vector<double> m2l_params(double ro, double rs) {
     return prm;
 }
 
+// ---- on-disk cache of the float64 factorisations the operators start from
+// (the SVD of the check-to-equivalent map of the surface form, the
+// eigenvectors of the Chebyshev form's Gram matrix). They depend on the form
+// and the order only (the threshold truncates them afterwards) and take most
+// of the build time (a host Jacobi SVD of an n_s x n_s matrix). Directory:
+// FMM_OP_CACHE, else ~/.cache/fmm_mi355x_ops; FMM_OP_CACHE=0 turns it off.
+// A file holds a header (tag, format version, form, order, the surface radii,
+// array lengths) and a checksum of the data; a file that does not match is
+// ignored and rewritten. Files are written under a temporary name and renamed.
+constexpr char kOpTag[8] = {'F', 'M', 'M', 'O', 'P', 'S', '0', '1'};
+struct FactorHeader {
+    char tag[8];
+    int32_t form, order, narr, pad;
+    double rad_in, rad_out;
+    int64_t len[4];
+    uint64_t sum;  // FNV-1a over the data bytes
+};
+
+uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    return h;
+}
+
+std::string factor_path(int form, int order) {
+    const char *dir = std::getenv("FMM_OP_CACHE");
+    std::string d;
+    if (dir) {
+        if (!*dir || std::string(dir) == "0") return "";
+        d = dir;
+    } else {
+        const char *home = std::getenv("HOME");
+        if (!home) return "";
+        d = std::string(home) + "/.cache/fmm_mi355x_ops";
+    }
+    return d + "/" + (form == kBasisChebyshev ? "cheb" : "surface") + "_" + std::to_string(order) + ".f64";
+}
+
+FactorHeader factor_header(int form, int order, const std::vector<std::vector<double> *> &arrs) {
+    FactorHeader h{};
+    std::memcpy(h.tag, kOpTag, 8);
+    h.form = form;
+    h.order = order;
+    h.narr = (int)arrs.size();
+    h.rad_in = kRadIn;
+    h.rad_out = kRadOut;
+    for (size_t a = 0; a < arrs.size(); ++a) h.len[a] = (int64_t)arrs[a]->size();
+    return h;
+}
+
+// Fills arrs (sized by the caller) from the cache file; false if absent or not matching.
+bool load_factors(int form, int order, const std::vector<std::vector<double> *> &arrs) {
+    const std::string path = factor_path(form, order);
+    if (path.empty()) return false;
+    FILE *f = std::fopen(path.c_str(), "rb");
+    if (!f) return false;
+    const FactorHeader want = factor_header(form, order, arrs);
+    FactorHeader got{};
+    bool ok = std::fread(&got, sizeof got, 1, f) == 1 && std::memcmp(got.tag, want.tag, 8) == 0 &&
+              got.form == want.form && got.order == want.order && got.narr == want.narr &&
+              got.rad_in == want.rad_in && got.rad_out == want.rad_out;
+    for (size_t a = 0; ok && a < arrs.size(); ++a) ok = got.len[a] == want.len[a];
+    uint64_t sum = 1469598103934665603ull;
+    for (size_t a = 0; ok && a < arrs.size(); ++a) {
+        ok = std::fread(arrs[a]->data(), sizeof(double), arrs[a]->size(), f) == arrs[a]->size();
+        if (ok) sum = fnv1a(arrs[a]->data(), arrs[a]->size() * sizeof(double), sum);
+    }
+    ok = ok && sum == got.sum && std::fgetc(f) == EOF;
+    std::fclose(f);
+    FMM_LOG("operators: factors %s %s\n", path.c_str(), ok ? "read" : "do not match; rebuilt");
+    return ok;
+}
+
+void save_factors(int form, int order, const std::vector<std::vector<double> *> &arrs) {
+    const std::string path = factor_path(form, order);
+    if (path.empty()) return;
+    // create the directory and its parents (existing ones are fine)
+    const std::string dir = path.substr(0, path.rfind('/'));
+    for (size_t k = 1; k <= dir.size(); ++k)
+        if (k == dir.size() || dir[k] == '/') (void)mkdir(dir.substr(0, k).c_str(), 0755);
+    FactorHeader h = factor_header(form, order, arrs);
+    uint64_t sum = 1469598103934665603ull;
+    for (auto *a : arrs) sum = fnv1a(a->data(), a->size() * sizeof(double), sum);
+    h.sum = sum;
+    const std::string tmp = path + ".tmp." + std::to_string((long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return;  // the cache is an optimisation: no file, no error
+    bool ok = std::fwrite(&h, sizeof h, 1, f) == 1;
+    for (auto *a : arrs) ok = ok && std::fwrite(a->data(), sizeof(double), a->size(), f) == a->size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (ok && std::rename(tmp.c_str(), path.c_str()) == 0) {
+        FMM_LOG("operators: factors written to %s\n", path.c_str());
+    } else {
+        std::remove(tmp.c_str());
+    }
+}
+
 std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
     auto op = std::make_shared<Operators>();
     op->p = p;
@@ -205,8 +307,11 @@ std::shared_ptr<Operators> build_operators(int p, double eps, hipStream_t s) {
             }
             K[(size_t)i * n + j] = 1.0 / (kFourPi * std::sqrt(d2));
         }
-    std::vector<double> Uf, sv, Vf;
-    svd_jacobi(K, n, Uf, sv, Vf);
+    std::vector<double> Uf((size_t)n * n), sv(n), Vf((size_t)n * n);
+    if (!load_factors(kBasisSurface, p, {&Uf, &sv, &Vf})) {
+        svd_jacobi(K, n, Uf, sv, Vf);
+        save_factors(kBasisSurface, p, {&Uf, &sv, &Vf});
+    }
     int r = 0;
     while (r < n && sv[r] > eps * sv[0]) ++r;
     const int rp = ((r + 31) / 32) * 32;
@@ -329,6 +434,8 @@ std::shared_ptr<Operators> build_chebyshev(int n, double eps, hipStream_t s) {
             for (int c = 0; c < 3; ++c) std::swap(t[b + c], t[b + 4 + c]);
         return t;
     }();
+    std::vector<double> Qf((size_t)nn * nn), lam(nn), Vf;
+    if (!load_factors(kBasisChebyshev, n, {&Qf, &lam})) {
     std::vector<double> gram((size_t)nn * nn, 0.0);
     {
         const int chunk = 16, nb = (int)prm.size() / 9;
@@ -348,8 +455,9 @@ std::shared_ptr<Operators> build_chebyshev(int n, double eps, hipStream_t s) {
                 for (size_t e = 0; e < n2; ++e) gram[e] += h[b * n2 + e];
         }
     }
-    std::vector<double> Qf, lam, Vf;
     svd_jacobi(gram, nn, Qf, lam, Vf);
+    save_factors(kBasisChebyshev, n, {&Qf, &lam});
+    }
     // sigma_k = sqrt(lambda_k); float64 resolves lambda to ~1e-16 lambda_max
     const double thr = std::max(eps * eps, 1e-15) * lam[0];
     int r = 0;

@@ -177,3 +177,62 @@ def test_injected_allocation_failure_is_reported_and_recovered():
     assert torch.equal(pot, ref)
     F.fmm_destroy(plan2)
     F.fmm_destroy(plan)
+
+
+_OPS_SCRIPT = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, {root!r})
+import workloads as W
+import paper_1605_01715_amd as F
+d = W.clustered(20000, seed=24)
+x, q = torch.from_numpy(d["xyz"]).cuda(), torch.from_numpy(d["q"]).cuda()
+for basis, order in ((0, 6), (1, 5)):
+    plan = F.fmm_setup(x, options=F.fmm_default_options(order=order, leaf_size=64, basis=basis))
+    pot = torch.empty(20000, device="cuda")
+    F.fmm_apply(plan, q=q, pot=pot)
+    np.save({out!r} + "_%d.npy" % basis, pot.cpu().numpy())
+    F.fmm_destroy(plan)
+"""
+
+
+def test_operator_factors_cached_on_disk(tmp_path):
+    """The float64 factorisations the operators are built from are written to
+    FMM_OP_CACHE by the first process and read by the next (same potentials
+    bit for bit); a damaged file is detected, ignored and rewritten."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    ops = tmp_path / "ops"
+    env = dict(os.environ, FMM_OP_CACHE=str(ops), FMM_LOG="1")
+
+    def run(tag):
+        out = str(tmp_path / tag)
+        say(f"test_operator_factors_cached_on_disk: process {tag}")
+        r = subprocess.run([sys.executable, "-c", _OPS_SCRIPT.format(root=root, out=out)], env=env,
+                           capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        lines = [l for l in r.stderr.splitlines() if "operators: factors" in l]
+        say("  " + " | ".join(lines))
+        return lines, [np.load(out + "_%d.npy" % b) for b in (0, 1)]
+
+    first, pots1 = run("a")
+    assert sum("written to" in l for l in first) == 2
+    files = sorted(p.name for p in ops.iterdir())
+    assert files == ["cheb_5.f64", "surface_6.f64"]
+    second, pots2 = run("b")
+    assert sum(l.endswith("read") for l in second) == 2 and not any("written" in l for l in second)
+    for a, b in zip(pots1, pots2):
+        assert np.array_equal(a, b)
+    # flip one byte of the data: detected by the checksum, rebuilt and rewritten
+    f = ops / "surface_6.f64"
+    raw = bytearray(f.read_bytes())
+    raw[-100] ^= 0x40
+    f.write_bytes(bytes(raw))
+    third, pots3 = run("c")
+    assert any("do not match" in l for l in third) and any("written to" in l for l in third)
+    for a, b in zip(pots1, pots3):
+        assert np.array_equal(a, b)
