@@ -13,9 +13,11 @@ Chebyshev form with 8 nodes per axis) gets its leaf size from the library's
 autotuner (trial runs, as the paper tunes its octree height, Sec. III.A.1),
 whose choice the plan then reads back from the tuning cache (leaf_size = 0).
 Its error is measured against the float64 direct sum on two independent sets
-of 10,000 targets (seeds 1 and 7); the fastest form whose error meets the
-target on both is timed in full. The error reported is the one on the seed-1
-set, the definition of the metric; the seed-7 error is reported beside it.
+of 10,000 targets (seeds 1 and 7); the two fastest forms whose error meets
+the target on both are timed in full (ordinary applies with the library's
+stage events, read once after the timed steps; then graph replays) and the
+faster is the line's. The error reported is the one on the seed-1 set, the
+definition of the metric; the seed-7 error is reported beside it.
 
 Prints one JSON line (one GPU).
 """
