@@ -202,6 +202,7 @@ void finish_plan(fmm::Plan &P, const fmm_options *opt, const float *trg_nrm, hip
         P.my.alloc(nsv);
         P.mz.alloc(nsv);
     }
+    if (P.sl && P.dl) P.qm.alloc(2 * nsv);
     if (trg_nrm && !P.t.tsm && P.t.n_src) {
         P.trg_nrm_user.alloc(3 * (size_t)P.t.n_src);
         FMM_HIP(hipMemcpyAsync(P.trg_nrm_user.p, trg_nrm, 3 * P.t.n_src * sizeof(float), hipMemcpyDeviceToDevice, s));

@@ -150,6 +150,29 @@ __global__ void k_zero(float *p, int64_t n) {
     if (i < n) p[i] = 0.f;
 }
 
+// Both layers: the two densities side by side first (coalesced), so that the
+// gather into tree order below fetches one 8-byte pair per point from a
+// random place instead of two 4-byte values from two (the caller's order is
+// arbitrary, so every such fetch moves a whole cache line).
+__global__ void k_pair_densities(int64_t total, const float *q, const float *mu, float2 *qm) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < total) qm[i] = make_float2(q[i], mu[i]);
+}
+
+__global__ void k_sort_density_pairs(const int64_t *perm, int64_t n, int nrhs, const float2 *qm, const float *nx,
+                                     const float *ny, const float *nz, float *qs, float *mx, float *my, float *mz) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int64_t o = perm[i];
+    for (int r = 0; r < nrhs; ++r) {
+        const float2 v = qm[r * n + o];
+        qs[r * n + i] = v.x;
+        mx[r * n + i] = v.y * nx[i];
+        my[r * n + i] = v.y * ny[i];
+        mz[r * n + i] = v.y * nz[i];
+    }
+}
+
 __global__ void k_sort_densities(const int64_t *perm, int64_t n, int nrhs, const float *q, const float *mu,
                                  const float *nx, const float *ny, const float *nz, float *qs, float *mx, float *my,
                                  float *mz) {
@@ -1017,8 +1040,17 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         if (ts) FMM_HIP(hipEventRecord(ts->ev[k], s));
     };
     const bool sl = q != nullptr, dl = mu != nullptr;
-    hipLaunchKernelGGL(k_sort_densities, dim3(grid_for(t.n_src, kBlock)), dim3(kBlock), 0, s, t.src_perm.p, t.n_src,
-                       nrhs, q, mu, t.snx.p, t.sny.p, t.snz.p, P.q_sorted.p, P.mx.p, P.my.p, P.mz.p);
+    if (sl && dl && P.qm.n) {
+        const int64_t total = (int64_t)nrhs * t.n_src;
+        hipLaunchKernelGGL(k_pair_densities, dim3(grid_for(total, kBlock)), dim3(kBlock), 0, s, total, q, mu,
+                           (float2 *)P.qm.p);
+        hipLaunchKernelGGL(k_sort_density_pairs, dim3(grid_for(t.n_src, kBlock)), dim3(kBlock), 0, s, t.src_perm.p,
+                           t.n_src, nrhs, (const float2 *)P.qm.p, t.snx.p, t.sny.p, t.snz.p, P.q_sorted.p, P.mx.p,
+                           P.my.p, P.mz.p);
+    } else {
+        hipLaunchKernelGGL(k_sort_densities, dim3(grid_for(t.n_src, kBlock)), dim3(kBlock), 0, s, t.src_perm.p,
+                           t.n_src, nrhs, q, mu, t.snx.p, t.sny.p, t.snz.p, P.q_sorted.p, P.mx.p, P.my.p, P.mz.p);
+    }
     FMM_HIP(hipGetLastError());
     if (P.dt.n) {
         hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)P.dt.n, kBlock)), dim3(kBlock), 0, s, P.dt.p, (int64_t)P.dt.n);

@@ -44,6 +44,7 @@ struct Plan {
     DBuf<float> chk;                        // [nb * nrhs][n_pad] check potentials made from points
     DBuf<float> phi_u, phi_d;               // [nb * nrhs][n_pad] equivalent densities
     DBuf<float> q_sorted, mx, my, mz;       // [nrhs][n_src]
+    DBuf<float> qm;                         // [nrhs][n_src][2]: q and mu side by side (both layers)
     DBuf<double> col_scale;                 // half-width per vector index
     DBuf<double> col_iscale;                // 1 / half-width per vector index (Chebyshev M2L expansion)
     DBuf<float> trg_nrm_user;               // [n_trg][3] target normals, caller's order
