@@ -184,8 +184,14 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const double *coef, Eval
                 if (lane + 64 * i < NN) sl[r * NN + lane + 64 * i] = lv[r][i];
     }
     __syncthreads();
-    if (lane >= nt) return;
-    const int64_t k = t_first + lane;
+    // SP lanes per target for short items (SP a power of two, nt SP <= 64):
+    // lane part takes x-nodes i = part, part + SP, ..., and the SP partial
+    // sums are added across the group's lanes at the end (a fixed order)
+    int SP = 1;
+    while (SP * 2 <= N && nt * SP * 2 <= 64) SP *= 2;
+    const int part = lane & (SP - 1), tl = lane / SP;
+    const bool valid = tl < nt;
+    const int64_t k = t_first + (valid ? tl : 0);
     const double ih = 1.0 / g.half[leaf];
     const double tx = ((double)a.tx[k] - g.centre[3 * leaf]) * ih;
     const double ty = ((double)a.ty[k] - g.centre[3 * leaf + 1]) * ih;
@@ -202,7 +208,7 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const double *coef, Eval
         // the x axis stays a loop (n^2 node values live at a time); S_x(i) is
         // formed from row i of the coefficients
 #pragma unroll 1
-        for (int i = 0; i < N; ++i) {
+        for (int i = part; i < N; i += SP) {
             double sxi = 0.0, dsxi = 0.0;
 #pragma unroll
             for (int q = 0; q < N; ++q) {
@@ -232,6 +238,15 @@ __global__ __launch_bounds__(64) void k_nodes_to_points(const double *coef, Eval
                 gz += sxi * biz;
             }
         }
+        for (int o = 1; o < SP; o <<= 1) {
+            pot += __shfl_xor(pot, o);
+            if (FIELD) {
+                gx += __shfl_xor(gx, o);
+                gy += __shfl_xor(gy, o);
+                gz += __shfl_xor(gz, o);
+            }
+        }
+        if (!valid || part != 0) continue;
         if (a.pot) {
             float *pp = a.pot + r * a.n_trg + dst;
             *pp = a.accumulate ? (float)((double)*pp + pot) : (float)pot;
