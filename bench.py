@@ -179,8 +179,12 @@ def roofline(res, precision, n, cfg):
             ext["mfma_issued_frac"] = round(issued / (ms_m2l * 1e-3) / 1e12 / peak_m2l, 5)
         return ext
 
+    # the counts the evaluation's FLOP model is applied to
+    eval_counts = {"near_pairs": info["p2p_pairs"], "surface_evals": info["surf_evals"]}
     if name == "M2L":
         out.update(m2l_extras(ms, peak))
+    else:
+        out.update(eval_counts)
     if bound == "alu":
         out["frac_unpacked"] = round(achieved / PEAK_TFLOPS["fp32_valu_unpacked"], 5)
     others = {}
@@ -190,6 +194,7 @@ def roofline(res, precision, n, cfg):
                      "avg_ms": round(t, 4), "flop_model": flop_models[k]}
     if cands["M2L"][1] > 0:
         others["M2L"].update(m2l_extras(cands["M2L"][1], cands["M2L"][3]))
+    others["EVAL"].update(eval_counts)
     if overlapped:
         others["M2L"]["note"] = ("stage time on the caller's stream: the translation kernel, its reduction and "
                                  "gather, which run beside the leaf evaluation on the plan's second stream")
@@ -201,6 +206,33 @@ def roofline(res, precision, n, cfg):
                               "note": "stage time includes queueing behind the leaf evaluation on the second "
                                       "stream; the kernel time is in the rocprofv3 trace"})
     return out, others
+
+
+def calibrate_issue(F, torch, dev, waves_per_simd=8, iters=2048):
+    """The library's issue-rate probes (independent chains, so only issue
+    limits them): wave64 VALU instructions per SIMD per 4 cycles, at the
+    2.4 GHz peak clock, from event times on the stream they are queued on.
+    One such instruction per 4 cycles is the unpacked float32 rate."""
+    simds, ghz = 1024, 2.4
+    out = torch.empty(simds * waves_per_simd * 64, device=dev)
+    names = ("fma", "rsq", "fma12_rsq1", "int_add_xor")
+    res = {}
+    for kind, name in enumerate(names):
+        F.fmm_issue_probe(kind, out, iters)  # warm-up
+        times = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            instr = F.fmm_issue_probe(kind, out, iters)
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = sorted(times)[len(times) // 2]
+        wave_instr = instr * out.numel() / 64
+        res[name] = {"median_ms": round(ms, 4), "wave64_instr": int(wave_instr),
+                     "per_simd_per_4_cycles": round(wave_instr / simds / (ms * 1e-3 * ghz * 1e9) * 4, 4)}
+    print(json.dumps({"issue_probe": res, "waves_per_simd": waves_per_simd, "iters": iters, "simds": simds,
+                      "clock_ghz_assumed": ghz}), flush=True)
 
 
 def paper_workloads(F, W, torch, dev):
@@ -402,6 +434,9 @@ def main():
                          "field) workloads in the surface form (order 8) and the Chebyshev form (n = 8 and 5)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
+    ap.add_argument("--calibrate-issue", action="store_true",
+                    help="only run the library's issue-rate probes (float32 FMA, reciprocal square root, the pair "
+                         "loop's 12:1 mix, integer) and report their VALU issue rates")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the FMM runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -425,6 +460,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}), flush=True)
+        return
+    if args.calibrate_issue:
+        calibrate_issue(F, torch, dev)
         return
     if args.setup_batch:
         setup_batch(F, W, torch, dev, args.setup_batch)

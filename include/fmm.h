@@ -450,6 +450,23 @@ int fmm_export_stage(fmm_plan plan, int which, float *host_out);
  * is the near field (second stream) plus the L2P pass after the join. */
 int fmm_stage_times(fmm_plan plan, double *ms /* [7] */);
 
+/* Measurement utility (no step of the method): an issue-rate probe, whose
+ * lanes run independent chains so that only instruction issue limits it,
+ * queued on hip_stream (asynchronous; the caller times it):
+ *   kind = 0  float32 fused multiply-adds (v_fma_f32), 16 chains;
+ *   kind = 1  float32 reciprocal square roots (v_rsq_f32), 16 chains;
+ *   kind = 2  8 chains, each step 12 fused multiply-adds and one reciprocal
+ *             square root (the ratio of the leaf evaluation's pair loop);
+ *   kind = 3  32-bit integer add then exclusive or, 8 chains.
+ *   nthreads  lanes, a positive multiple of 256, at most 2^24 (workgroups
+ *             of 256)
+ *   iters     chain steps per lane, 1..2^20
+ *   out       device float [nthreads], one value per lane (keeps the chains)
+ *   instr_per_lane  if not NULL, receives the wave64 VALU instructions of
+ *             the chains per lane: 16 iters (kinds 0, 1, 3), 104 iters (2)
+ * FMM_ERR_ARG for other arguments. */
+int fmm_issue_probe(int kind, int64_t nthreads, int iters, float *out, int64_t *instr_per_lane, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

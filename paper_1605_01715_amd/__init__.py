@@ -21,7 +21,7 @@ from ._lib import (FMM_BASIS_CHEBYSHEV, FMM_BASIS_SURFACE, FMM_ERR_ARG, FMM_ERR_
 
 __all__ = ["fmm_setup_batch", "Plan", "FmmError", "fmm_default_options", "fmm_setup", "fmm_apply", "gmres_solve", "fmm_destroy",
            "fmm_last_error", "fmm_direct", "fmm_plan_info", "fmm_export_tree", "fmm_export_stage",
-           "fmm_set_timing", "fmm_set_graph", "fmm_dielectric_rhs", "fmm_body_forces", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "fmm_split_bf16", "fmm_dielectric_rhs_noalloc", "fmm_autotune",
+           "fmm_set_timing", "fmm_set_graph", "fmm_dielectric_rhs", "fmm_body_forces", "fmm_stage_times", "fmm_pinv", "fmm_unit_surface", "fmm_split_bf16", "fmm_dielectric_rhs_noalloc", "fmm_autotune", "fmm_issue_probe",
            "library_path"]
 
 
@@ -297,6 +297,18 @@ def fmm_split_bf16(which, r_pad, values, stream=None):
     _check(L.load().fmm_split_bf16(int(which), int(r_pad), n // per, _ptr(values, torch.float32, "values"),
                                     parts.data_ptr(), _stream(stream)))
     return parts.view(3, n)
+
+
+def fmm_issue_probe(kind, out, iters, stream=None):
+    """Queue the library's issue-rate probe of the given kind on the stream
+    over out.numel() lanes (out: device float32, a multiple of 256 values).
+    Returns the wave64 VALU instructions of its chains per lane."""
+    import torch
+
+    instr = ctypes.c_int64(0)
+    _check(L.load().fmm_issue_probe(int(kind), int(out.numel()), int(iters), _ptr(out, torch.float32, "out"),
+                                    ctypes.byref(instr), _stream(stream)))
+    return instr.value
 
 
 def fmm_dielectric_rhs_noalloc(plan, sigma_f, areas, curvature, eps_i, eps_m, b, e0=None, stream=None):

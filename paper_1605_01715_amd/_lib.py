@@ -91,6 +91,7 @@ SIGNATURES = {
                              ctypes.POINTER(FmmOptions), ctypes.POINTER(FmmTuneSpace), ctypes.c_char_p,
                              ctypes.POINTER(FmmTuneResult), c_void_p]),
     "fmm_split_bf16": (c_int, [c_int, c_int, c_int64, c_void_p, c_void_p, c_void_p]),
+    "fmm_issue_probe": (c_int, [c_int, c_int64, c_int, c_void_p, ctypes.POINTER(c_int64), c_void_p]),
     "fmm_unit_surface": (c_int, [c_int, c_void_p, ctypes.POINTER(c_int)]),
 }
 

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmm_mi355x.so")
 SOURCES = ["primitives.hip", "tree.hip", "gemm.hip", "m2l.hip", "operators.hip", "nbody.hip", "chebyshev.hip", "plan.hip",
-           "gmres.hip", "dielectric.hip", "tune.hip", "api.hip"]
+           "gmres.hip", "dielectric.hip", "tune.hip", "probe.hip", "api.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-fopenmp",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-I", os.path.join(ROOT, "include"), "-I", CSRC]

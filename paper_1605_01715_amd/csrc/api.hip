@@ -5,6 +5,7 @@
 #include <unordered_map>
 
 #include "plan.hpp"
+#include "probe.hpp"
 
 // A handle is a small shell around the plan. fmm_destroy frees the plan and
 // keeps the shell as a tombstone for the rest of the process, so a handle
@@ -683,6 +684,19 @@ int fmm_stage_times(fmm_plan plan, double *ms) {
         FMM_REQUIRE(ms != nullptr, "fmm_stage_times: out is NULL");
         plan_report_times(P);
         for (int k = 0; k < ST_COUNT; ++k) ms[k] = P.have_times ? P.stage_ms[k] : -1.0;
+    });
+}
+
+int fmm_issue_probe(int kind, int64_t nthreads, int iters, float *out, int64_t *instr_per_lane, void *hip_stream) {
+    return guarded([&] {
+        using namespace fmm;
+        FMM_REQUIRE(kind >= 0 && kind <= 3, "fmm_issue_probe: kind must be 0..3");
+        FMM_REQUIRE(nthreads > 0 && nthreads % 256 == 0 && nthreads <= (int64_t(1) << 24),
+                    "fmm_issue_probe: nthreads must be a positive multiple of 256, at most 2^24");
+        FMM_REQUIRE(iters >= 1 && iters <= (1 << 20), "fmm_issue_probe: iters must be in 1..2^20");
+        FMM_REQUIRE(out != nullptr, "fmm_issue_probe: out is NULL");
+        issue_probe(kind, nthreads, iters, out, as_stream(hip_stream));
+        if (instr_per_lane) *instr_per_lane = (int64_t)iters * issue_probe_instr(kind);
     });
 }
 
