@@ -2,12 +2,12 @@
 sizes, through the C ABI, against the float64 oracle.
 
 * The headline path (the paper's Chebyshev form, Sec. III.A.1 Eq. p2m, with 8
-  nodes per axis, leaf 192, M2L basis threshold 1e-8, bf16x3 M2L): at 20,000
-  points against the oracle's Chebyshev FMM compressed to the GPU's rank
-  (every target), and on the 4M-point clustered cloud in the launch
-  configuration the benchmark times (with the other arithmetics and the
-  surface form beside it) against the direct sum on the benchmark's second
-  set of 10,000 targets.
+  nodes per axis, leaf 192, bf16x3 M2L, M2L basis threshold 1e-7 or 1e-8:
+  the benchmark takes the faster of the two): at 20,000 points against the
+  oracle's Chebyshev FMM compressed to the GPU's rank (every target), and on
+  the 4M-point clustered cloud in the launch configuration the benchmark
+  times (with the other arithmetics and the surface form beside it) against
+  the direct sum on the benchmark's second set of 10,000 targets.
 * Eight spheres, 196,000 quadrature points, double layer: one apply against
   the direct sum, then the interior Dirichlet problem (Eq. fk_integral with
   Omega = 2 pi) by matrix-free GMRES (Sec. III) to 1e-6, with the true
@@ -43,15 +43,16 @@ pytestmark = pytest.mark.gpu
 CHEB = 1
 
 
-def test_headline_path_against_the_oracle_chebyshev_fmm():
-    """The benchmark's selected form (Chebyshev, 8 nodes per axis, threshold
-    1e-8, leaf 192, bf16x3 M2L) at 20,000 points against the oracle's
-    Chebyshev FMM compressed to the GPU's rank, every target."""
+@pytest.mark.parametrize("eps", [1e-7, 1e-8])
+def test_headline_path_against_the_oracle_chebyshev_fmm(eps):
+    """The benchmark's two finalists (Chebyshev, 8 nodes per axis, threshold
+    1e-7 or 1e-8, leaf 192, bf16x3 M2L) at 20,000 points against the
+    oracle's Chebyshev FMM compressed to the GPU's rank, every target."""
     d = W.clustered(20000, seed=31)
     x, nrm, q, mu = d["xyz"], d["normals"], d["q"], d["mu"]
-    say("test_headline_path_against_the_oracle_chebyshev_fmm: clustered n=20000, Chebyshev n=8, leaf 192, "
-        "eps 1e-8, bf16x3, 3 M2L pieces")
-    r = fmm_run(x, q=q, mu=mu, nrm=nrm, order=8, leaf=192, root=d["root"], pinv_eps=1e-8, basis=CHEB, precision=2,
+    say(f"test_headline_path_against_the_oracle_chebyshev_fmm: clustered n=20000, Chebyshev n=8, leaf 192, "
+        f"eps {eps:g}, bf16x3, 3 M2L pieces")
+    r = fmm_run(x, q=q, mu=mu, nrm=nrm, order=8, leaf=192, root=d["root"], pinv_eps=eps, basis=CHEB, precision=2,
                 m2l_pieces=3)
     info = r["info"]
     assert info["m2l_pieces"] == 3 and info["basis"] == CHEB
@@ -82,17 +83,18 @@ def _full_size_reference():
     return _FULL["d"], _FULL["sample"], _FULL["ref"]
 
 
-@pytest.mark.parametrize("basis,precision,eps,bound", [(CHEB, 2, 1e-8, 1e-6), (CHEB, 1, 1e-8, 1e-6),
-                                                       (CHEB, 0, 1e-8, 1e-6), (0, 2, 1e-7, 1e-6),
-                                                       (CHEB, 1, 1e-7, 1.5e-6)])
+@pytest.mark.parametrize("basis,precision,eps,bound", [(CHEB, 2, 1e-7, 1e-6), (CHEB, 2, 1e-8, 1e-6),
+                                                       (CHEB, 1, 1e-8, 1e-6), (CHEB, 0, 1e-8, 1e-6),
+                                                       (0, 2, 1e-7, 1e-6), (CHEB, 1, 1e-7, 1.5e-6)])
 def test_headline_configuration_at_full_size(basis, precision, eps, bound):
     """The 4M-point clustered cloud as the benchmark runs it (order 8, leaf
-    192, pieces chosen at setup) on the benchmark's seed-7 error set: the
-    selected form (Chebyshev, threshold 1e-8, bf16x3), the same with bf16x6
-    and float32, the surface form, all below 1e-6. The Chebyshev form at
-    threshold 1e-7 sits just above it on this set (1.09e-6; its error is
-    dominated by the few targets near blob centres whose potential is up to
-    80 times the rms), which is why the benchmark does not select it."""
+    192, pieces chosen at setup) on the benchmark's seed-7 error set: its two
+    finalists (Chebyshev, bf16x3, thresholds 1e-7 and 1e-8), the Chebyshev
+    form at 1e-8 with bf16x6 and float32, the surface form, all below 1e-6.
+    The Chebyshev form at 1e-7 is closest to the bound on this set (9.7e-7
+    with bf16x3 in the benchmark; its error is dominated by the few targets
+    near blob centres whose potential is up to 80 times the rms); with bf16x6
+    it is held to 1.5e-6."""
     d, sample, ref = _full_size_reference()
     x, nrm, q, mu = d["xyz"], d["normals"], d["q"], d["mu"]
     say(f"test_headline_configuration_at_full_size: clustered n=4M, basis {basis}, order 8, leaf 192, "
