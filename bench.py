@@ -215,7 +215,7 @@ def calibrate_issue(F, torch, dev, waves_per_simd=8, iters=2048):
     One such instruction per 4 cycles is the unpacked float32 rate."""
     simds, ghz = 1024, 2.4
     out = torch.empty(simds * waves_per_simd * 64, device=dev)
-    names = ("fma", "rsq", "fma12_rsq1", "int_add_xor")
+    names = ("fma", "rsq", "fma12_rsq1", "int_add_xor", "mfma_bf16")
     res = {}
     for kind, name in enumerate(names):
         F.fmm_issue_probe(kind, out, iters)  # warm-up
@@ -228,7 +228,13 @@ def calibrate_issue(F, torch, dev, waves_per_simd=8, iters=2048):
             e1.synchronize()
             times.append(e0.elapsed_time(e1))
         ms = sorted(times)[len(times) // 2]
-        wave_instr = instr * out.numel() / 64
+        waves = out.numel() / 64
+        if name == "mfma_bf16":  # instr: MFMA per wave, 32x32x16 products of 32768 FLOP
+            tflops = instr * waves * 32768 / (ms * 1e-3) / 1e12
+            res[name] = {"median_ms": round(ms, 4), "mfma_instr": int(instr * waves), "tflops": round(tflops, 1),
+                         "frac_of_peak": round(tflops / PEAK_TFLOPS["bf16"], 4)}
+            continue
+        wave_instr = instr * waves
         res[name] = {"median_ms": round(ms, 4), "wave64_instr": int(wave_instr),
                      "per_simd_per_4_cycles": round(wave_instr / simds / (ms * 1e-3 * ghz * 1e9) * 4, 4)}
     print(json.dumps({"issue_probe": res, "waves_per_simd": waves_per_simd, "iters": iters, "simds": simds,
@@ -436,7 +442,7 @@ def main():
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     ap.add_argument("--calibrate-issue", action="store_true",
                     help="only run the library's issue-rate probes (float32 FMA, reciprocal square root, the pair "
-                         "loop's 12:1 mix, integer) and report their VALU issue rates")
+                         "loop's 12:1 mix, integer; bfloat16 MFMA from registers) and report their rates")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the FMM runs on exactly one GPU; --gpus {args.gpus} is not supported "

@@ -457,13 +457,17 @@ int fmm_stage_times(fmm_plan plan, double *ms /* [7] */);
  *   kind = 1  float32 reciprocal square roots (v_rsq_f32), 16 chains;
  *   kind = 2  8 chains, each step 12 fused multiply-adds and one reciprocal
  *             square root (the ratio of the leaf evaluation's pair loop);
- *   kind = 3  32-bit integer add then exclusive or, 8 chains.
+ *   kind = 3  32-bit integer add then exclusive or, 8 chains;
+ *   kind = 4  bfloat16 matrix products (v_mfma_f32_32x32x16_bf16, 32768
+ *             FLOP each) on operands held in registers, 4 accumulators; every
+ *             lane's output is 512 iters.
  *   nthreads  lanes, a positive multiple of 256, at most 2^24 (workgroups
  *             of 256)
  *   iters     chain steps per lane, 1..2^20
  *   out       device float [nthreads], one value per lane (keeps the chains)
- *   instr_per_lane  if not NULL, receives the wave64 VALU instructions of
- *             the chains per lane: 16 iters (kinds 0, 1, 3), 104 iters (2)
+ *   instr_per_lane  if not NULL, receives the instructions of the chains:
+ *             wave64 VALU instructions per lane, 16 iters (kinds 0, 1, 3) or
+ *             104 iters (2); MFMA instructions per wave, 4 iters (4)
  * FMM_ERR_ARG for other arguments. */
 int fmm_issue_probe(int kind, int64_t nthreads, int iters, float *out, int64_t *instr_per_lane, void *hip_stream);
 

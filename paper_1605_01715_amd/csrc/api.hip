@@ -690,7 +690,7 @@ int fmm_stage_times(fmm_plan plan, double *ms) {
 int fmm_issue_probe(int kind, int64_t nthreads, int iters, float *out, int64_t *instr_per_lane, void *hip_stream) {
     return guarded([&] {
         using namespace fmm;
-        FMM_REQUIRE(kind >= 0 && kind <= 3, "fmm_issue_probe: kind must be 0..3");
+        FMM_REQUIRE(kind >= 0 && kind <= 4, "fmm_issue_probe: kind must be 0..4");
         FMM_REQUIRE(nthreads > 0 && nthreads % 256 == 0 && nthreads <= (int64_t(1) << 24),
                     "fmm_issue_probe: nthreads must be a positive multiple of 256, at most 2^24");
         FMM_REQUIRE(iters >= 1 && iters <= (1 << 20), "fmm_issue_probe: iters must be in 1..2^20");

@@ -1,7 +1,8 @@
 // Issue-rate probes: a measurement utility, not a step of the method.
 //
 // Every lane runs independent float32 (or 32-bit integer) chains, so the
-// only limit is how fast a SIMD issues the instructions. The rates they
+// only limit is how fast a SIMD issues the instructions; one more kind runs
+// bfloat16 matrix products on operands held in registers. The rates they
 // reach are the ceilings against which the leaf evaluation (a loop of
 // float32 VALU instructions with one reciprocal square root per pair) is
 // judged: packed float32 is not used anywhere in the library, so the
@@ -73,9 +74,37 @@ __global__ __launch_bounds__(256) void k_probe_int(float *out, uint32_t a, uint3
     out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = (float)s;
 }
 
+typedef __bf16 pbf16x8 __attribute__((ext_vector_type(8)));
+typedef float pf32x16 __attribute__((ext_vector_type(16)));
+
+// 4 independent accumulators of v_mfma_f32_32x32x16_bf16, operands held in
+// registers: the matrix-core rate with no data movement at all
+__global__ __launch_bounds__(256) void k_probe_mfma(float *out, float a, float b, int iters) {
+    pbf16x8 va, vb;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        va[k] = (__bf16)a;
+        vb[k] = (__bf16)b;
+    }
+    pf32x16 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][v] = 0.f;
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va, vb, acc[i], 0, 0, 0);
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) s += acc[i][v];
+    out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 }  // namespace
 
-int64_t issue_probe_instr(int kind) { return kind == 2 ? 104 : 16; }
+int64_t issue_probe_instr(int kind) { return kind == 2 ? 104 : kind == 4 ? 4 : 16; }
 
 void issue_probe(int kind, int64_t nthreads, int iters, float *out, hipStream_t s) {
     const dim3 grid((unsigned)(nthreads / 256)), block(256);
@@ -83,7 +112,8 @@ void issue_probe(int kind, int64_t nthreads, int iters, float *out, hipStream_t 
     case 0: hipLaunchKernelGGL(k_probe_fma, grid, block, 0, s, out, 0.999f, 1e-3f, iters); break;
     case 1: hipLaunchKernelGGL(k_probe_rsq, grid, block, 0, s, out, 0.999f, 1e-3f, iters); break;
     case 2: hipLaunchKernelGGL(k_probe_mix, grid, block, 0, s, out, 0.999f, 1e-3f, iters); break;
-    default: hipLaunchKernelGGL(k_probe_int, grid, block, 0, s, out, 0x9e3779b9u, 0x85ebca6bu, iters); break;
+    case 3: hipLaunchKernelGGL(k_probe_int, grid, block, 0, s, out, 0x9e3779b9u, 0x85ebca6bu, iters); break;
+    default: hipLaunchKernelGGL(k_probe_mfma, grid, block, 0, s, out, 1.0f, 0.5f, iters); break;
     }
     FMM_HIP(hipGetLastError());
 }

@@ -1,9 +1,9 @@
 """The issue-rate probes of the library (a measurement utility): every lane
 runs the chains its kind names, so each output equals the same chains run on
 the host (float32 arithmetic to a relative 1e-5, the reciprocal square root
-being the hardware approximation; the integer chains bit for bit), the
-instruction count per lane is the documented one, and bad arguments are
-refused before any launch."""
+being the hardware approximation; the integer chains and the exact bfloat16
+matrix products bit for bit), the instruction count is the documented one,
+and bad arguments are refused before any launch."""
 
 import numpy as np
 import pytest
@@ -17,6 +17,8 @@ IA, IB = np.uint32(0x9E3779B9), np.uint32(0x85EBCA6B)
 
 
 def _host(kind, nthreads, iters):
+    if kind == 4:  # 4 accumulators x 16 elements per lane, each gaining 16 x 1.0 x 0.5 per step
+        return np.full(nthreads, 512.0 * iters, np.float32)
     t = (np.arange(nthreads) % 256).astype(np.float32)
     if kind == 3:
         acc = [(np.arange(nthreads) % 256).astype(np.uint64) * 2654435761 + i for i in range(8)]
@@ -42,7 +44,7 @@ def _host(kind, nthreads, iters):
     return s
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4])
 def test_issue_probe_runs_its_chains(kind):
     import torch
 
@@ -53,10 +55,10 @@ def test_issue_probe_runs_its_chains(kind):
     out = torch.full((nthreads,), float("nan"), device="cuda:0")
     instr = F.fmm_issue_probe(kind, out, iters)
     torch.cuda.synchronize()
-    assert instr == iters * (104 if kind == 2 else 16)
+    assert instr == iters * {2: 104, 4: 4}.get(kind, 16)
     got = out.cpu().numpy()
     want = _host(kind, nthreads, iters)
-    if kind == 3:
+    if kind in (3, 4):
         assert np.array_equal(got, want)
     else:
         np.testing.assert_allclose(got, want, rtol=1e-5)
@@ -70,7 +72,7 @@ def test_issue_probe_refuses_bad_arguments():
     lib = F._lib.load()
     out = torch.zeros(256, device="cuda:0")
     p = out.data_ptr()
-    assert lib.fmm_issue_probe(4, 256, 1, p, None, None) == F.FMM_ERR_ARG
+    assert lib.fmm_issue_probe(5, 256, 1, p, None, None) == F.FMM_ERR_ARG
     assert lib.fmm_issue_probe(-1, 256, 1, p, None, None) == F.FMM_ERR_ARG
     assert lib.fmm_issue_probe(0, 100, 1, p, None, None) == F.FMM_ERR_ARG
     assert lib.fmm_issue_probe(0, 0, 1, p, None, None) == F.FMM_ERR_ARG
