@@ -209,7 +209,7 @@ constexpr int kF32BStr = kF32Slice + 4;   // floats per column in LDS
 template <int MAXRB>
 __global__ __launch_bounds__(512) void k_gemm_f32(int m_pad, int k_pad, const int32_t *tile_cols, const float *Mf,
                                                   const float *in, float *out, const double *col_scale,
-                                                  int accumulate) {
+                                                  int accumulate, const int8_t *add_col) {
     __shared__ __align__(16) float Bs[kGemmCols * kF32BStr];
     __shared__ int32_t cols[kGemmCols];
     const int t = threadIdx.x, lane = t & 63, c = lane & 31, h = lane >> 5;
@@ -277,6 +277,7 @@ __global__ __launch_bounds__(512) void k_gemm_f32(int m_pad, int k_pad, const in
     const int o = cols[c];
     if (o < 0) return;
     const float sc = col_scale ? (float)col_scale[o] : 1.f;
+    const bool add = accumulate || (add_col && add_col[o]);
 #pragma unroll
     for (int i = 0; i < MAXRB; ++i) {
         if (!live[i]) continue;
@@ -287,7 +288,7 @@ __global__ __launch_bounds__(512) void k_gemm_f32(int m_pad, int k_pad, const in
             float4 r = make_float4(acc[i][4 * v4] * sc, acc[i][4 * v4 + 1] * sc, acc[i][4 * v4 + 2] * sc,
                                    acc[i][4 * v4 + 3] * sc);
             float4 *dst = (float4 *)(op + 8 * v4);
-            if (accumulate) {
+            if (add) {
                 const float4 old = *dst;
                 r.x += old.x;
                 r.y += old.y;
@@ -326,14 +327,14 @@ void box_gemm_f64(const GemmLaunch &a, hipStream_t s) {
 }
 
 void dense_gemm_f32(int m_pad, int k_pad, int ntile, const int32_t *tile_cols, const float *M, const float *in,
-                    float *out, const double *col_scale, int accumulate, hipStream_t s) {
+                    float *out, const double *col_scale, int accumulate, hipStream_t s, const int8_t *add_col) {
     if (ntile <= 0) return;
     FMM_REQUIRE(m_pad > 0 && k_pad > 0 && m_pad % 32 == 0 && k_pad % 32 == 0 && m_pad <= 512,
                 "dense_gemm_f32: unsupported size");
     const int nrb = m_pad / 32, nw = std::min(nrb, 8);  // waves per workgroup; each owns ceil(nrb / nw) row blocks
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3((unsigned)ntile), dim3(64 * nw), 0, s, m_pad, k_pad, tile_cols, M, in, out,
-                           col_scale, accumulate);
+                           col_scale, accumulate, add_col);
     };
     if (nrb <= 8)
         go(k_gemm_f32<1>);

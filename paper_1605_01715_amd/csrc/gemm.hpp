@@ -36,9 +36,11 @@ void box_gemm_f64(const GemmLaunch &a, hipStream_t s);
 // c < 32 with o = tile_cols[t][c] >= 0,
 //     out[o] (+)= col_scale[o] * M * in[o]
 // (in rows of k_pad floats, out rows of m_pad floats; col_scale may be NULL,
-// accumulate adds to out). m_pad and k_pad are multiples of 32, m_pad <= 512.
+// accumulate adds to out, and so does a nonzero add_col[o] for column o).
+// m_pad and k_pad are multiples of 32, m_pad <= 512.
 void dense_gemm_f32(int m_pad, int k_pad, int ntile, const int32_t *tile_cols, const float *M, const float *in,
-                    float *out, const double *col_scale, int accumulate, hipStream_t s);
+                    float *out, const double *col_scale, int accumulate, hipStream_t s,
+                    const int8_t *add_col = nullptr);
 // float64 row-major M [rows][cols] -> float32 fragment order for dense_gemm_f32, zero-padded to m_pad x k_pad.
 void to_frag_f32(const double *M, int rows, int cols, int m_pad, int k_pad, float *out, hipStream_t s);
 

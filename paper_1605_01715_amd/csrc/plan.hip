@@ -693,6 +693,14 @@ void plan_build_worklists(Plan &P, hipStream_t s) {
             roff.push_back((int32_t)(rng.size() / 2));
         }
         P.n_p2l = (int)items.size();
+        if (P.cheb) {
+            // the Chebyshev expansion out of the M2L basis adds to the node
+            // values P2L wrote and overwrites every other box's
+            std::vector<int8_t> add((size_t)nb * nrhs, 0);
+            for (int32_t b : items)
+                for (int r = 0; r < nrhs; ++r) add[(size_t)b * nrhs + r] = 1;
+            P.expand_add = upload(add, s);
+        }
         P.p2l_items = upload(items, s);
         P.p2l_roff = upload(roff, s);
         P.p2l_rng = upload(rng, s);
@@ -1139,10 +1147,10 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         // tree, node values L (phi_d) down; M2L in the shared compressed basis.
         // The leaf evaluation needs W only (M2P), so it runs on the side stream
         // from the end of the upward pass, beside P2L, M2L and L2L, and writes
-        // the outputs; L2P adds to them after the join.
-        hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)P.phi_d.n, kBlock)), dim3(kBlock), 0, s, P.phi_d.p,
-                           (int64_t)P.phi_d.n);
-        FMM_HIP(hipGetLastError());
+        // the outputs; L2P adds to them after the join. The node values need
+        // no clearing: P2L writes its boxes', the expansion overwrites every
+        // other box the downward pass reads (all boxes with targets from
+        // level 2) and adds to P2L's, and the rest stay zero from the setup.
         // side stream, first: P2L at the nodes, beside P2M and M2M
         FMM_HIP(hipEventRecord(P.fork0, s));
         FMM_HIP(hipStreamWaitEvent(P.side, P.fork0, 0));
@@ -1179,7 +1187,7 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         // adding to the P2L values
         FMM_HIP(hipStreamWaitEvent(s, P.p2l_done, 0));
         dense_gemm_f32(np, rp, P.cheb_expand.ntile, P.cheb_expand.cols.p, op.cd_f32.p, P.dt.p, P.phi_d.p,
-                       P.col_iscale.p, 1, s);
+                       P.col_iscale.p, 0, s, P.expand_add.p);
         for (auto &j : P.cheb_l2l)
             cheb_tensor(nrhs, op.p, true, op.cheb_s1.p, j.n, j.dst.p, j.src.p, j.oct.p, P.phi_d.p, P.phi_d.p, np, s);
         if (ts) FMM_HIP(hipEventRecord(ts->l2l_end, s));

@@ -47,6 +47,7 @@ struct Plan {
     DBuf<float> qm;                         // [nrhs][n_src][2]: q and mu side by side (both layers)
     DBuf<double> col_scale;                 // half-width per vector index
     DBuf<double> col_iscale;                // 1 / half-width per vector index (Chebyshev M2L expansion)
+    DBuf<int8_t> expand_add;                // per vector index: 1 where P2L writes the node values (Chebyshev expansion adds there, writes elsewhere)
     DBuf<float> trg_nrm_user;               // [n_trg][3] target normals, caller's order
 
     DBuf<int32_t> p2m_items, p2m_roff, p2m_rng;
