@@ -1060,10 +1060,16 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
                            t.n_src, nrhs, q, mu, t.snx.p, t.sny.p, t.snz.p, P.q_sorted.p, P.mx.p, P.my.p, P.mz.p);
     }
     FMM_HIP(hipGetLastError());
-    if (P.dt.n) {
+    // the M2L output accumulates (translation, reduction, gather and, in the
+    // surface form, the P2L projection): cleared once per apply, in the
+    // Chebyshev form only after the fork, where it waits behind the
+    // evaluation's workgroups instead of ahead of P2M
+    auto clear_dt = [&]() {
+        if (!P.dt.n) return;
         hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)P.dt.n, kBlock)), dim3(kBlock), 0, s, P.dt.p, (int64_t)P.dt.n);
         FMM_HIP(hipGetLastError());
-    }
+    };
+    if (!P.cheb) clear_dt();
     const int np = P.n_pad, rp = P.r_pad;
 
     PointSrc src;
@@ -1176,9 +1182,11 @@ void plan_apply(Plan &P, const float *q, const float *mu, float *pot, float *fie
         if (ts) FMM_HIP(hipEventRecord(ts->side[3], P.side));
         FMM_HIP(hipEventRecord(P.join, P.side));
         mark(ST_P2L);  // (P2L runs on the side stream; timed there)
-        // the split of the M2L input queues behind the evaluation's
-        // workgroups; it stays out of the M2L stage, which times the
-        // translation kernel, the reduction and the gather
+        // the clearing of the M2L output and the split of its input queue
+        // behind the evaluation's workgroups; they stay out of the M2L
+        // stage, which times the translation kernel, the reduction and the
+        // gather
+        clear_dt();
         split_m2l_input();
         mark(ST_M2L);
         run_m2l();
